@@ -1,0 +1,214 @@
+"""Benchmark: the estimator's hot path on the R-MAT scale-20 workload.
+
+One step = one pass of the whole path over the workload: for both
+f = exp(beta A), beta = 1/d_max, and f = (I - gamma A)^-1, gamma =
+0.85/lambda_max (50 power iterations), the full diagonal diag(f(A)) and the
+full action f(A) 1, each with K = 40 and N = 256 walks per start row, FP64.
+Inputs are resident in device memory before the timed region starts.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "walk steps/s + HBM GB/s; queries/s & p99 latency vs plain at equal error"
+
+
+def log(msg):
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=20, help="R-MAT scale")
+    ap.add_argument("--walks", type=int, default=256)
+    ap.add_argument("--K", type=int, default=40)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=100,
+                    help="output rows per query in the oracle's timed sample")
+    ap.add_argument("--only", choices=["all", "action", "diag"], default="all")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(kind, st, K):
+    """Bytes each kernel must move per launch set:
+    action walk: 16 B row record per recorded state + 4 B column per transition;
+    diag walk:   8 B row record per state + 4 B column per transition + 12 B visit record out;
+    gather:      12 B visit record in per state + 4 B column entry per probe."""
+    steps = st["walk_steps"]
+    transitions = steps - st["walks"]
+    if kind == "action_walk":
+        return 16 * steps + 4 * transitions + 12 * st["start_rows"]
+    if kind == "diag_walk":
+        return 8 * steps + 4 * transitions + 12 * steps
+    if kind == "diag_gather":
+        return 12 * steps + 4 * st["gather_probes"]
+    raise ValueError(kind)
+
+
+def cpu_baseline(csr, queries, rows, K, N):
+    """The oracle, single-threaded, on a bounded sample: each query evaluated at
+    `rows` random non-isolated output rows (its walks start from their
+    neighbourhoods).  Returns walk steps per second."""
+    import oracle
+    rng = np.random.default_rng(123)
+    cand = np.nonzero(csr.deg > 0)[0]
+    sample = np.sort(rng.choice(cand, size=min(rows, cand.size), replace=False)).astype(np.int32)
+    total_steps, total_s = 0, 0.0
+    for kind, fn, scale in queries:
+        t0 = time.perf_counter()
+        if kind == "action":
+            r = oracle.action(csr, fn, np.ones(csr.n), N=N, K=K, scale=scale, seed=1, rows=sample)
+        else:
+            r = oracle.diag(csr, fn, N=N, K=K, scale=scale, seed=1, rows=sample,
+                            assume_symmetric=True)
+        dt = time.perf_counter() - t0
+        total_steps += r["steps"]
+        total_s += dt
+        log(f"oracle {kind} fn={fn}: {r['steps']} steps in {dt:.2f} s")
+    return total_steps / total_s, total_steps, total_s, sample.size
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the estimator's "
+              "multi-GPU sharding is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen as G
+    from paper_2308_01037_amd import mcmf as M
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    K, N = args.K, args.walks
+    t0 = time.time()
+    csr = G.rmat(args.scale, edge_factor=16, seed=0)
+    log(f"R-MAT scale {args.scale}: n={csr.n} nnz={csr.nnz} d_max={csr.d_max} "
+        f"({time.time() - t0:.1f} s)")
+    lam = G.lambda_max(csr, 50)
+    beta, gamma = 1.0 / csr.d_max, 0.85 / lam
+    log(f"lambda_max={lam:.2f} beta={beta:.4e} gamma={gamma:.4e}")
+
+    g = M.Graph.from_csr(csr)
+    n = csr.n
+    stream = torch.cuda.current_stream().cuda_stream
+    v = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    d = torch.empty(n, dtype=torch.float64, device="cuda")
+    queries = []
+    for fname, kind, scale in (("exp", M.MCMF_FN_EXP, beta), ("resolvent", M.MCMF_FN_RESOLVENT, gamma)):
+        if args.only in ("all", "action"):
+            queries.append(("action", fname, kind, scale))
+        if args.only in ("all", "diag"):
+            queries.append(("diag", fname, kind, scale))
+
+    def step(req):
+        out = []
+        for qi, (what, fname, kind, scale) in enumerate(queries):
+            st = M.mcmf_stats()
+            opts = M.make_opts(seed=1, request_id=req, stream=stream)
+            f = M.make_fn(kind, scale)
+            tq = time.perf_counter()
+            if what == "action":
+                M.mcmf_action(g.handle, f, v, N, K, opts, y, st)
+            else:
+                M.mcmf_diag(g.handle, f, None, 0, N, K, opts, d, st)
+            out.append((what, fname, st.as_dict(), time.perf_counter() - tq))
+        return out
+
+    for w in range(args.warmup):
+        step(1000 + w)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    records = []
+    for s in range(args.steps):
+        records.extend(step(s))
+        log(f"step {s + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+
+    total_steps = sum(r[2]["walk_steps"] for r in records)
+    value = total_steps / elapsed
+    lat = np.array([r[3] for r in records]) * 1e3
+    # Per-kernel device time and algorithmic bytes over the timed region.
+    kernels = {}
+    for what, fname, st, _ in records:
+        parts = [("action_walk", st["ms_walk"])] if what == "action" else \
+            [("diag_walk", st["ms_walk"]), ("diag_gather", st["ms_gather"])]
+        for kind, ms in parts:
+            k = kernels.setdefault(kind, {"ms": 0.0, "bytes": 0})
+            k["ms"] += ms
+            k["bytes"] += algorithmic_bytes(kind, st, K)
+    for kind, k in kernels.items():
+        k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+        log(f"{kind}: {k['ms'] / args.steps:.1f} ms/step, {k['gbs']:.1f} GB/s algorithmic")
+    dominant = max(kernels, key=lambda kk: kernels[kk]["ms"])
+    dk = kernels[dominant]
+    alg_total = sum(k["bytes"] for k in kernels.values())
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oq = [(what, oracle.FN_EXP if fname == "exp" else oracle.FN_RESOLVENT,
+               beta if fname == "exp" else gamma) for what, fname, _, _ in queries]
+        rate, steps_c, secs, nrows = cpu_baseline(csr, oq, args.cpu_rows, K, N)
+        cpu = {"value": rate, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"each of the {len(oq)} queries evaluated at {nrows} random non-isolated "
+                         f"rows (walks from their neighbourhoods): {steps_c} walk steps in "
+                         f"{secs:.1f} s, single thread"}
+
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "walk-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"rmat{args.scale}-ef16 (a,b,c)=(.57,.19,.19) symmetrised: full diag and "
+                        f"f(A)1 for exp(A/d_max) and (I-0.85A/lambda_max)^-1, K={K}, N={N}/row",
+            "n": csr.n, "nnz": csr.nnz, "d_max": csr.d_max, "lambda_max": lam,
+            "K": K, "walks_per_row": N, "queries_per_step": len(queries),
+        },
+        "queries_per_s": len(records) / elapsed,
+        "query_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "hbm_gbs_algorithmic": alg_total / elapsed / 1e9,
+        "kernels": {k: {"ms_per_step": v_["ms"] / args.steps, "gbs_algorithmic": v_["gbs"]}
+                    for k, v_ in kernels.items()},
+        "roofline": {
+            "kernel": dominant,
+            "bound": "hbm",
+            "achieved": dk["gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": dk["gbs"] / HBM_PEAK_GBS,
+            "traffic": None,
+        },
+        "cpu_baseline": cpu,
+    }
+    g.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * mcmf.h -- C ABI of the MI355X library for the row/column-sampling Monte
+ * Carlo estimator of power-series matrix functions on sparse graphs.
+ *
+ * Method: Guidotti, Acebron and Monteiro, "A fast Monte Carlo algorithm for
+ * evaluating matrix functions with application in complex networks".
+ * For f(sA) = sum_{k=0}^{K} c_k (sA)^k over the adjacency matrix A of a
+ * graph (Section 2.2, Eq. power_series, with the inverse-temperature scale
+ * s of the parametric form f(gamma A)) the library computes
+ *
+ *   - subgraph centrality  diag(f(sA))        (Section 3.3, RandFunmDiag,
+ *                                               Eq. rand_funm_formula_diag)
+ *   - total communicability / action f(sA) v  (Section 3.4, Algorithm 3,
+ *                                               Eq. rand_funm_action_formula;
+ *                                               v = 1 gives Eq. total_comm)
+ *
+ * on one AMD Instinct MI355X (gfx950).  The exact part H = c0 I + c1 sA
+ * (Corollary 1) is computed exactly; the rest, U = sum_{k>=2} c_k (sA)^k, is
+ * estimated from random walks on the Markov chain of Definition 1 (ii),
+ * t_ij = |a_ij| / sum_k |a_ik|, with weights W^(k) = W^(k-1) a/t (Lemma 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every array argument may be host memory or device memory of the
+ * current HIP device; the library detects which.  The caller owns every
+ * array it passes; the library never keeps a caller pointer after a call
+ * returns (mcmf_graph_create copies the CSR into device memory).
+ *
+ * Walks.  K is the highest power kept.  Each start row k gets exactly
+ * n_walks walks; a walk records the states t = 0..K-2 (K-1 states, K-2
+ * transitions), so the expectation of the estimate is exactly the series
+ * truncated at K.  The transition out of step t of walk w from start row k
+ * draws Philox4x32-10 (Salmon et al., SC'11) at counter (k, w, t,
+ * request_id) with key (low, high 32-bit word of seed) and uses
+ * u = X1 * 2^32 + X0.  An unweighted row picks entry floor(u * deg / 2^64);
+ * a weighted row picks the first entry j with u53 * rowabs < cum_j
+ * (u53 = (u >> 11) * 2^-53, running sums of |a| taken left to right).
+ * Identical (graph, seed, request_id, n_walks, K) therefore give identical
+ * walks, whatever row subset, stream or batch they run in.
+ *
+ * Errors.  Every call returns a status.  On any status other than MCMF_OK
+ * the output arrays are left untouched (a failure inside the GPU work of an
+ * asynchronous call is reported by the next synchronising call instead).
+ * mcmf_last_error() gives a readable message for the calling thread.
+ *
+ * Streams.  opts->stream == NULL: the call uses the graph's own stream and
+ * returns when the outputs are complete.  A non-NULL hipStream_t with every
+ * array in device memory and stats == NULL makes the call asynchronous and
+ * ordered on that stream; otherwise it synchronises before returning.
+ *
+ * Thread safety.  Graphs are immutable after creation; concurrent calls on
+ * one graph are allowed.  Destroying a graph while a call on it is running
+ * is undefined.
+ */
+#ifndef MCMF_H
+#define MCMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCMF_VERSION_MAJOR 1
+#define MCMF_VERSION_MINOR 0
+
+typedef struct mcmf_graph mcmf_graph; /* opaque; owns its device copy of A */
+
+typedef enum {
+    MCMF_OK = 0,
+    MCMF_E_ARG = 1,           /* bad scalar or pointer argument */
+    MCMF_E_CSR = 2,           /* malformed CSR arrays */
+    MCMF_E_NOT_SYMMETRIC = 3, /* diag needs A = A^T (C_i = R_i) */
+    MCMF_E_NOMEM = 4,         /* device memory or the byte budget exhausted */
+    MCMF_E_DEVICE = 5,        /* HIP runtime error or no usable device */
+    MCMF_E_UNSUPPORTED = 6    /* valid request outside what this build handles */
+} mcmf_status;
+
+/* Function family: coefficients c_k of f(x) = sum_k c_k x^k (Eq. power_series). */
+typedef enum {
+    MCMF_FN_EXP = 0,       /* c_0 = 1, c_k = c_{k-1} / k (exponential) */
+    MCMF_FN_RESOLVENT = 1, /* c_k = 1: (I - sA)^-1 (Katz centrality, Section 4.5) */
+    MCMF_FN_COEFFS = 2     /* caller-supplied c_0 .. c_{n_coeffs-1} */
+} mcmf_fn_kind;
+
+typedef struct {
+    int32_t kind;          /* mcmf_fn_kind */
+    double scale;          /* s: the estimate is of f(sA); must be finite */
+    const double *coeffs;  /* MCMF_FN_COEFFS only: host array, n_coeffs >= K+1 */
+    int32_t n_coeffs;
+} mcmf_fn;
+
+/* Flags for mcmf_graph_create. */
+#define MCMF_SYMMETRIC 1u /* caller states A = A^T; required by mcmf_diag */
+#define MCMF_VALIDATE 2u  /* check the CSR arrays (and, with MCMF_SYMMETRIC, symmetry) */
+
+/* Precision of the walk weights (the accumulators and final reduction are FP64). */
+#define MCMF_PRECISION_FP64 0
+#define MCMF_PRECISION_FP32_WEIGHTS 1
+
+typedef struct {
+    uint64_t seed;          /* RNG key */
+    uint32_t request_id;    /* fourth Philox counter word; same id => same walks */
+    int32_t precision;      /* MCMF_PRECISION_* */
+    double weight_cutoff;   /* Wc > 0: a walk stops before step t once |W_t| <= Wc
+                               (Eq. weight_cutoff with W^(0) = 1); 0 = off */
+    void *stream;           /* hipStream_t or NULL */
+    uint64_t *path_digest;  /* optional out, n entries: per start row k the wrapping
+                               sum over its walks of FNV-1a over the 32-bit words of
+                               the recorded states; 0 for rows that start no walk */
+    double *q_out;          /* optional out (mcmf_action only), n entries: q_k of
+                               Algorithm 3 per start row, 0 elsewhere */
+    uint32_t reserved[8];   /* must be zero */
+} mcmf_opts;
+
+typedef struct {
+    uint64_t start_rows;    /* rows that started walks */
+    uint64_t walks;         /* start_rows * n_walks */
+    uint64_t walk_steps;    /* recorded walk states (K-1 per full walk) */
+    uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather */
+    double ms_setup;        /* marks, start set, temporaries */
+    double ms_spmv;         /* r = sA v and the final assembly (action) */
+    double ms_walk;         /* walk kernels */
+    double ms_gather;       /* Q_k build + column gather + scatter (diag) */
+    double ms_total;        /* whole call, device time */
+} mcmf_stats;
+
+/*
+ * mcmf_graph_create -- copy a CSR matrix into device memory and build the
+ * per-row metadata the walks need (Section 2.1, Eq. adj_matrix; the
+ * transition matrix T of Definition 1 (ii) is implied by the rows and never
+ * stored for unweighted graphs).
+ *
+ *   n        number of rows/columns, 0 <= n < 2^31
+ *   row_ptr  int64[n+1], row_ptr[0] = 0, non-decreasing; nnz = row_ptr[n] < 2^32
+ *   col_idx  int32[nnz], 0 <= col < n (order within a row is kept: it is the
+ *            order the sampler's cumulative sums run in)
+ *   values   double[nnz], finite; NULL means every stored entry is 1
+ *   flags    MCMF_SYMMETRIC | MCMF_VALIDATE
+ *   out      receives the handle; set only on MCMF_OK
+ *
+ * Errors: MCMF_E_ARG (null out, n out of range, null arrays with nnz > 0),
+ * MCMF_E_CSR (with MCMF_VALIDATE: row_ptr[0] != 0, decreasing row_ptr, a
+ * column out of range, a non-finite value; without it only row_ptr[0] and
+ * row_ptr[n] are checked), MCMF_E_NOT_SYMMETRIC (MCMF_VALIDATE |
+ * MCMF_SYMMETRIC and A != A^T, or unsorted rows, which that check needs),
+ * MCMF_E_UNSUPPORTED (nnz >= 2^32), MCMF_E_NOMEM, MCMF_E_DEVICE.
+ */
+mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                              const double *values, uint32_t flags, mcmf_graph **out);
+
+/* Release the graph's device memory.  NULL is ignored. */
+void mcmf_graph_destroy(mcmf_graph *g);
+
+/*
+ * mcmf_graph_info -- sizes of a graph: n, nnz, the largest row length d_max
+ * (used for the scale 1/d_max) and the number of rows with at least one
+ * entry.  Any output pointer may be NULL.
+ */
+mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64_t *d_max,
+                            int64_t *active_rows);
+
+/*
+ * mcmf_diag -- RandFunmDiag (Section 3.3): out[p] estimates f(sA)_{ii} for
+ * i = rows[p],
+ *
+ *   d_i = c0 + c1 s a_ii + s^2 sum_k a_ik <Q_k, C_i>      (Eq. rand_funm_formula_diag)
+ *
+ * with Q_k = (1/n_walks) sum_{walks from k} sum_t c_{t+2} W_t e_{l_t}
+ * (Eq. rand_funm_Q).  Walks start from every row k adjacent to a requested
+ * row; each Q_k is used for all requested rows adjacent to k.
+ *
+ *   g        graph created with MCMF_SYMMETRIC
+ *   f        function and scale
+ *   rows     int32[n_rows] requested rows, any order, duplicates allowed, or
+ *            NULL for every row (then n_rows is ignored and out has n entries)
+ *   n_walks  walks per start row, >= 1 when K >= 2
+ *   K        highest power kept, 0 <= K <= 4096
+ *   opts     may be NULL (seed 0, request 0, FP64, no cutoff, own stream)
+ *   out      double[n_rows] (or [n])
+ *   stats    optional
+ *
+ * Errors: MCMF_E_ARG (null g/f/out, K out of range, n_walks < 1 with K >= 2,
+ * n_rows < 0, a row outside [0, n), non-finite scale or coefficients,
+ * n_coeffs < K+1, non-zero reserved words), MCMF_E_NOT_SYMMETRIC,
+ * MCMF_E_NOMEM, MCMF_E_DEVICE.
+ */
+mcmf_status mcmf_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int64_t n_rows,
+                      int64_t n_walks, int32_t K, const mcmf_opts *opts, double *out,
+                      mcmf_stats *stats);
+
+/*
+ * mcmf_action -- RandFunmAction (Section 3.4, Algorithm 3): out = estimate of
+ * f(sA) v,
+ *
+ *   r = s A v,  q_k = (1/n_walks) sum_{walks from k} sum_t c_{t+2} W_t r_{l_t},
+ *   out = c0 v + c1 r + s A q                       (Eq. rand_funm_action_formula)
+ *
+ * Walks start from every row with at least one entry.  A need not be
+ * symmetric; a walk that reaches a row without entries stops.
+ *
+ *   v        double[n]
+ *   out      double[n]; may not alias v
+ *   other arguments as for mcmf_diag
+ *
+ * Errors: MCMF_E_ARG (null g/f/v/out, K out of range, n_walks < 1 with
+ * K >= 2, non-finite scale or coefficients, n_coeffs < K+1, non-zero reserved
+ * words), MCMF_E_NOMEM, MCMF_E_DEVICE.
+ */
+mcmf_status mcmf_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_t n_walks,
+                        int32_t K, const mcmf_opts *opts, double *out, mcmf_stats *stats);
+
+/* Static name of a status code. */
+const char *mcmf_status_string(mcmf_status s);
+
+/* Message describing the calling thread's last failure ("" if none). */
+const char *mcmf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCMF_H */

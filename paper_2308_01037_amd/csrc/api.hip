@@ -1,0 +1,473 @@
+// Entry points mcmf_action and mcmf_diag: argument checks, marshalling of
+// host/device buffers, the start set, chunking of the diagonal's visit
+// buffer, statistics, and the small kernels that assemble the diagonal.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "device.hpp"
+#include "ops.hpp"
+
+namespace mcmf {
+
+namespace {
+
+constexpr int kMaxK = 4096;
+
+// ---- small kernels ----
+
+// in_set[i] = 1 for every requested row; counts rows outside [0, n).
+__global__ void k_mark_rows(const int32_t *rows, int64_t n_rows, int64_t n, uint8_t *in_set,
+                            int *bad) {
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; p < n_rows;
+         p += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t i = rows[p];
+        if (i < 0 || i >= n)
+            atomicOr(bad, 1);
+        else
+            in_set[i] = 1;
+    }
+}
+
+// start[k] = 1 for every k adjacent to a requested row (one wavefront per row).
+__global__ __launch_bounds__(256) void k_mark_starts(const int32_t *rows, int64_t n_rows,
+                                                     const uint2 *node, const int32_t *col,
+                                                     uint8_t *start) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x / 64) + (threadIdx.x >> 6); p < n_rows;
+         p += waves) {
+        const uint2 ri = node[rows[p]];
+        for (uint32_t e = lane; e < ri.y; e += 64)
+            start[col[int64_t(ri.x) + e]] = 1;
+    }
+}
+
+// out[p] = c0 + c1 s a_ii + dacc[i], i = rows[p] (rows null: i = p).
+// a_ii is the sum of the stored (i, i) entries (one wavefront per output).
+__global__ __launch_bounds__(256) void k_diag_finish(const int32_t *rows, int64_t count,
+                                                     const uint2 *node, const int32_t *col,
+                                                     const double *val, int K, double c0, double c1,
+                                                     double scale, const double *dacc,
+                                                     double *out) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t p = blockIdx.x * int64_t(blockDim.x / 64) + (threadIdx.x >> 6); p < count;
+         p += waves) {
+        const int32_t i = rows ? rows[p] : static_cast<int32_t>(p);
+        double aii = 0.0;
+        if (K >= 1) {
+            const uint2 ri = node[i];
+            for (uint32_t e = lane; e < ri.y; e += 64) {
+                const int64_t idx = int64_t(ri.x) + e;
+                if (col[idx] == i)
+                    aii += val ? val[idx] : 1.0;
+            }
+            aii = dev::wave_sum(aii);
+        }
+        if (lane == 0) {
+            double d = c0;
+            if (K >= 1)
+                d = d + c1 * (scale * aii);
+            if (K >= 2)
+                d = d + dacc[i];
+            out[p] = d;
+        }
+    }
+}
+
+int64_t grid_for(int64_t n, int per_block) {
+    int64_t b = (n + per_block - 1) / per_block;
+    const int64_t cap = int64_t(1) << 20;
+    return b < 1 ? 1 : (b < cap ? b : cap);
+}
+
+// ---- argument handling ----
+
+Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K,
+                    const mcmf_opts *o) {
+    if (!g)
+        return fail(MCMF_E_ARG, "graph is NULL");
+    if (!f)
+        return fail(MCMF_E_ARG, "function is NULL");
+    if (K < 0 || K > kMaxK)
+        return fail(MCMF_E_ARG, "K = %d outside [0, %d]", K, kMaxK);
+    if (K >= 2 && (n_walks < 1 || n_walks > (int64_t(1) << 32)))
+        return fail(MCMF_E_ARG, "n_walks = %lld outside [1, 2^32]", static_cast<long long>(n_walks));
+    if (!std::isfinite(f->scale))
+        return fail(MCMF_E_ARG, "scale is not finite");
+    if (o) {
+        for (uint32_t r : o->reserved)
+            if (r != 0)
+                return fail(MCMF_E_ARG, "reserved option words must be zero");
+        if (o->precision != MCMF_PRECISION_FP64 && o->precision != MCMF_PRECISION_FP32_WEIGHTS)
+            return fail(MCMF_E_ARG, "unknown precision %d", o->precision);
+        if (o->precision == MCMF_PRECISION_FP32_WEIGHTS)
+            return fail(MCMF_E_UNSUPPORTED, "FP32-weight walks are not built into this library");
+        if (!(o->weight_cutoff >= 0.0) || !std::isfinite(o->weight_cutoff))
+            return fail(MCMF_E_ARG, "weight_cutoff must be finite and >= 0");
+    }
+    return {};
+}
+
+// Events destroyed on scope exit.
+struct EventList : std::vector<hipEvent_t> {
+    ~EventList() {
+        for (hipEvent_t e : *this)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+};
+
+struct Timer {
+    bool on = false;
+    hipEvent_t ev[5] = {};
+    hipStream_t s = nullptr;
+    Status start(bool enable, hipStream_t stream) {
+        on = enable;
+        s = stream;
+        if (!on)
+            return {};
+        for (auto &e : ev)
+            MCMF_HIP(hipEventCreate(&e));
+        MCMF_HIP(hipEventRecord(ev[0], s));
+        return {};
+    }
+    Status mark(int i) {
+        if (on)
+            MCMF_HIP(hipEventRecord(ev[i], s));
+        return {};
+    }
+    float ms(int a, int b) const {
+        float t = 0.f;
+        if (on && hipEventElapsedTime(&t, ev[a], ev[b]) != hipSuccess) {
+            (void)hipGetLastError();
+            t = 0.f;
+        }
+        return t;
+    }
+    ~Timer() {
+        if (on)
+            for (auto &e : ev)
+                if (e)
+                    (void)hipEventDestroy(e);
+    }
+};
+
+WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N) {
+    WalkParams p;
+    p.coef = coef;
+    p.K = K;
+    p.scale = scale;
+    p.n_walks = N;
+    const uint64_t seed = o ? o->seed : 0;
+    p.key0 = static_cast<uint32_t>(seed & 0xffffffffu);
+    p.key1 = static_cast<uint32_t>(seed >> 32);
+    p.request = o ? o->request_id : 0u;
+    p.cutoff = o ? o->weight_cutoff : 0.0;
+    p.precision = o ? o->precision : 0;
+    return p;
+}
+
+// Device view of a caller array: the array itself or a staged copy.
+template <class T>
+struct View {
+    T *ptr = nullptr;
+    DevBuf<T> staged;
+    bool host = false;
+    Status in(const T *p, size_t count, hipStream_t s) {
+        host = classify(p) == Mem::Host;
+        if (!host) {
+            ptr = const_cast<T *>(p);
+            return {};
+        }
+        MCMF_TRY(staged.alloc(count, s));
+        ptr = staged.ptr;
+        if (count)
+            MCMF_HIP(hipMemcpyAsync(ptr, p, sizeof(T) * count, hipMemcpyHostToDevice, s));
+        return {};
+    }
+    Status out(T *p, size_t count, hipStream_t s) {
+        host = classify(p) == Mem::Host;
+        if (!host) {
+            ptr = p;
+            return {};
+        }
+        MCMF_TRY(staged.alloc(count, s));
+        ptr = staged.ptr;
+        return {};
+    }
+    Status copy_back(T *p, size_t count, hipStream_t s) {
+        if (host && count)
+            MCMF_HIP(hipMemcpyAsync(p, ptr, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+        return {};
+    }
+};
+
+Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_t N, int32_t K,
+                  const mcmf_opts *o, double *out, mcmf_stats *stats) {
+    MCMF_TRY(check_common(g, f, N, K, o));
+    if (!v || !out)
+        return fail(MCMF_E_ARG, "v and out must not be NULL");
+    if (v == out)
+        return fail(MCMF_E_ARG, "out may not alias v");
+    std::vector<double> c(K + 1);
+    MCMF_TRY(make_coeffs(f, K, c.data()));
+    MCMF_HIP(hipSetDevice(g->device));
+    hipStream_t s = (o && o->stream) ? static_cast<hipStream_t>(o->stream) : g->stream;
+    const int64_t n = g->n;
+    uint64_t *digest = o ? o->path_digest : nullptr;
+    double *q_out = o ? o->q_out : nullptr;
+
+    Timer tm;
+    MCMF_TRY(tm.start(stats != nullptr, s));
+    View<double> vin, yout, qv;
+    View<uint64_t> dig;
+    MCMF_TRY(vin.in(v, n, s));
+    MCMF_TRY(yout.out(out, n, s));
+    DevBuf<ActionNode> rec;
+    DevBuf<double> q, coef;
+    DevBuf<unsigned long long> steps;
+    MCMF_TRY(rec.alloc(n > 0 ? n : 1, s));
+    MCMF_TRY(steps.alloc(1, s));
+    MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(steps.ptr), 0, 1, s));
+    double *qptr = nullptr;
+    if (K >= 2) {
+        if (q_out && classify(q_out) == Mem::Device) {
+            qptr = q_out;
+        } else {
+            MCMF_TRY(q.alloc(n > 0 ? n : 1, s));
+            qptr = q.ptr;
+        }
+        MCMF_TRY(fill_f64(qptr, 0.0, n, s));
+        MCMF_TRY(coef.alloc(K - 1, s));
+        MCMF_HIP(hipMemcpyAsync(coef.ptr, c.data() + 2, sizeof(double) * (K - 1),
+                                hipMemcpyHostToDevice, s));
+    }
+    if (digest) {
+        MCMF_TRY(dig.out(digest, n, s));
+        MCMF_TRY(fill_u64(dig.ptr, 0, n, s));
+    }
+    MCMF_TRY(tm.mark(1));
+    MCMF_TRY(spmv_records(g, vin.ptr, f->scale, rec.ptr, s));
+    MCMF_TRY(tm.mark(2));
+    if (K >= 2) {
+        const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        MCMF_TRY(action_walks(g, rec.ptr, g->active, g->n_active, p, qptr, dig.ptr, steps.ptr, s));
+    }
+    MCMF_TRY(tm.mark(3));
+    MCMF_TRY(spmv_assemble(g, vin.ptr, rec.ptr, K >= 2 ? qptr : nullptr, c[0], K >= 1 ? c[1] : 0.0,
+                           f->scale, yout.ptr, s));
+    MCMF_TRY(tm.mark(4));
+    MCMF_TRY(yout.copy_back(out, n, s));
+    if (digest)
+        MCMF_TRY(dig.copy_back(digest, n, s));
+    if (q_out) {
+        if (K < 2) {
+            if (classify(q_out) == Mem::Device)
+                MCMF_TRY(fill_f64(q_out, 0.0, n, s));
+            else
+                std::fill(q_out, q_out + n, 0.0); // nothing was estimated
+        } else if (qptr != q_out && n) {
+            MCMF_HIP(hipMemcpyAsync(q_out, qptr, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+        }
+    }
+    const bool sync = !(o && o->stream) || stats || vin.host || yout.host ||
+                      (digest && dig.host) || (q_out && classify(q_out) == Mem::Host);
+    unsigned long long nsteps = 0;
+    if (stats)
+        MCMF_HIP(hipMemcpyAsync(&nsteps, steps.ptr, sizeof nsteps, hipMemcpyDeviceToHost, s));
+    if (sync)
+        MCMF_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->start_rows = K >= 2 ? static_cast<uint64_t>(g->n_active) : 0;
+        stats->walks = stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
+        stats->walk_steps = nsteps;
+        stats->ms_setup = tm.ms(0, 1);
+        stats->ms_spmv = tm.ms(1, 2) + tm.ms(3, 4);
+        stats->ms_walk = tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 4);
+    }
+    return {};
+}
+
+Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int64_t n_rows,
+                int64_t N, int32_t K, const mcmf_opts *o, double *out, mcmf_stats *stats) {
+    MCMF_TRY(check_common(g, f, N, K, o));
+    if (!out)
+        return fail(MCMF_E_ARG, "out must not be NULL");
+    if (rows && n_rows < 0)
+        return fail(MCMF_E_ARG, "n_rows = %lld is negative", static_cast<long long>(n_rows));
+    if (!g->symmetric)
+        return fail(MCMF_E_NOT_SYMMETRIC, "mcmf_diag needs a graph created with MCMF_SYMMETRIC");
+    const bool all = rows == nullptr;
+    const int64_t count = all ? g->n : n_rows;
+    if (!all && classify(rows) == Mem::Host)
+        for (int64_t p = 0; p < n_rows; ++p)
+            if (rows[p] < 0 || rows[p] >= g->n)
+                return fail(MCMF_E_ARG, "rows[%lld] = %d outside [0, %lld)", static_cast<long long>(p),
+                            rows[p], static_cast<long long>(g->n));
+    std::vector<double> c(K + 1);
+    MCMF_TRY(make_coeffs(f, K, c.data()));
+    MCMF_HIP(hipSetDevice(g->device));
+    hipStream_t s = (o && o->stream) ? static_cast<hipStream_t>(o->stream) : g->stream;
+    const int64_t n = g->n;
+    uint64_t *digest = o ? o->path_digest : nullptr;
+
+    Timer tm;
+    MCMF_TRY(tm.start(stats != nullptr, s));
+    View<int32_t> rv;
+    View<double> dout;
+    View<uint64_t> dig;
+    if (!all)
+        MCMF_TRY(rv.in(rows, count, s));
+    MCMF_TRY(dout.out(out, count, s));
+    DevBuf<double> dacc, coef;
+    DevBuf<uint8_t> in_set, start_flags;
+    DevBuf<int32_t> start_list;
+    DevBuf<int> bad;
+    DevBuf<unsigned long long> counters; // steps, probes
+    MCMF_TRY(counters.alloc(2, s));
+    MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, 2, s));
+    if (digest) {
+        MCMF_TRY(dig.out(digest, n, s));
+        MCMF_TRY(fill_u64(dig.ptr, 0, n, s));
+    }
+    const int32_t *starts = g->active;
+    int64_t n_start = g->n_active;
+    if (!all) {
+        // Rows given in device memory are range-checked here, before any write to out.
+        MCMF_TRY(in_set.alloc(n > 0 ? n : 1, s));
+        MCMF_TRY(bad.alloc(1, s));
+        MCMF_TRY(fill_u8(in_set.ptr, 0, n, s));
+        MCMF_TRY(fill_i32(bad.ptr, 0, 1, s));
+        if (count > 0) {
+            hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(count, 256)), dim3(256), 0, s, rv.ptr, count,
+                               n, in_set.ptr, bad.ptr);
+            MCMF_HIP(hipGetLastError());
+        }
+        int hbad = 0;
+        MCMF_HIP(hipMemcpyAsync(&hbad, bad.ptr, sizeof hbad, hipMemcpyDeviceToHost, s));
+        MCMF_HIP(hipStreamSynchronize(s));
+        if (hbad)
+            return fail(MCMF_E_ARG, "a requested row lies outside [0, %lld)", static_cast<long long>(n));
+        n_start = 0;
+        if (K >= 2 && count > 0) {
+            MCMF_TRY(start_flags.alloc(n > 0 ? n : 1, s));
+            MCMF_TRY(start_list.alloc(n > 0 ? n : 1, s));
+            MCMF_TRY(fill_u8(start_flags.ptr, 0, n, s));
+            hipLaunchKernelGGL(k_mark_starts, dim3(grid_for(count, 4)), dim3(256), 0, s, rv.ptr, count,
+                               g->node, g->col, start_flags.ptr);
+            MCMF_HIP(hipGetLastError());
+            MCMF_TRY(compact(start_flags.ptr, n, 1, start_list.ptr, &n_start, s));
+        }
+        starts = start_list.ptr;
+    }
+    if (K >= 2) {
+        MCMF_TRY(dacc.alloc(n > 0 ? n : 1, s));
+        MCMF_TRY(fill_f64(dacc.ptr, 0.0, n, s));
+        MCMF_TRY(coef.alloc(K - 1, s));
+        MCMF_HIP(hipMemcpyAsync(coef.ptr, c.data() + 2, sizeof(double) * (K - 1),
+                                hipMemcpyHostToDevice, s));
+    }
+    MCMF_TRY(tm.mark(1));
+    float ms_walk = 0.f, ms_gather = 0.f;
+    EventList chunk_events;
+    if (K >= 2 && n_start > 0) {
+        const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        // Visit records of a chunk of start rows: 12 bytes per visit.
+        const int64_t per_row = N * (K - 1);
+        int64_t chunk_bytes = int64_t(2) << 30;
+        if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
+            chunk_bytes = std::max<int64_t>(1, strtoll(e, nullptr, 10));
+        int64_t rows_per_chunk = chunk_bytes / (per_row * 12);
+        rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(rows_per_chunk, n_start));
+        DevBuf<int32_t> vstate;
+        DevBuf<double> vx;
+        MCMF_TRY(vstate.alloc(rows_per_chunk * per_row, s));
+        MCMF_TRY(vx.alloc(rows_per_chunk * per_row, s));
+        // Per-chunk events are read only after the call's final synchronisation,
+        // so timing does not stall the stream between chunks.
+        const int64_t n_chunks = (n_start + rows_per_chunk - 1) / rows_per_chunk;
+        if (stats) {
+            chunk_events.assign(static_cast<size_t>(2 * n_chunks + 1), nullptr);
+            for (auto &e : chunk_events)
+                MCMF_HIP(hipEventCreate(&e));
+        }
+        for (int64_t ci = 0; ci < n_chunks; ++ci) {
+            const int64_t c0 = ci * rows_per_chunk;
+            const int64_t rows_here = std::min(rows_per_chunk, n_start - c0);
+            if (stats)
+                MCMF_HIP(hipEventRecord(chunk_events[2 * ci], s));
+            MCMF_TRY(diag_walks(g, starts + c0, rows_here, p, vstate.ptr, vx.ptr, dig.ptr,
+                                counters.ptr, s));
+            if (stats)
+                MCMF_HIP(hipEventRecord(chunk_events[2 * ci + 1], s));
+            MCMF_TRY(diag_gather(g, starts + c0, rows_here, p, vstate.ptr, vx.ptr,
+                                 all ? nullptr : in_set.ptr, dacc.ptr, counters.ptr + 1, s));
+        }
+        if (stats)
+            MCMF_HIP(hipEventRecord(chunk_events.back(), s));
+    }
+    MCMF_TRY(tm.mark(2));
+    if (count > 0) {
+        hipLaunchKernelGGL(k_diag_finish, dim3(grid_for(count, 4)), dim3(256), 0, s,
+                           all ? nullptr : rv.ptr, count, g->node, g->col, g->val, K, c[0],
+                           K >= 1 ? c[1] : 0.0, f->scale, dacc.ptr, dout.ptr);
+        MCMF_HIP(hipGetLastError());
+    }
+    MCMF_TRY(tm.mark(3));
+    MCMF_TRY(dout.copy_back(out, count, s));
+    if (digest)
+        MCMF_TRY(dig.copy_back(digest, n, s));
+    unsigned long long hc[2] = {0, 0};
+    if (stats)
+        MCMF_HIP(hipMemcpyAsync(hc, counters.ptr, sizeof hc, hipMemcpyDeviceToHost, s));
+    const bool sync = !(o && o->stream) || stats || dout.host || (digest && dig.host) || rv.host;
+    if (sync)
+        MCMF_HIP(hipStreamSynchronize(s));
+    if (stats) {
+        for (size_t e = 0; e + 1 < chunk_events.size(); ++e) {
+            float t = 0.f;
+            MCMF_HIP(hipEventElapsedTime(&t, chunk_events[e], chunk_events[e + 1]));
+            // even -> odd: walk kernel; odd -> next even: gather kernel
+            if (e % 2 == 0)
+                ms_walk += t;
+            else
+                ms_gather += t;
+        }
+        memset(stats, 0, sizeof *stats);
+        stats->start_rows = K >= 2 ? static_cast<uint64_t>(n_start) : 0;
+        stats->walks = stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
+        stats->walk_steps = hc[0];
+        stats->gather_probes = hc[1];
+        stats->ms_setup = tm.ms(0, 1);
+        stats->ms_walk = ms_walk;
+        stats->ms_gather = ms_gather + tm.ms(2, 3);
+        stats->ms_total = tm.ms(0, 3);
+    }
+    return {};
+}
+
+} // namespace
+
+} // namespace mcmf
+
+using namespace mcmf;
+
+extern "C" mcmf_status mcmf_action(const mcmf_graph *g, const mcmf_fn *f, const double *v,
+                                   int64_t n_walks, int32_t K, const mcmf_opts *opts, double *out,
+                                   mcmf_stats *stats) {
+    clear_error();
+    return run_action(g, f, v, n_walks, K, opts, out, stats).code;
+}
+
+extern "C" mcmf_status mcmf_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows,
+                                 int64_t n_rows, int64_t n_walks, int32_t K, const mcmf_opts *opts,
+                                 double *out, mcmf_stats *stats) {
+    clear_error();
+    return run_diag(g, f, rows, n_rows, n_walks, K, opts, out, stats).code;
+}

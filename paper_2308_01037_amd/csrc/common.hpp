@@ -1,0 +1,119 @@
+// Host-side plumbing shared by the library's translation units: error state,
+// status propagation, device-memory accounting and pointer classification.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "mcmf.h"
+
+namespace mcmf {
+
+// Thread-local message behind mcmf_last_error().
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+// A status plus the place it came from; MCMF_OK converts to false.
+struct Status {
+    mcmf_status code = MCMF_OK;
+    explicit operator bool() const { return code != MCMF_OK; }
+};
+
+Status fail(mcmf_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+Status hip_fail(hipError_t e, const char *what, const char *file, int line);
+
+#define MCMF_HIP(expr)                                                        \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return ::mcmf::hip_fail(e_, #expr, __FILE__, __LINE__);           \
+    } while (0)
+
+#define MCMF_TRY(expr)                                                        \
+    do {                                                                      \
+        ::mcmf::Status s_ = (expr);                                           \
+        if (s_)                                                               \
+            return s_;                                                        \
+    } while (0)
+
+// Where a caller pointer lives.
+enum class Mem { Host, Device };
+Mem classify(const void *p);
+
+// Device memory accounting against an optional byte budget (environment
+// variable MCMF_HBM_BUDGET_BYTES).  MCMF_TEST_FAIL_ALLOC=1 makes every
+// allocation fail, so the out-of-memory path can be exercised on purpose.
+Status dev_alloc(void **p, size_t bytes, hipStream_t stream);
+void dev_free(void *p, size_t bytes, hipStream_t stream);
+Status dev_alloc_sync(void **p, size_t bytes);
+void dev_free_sync(void *p, size_t bytes);
+
+// Temporary device buffer that is released on scope exit, stream ordered.
+template <class T>
+struct DevBuf {
+    T *ptr = nullptr;
+    size_t count = 0;
+    hipStream_t stream = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { reset(); }
+    Status alloc(size_t n, hipStream_t s) {
+        reset();
+        stream = s;
+        count = n;
+        if (n == 0)
+            return {};
+        Status st = dev_alloc(reinterpret_cast<void **>(&ptr), n * sizeof(T), s);
+        if (st) {
+            ptr = nullptr;
+            count = 0;
+        }
+        return st;
+    }
+    void reset() {
+        if (ptr)
+            dev_free(ptr, count * sizeof(T), stream);
+        ptr = nullptr;
+        count = 0;
+    }
+};
+
+// Coefficients c_0..c_K of the function family (host, FP64, in sequence).
+Status make_coeffs(const mcmf_fn *f, int K, double *c);
+
+int num_cus();
+
+} // namespace mcmf
+
+// Opaque graph handle: the device copy of A and its per-row metadata.
+struct mcmf_graph {
+    int device = 0;
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int64_t d_max = 0;
+    int64_t n_active = 0; // rows with at least one entry
+    bool weighted = false;
+    bool symmetric = false;
+    bool has_loops = false;
+    hipStream_t stream = nullptr; // the graph's own stream
+
+    // Device arrays.
+    int64_t *row_ptr = nullptr; // [n+1]
+    int32_t *col = nullptr;     // [nnz]
+    double *val = nullptr;      // [nnz] or null
+    double *rowabs = nullptr;   // [n] sum |a| (weighted only)
+    double *cum = nullptr;      // [nnz] running sums of |a| per row (weighted only)
+    double *diagval = nullptr;  // [n] a_ii (only when the graph has loops)
+    uint2 *node = nullptr;      // [n] {first entry, row length}
+    int32_t *active = nullptr;  // [n_active] rows with entries, ascending
+    // Rows grouped by length for the sparse products: short (<= 64 entries,
+    // including empty rows), medium (<= 4096), long.
+    int32_t *bin_rows = nullptr; // [n] concatenated bins
+    int64_t bin_count[3] = {0, 0, 0};
+    int64_t bin_offset[3] = {0, 0, 0};
+    size_t bytes = 0;
+};

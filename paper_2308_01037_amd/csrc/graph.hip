@@ -1,0 +1,447 @@
+// CSR graph store in device memory and its per-row metadata (row records,
+// rows with entries, length bins, |a| sums and running sums for weighted
+// rows), plus the small utility kernels (fills, ordered compaction).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "device.hpp"
+#include "ops.hpp"
+
+namespace mcmf {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+int64_t grid_for(int64_t n, int threads = kThreads, int64_t cap = 1 << 20) {
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1)
+        b = 1;
+    return b < cap ? b : cap;
+}
+
+template <class T>
+__global__ void k_fill(T *out, T value, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = value;
+}
+
+template <class T>
+Status fill_impl(T *out, T value, int64_t n, hipStream_t s) {
+    if (n <= 0)
+        return {};
+    hipLaunchKernelGGL(k_fill<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, out, value, n);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+// ---- ordered compaction: 256 threads x 16 consecutive flags per block ----
+
+constexpr int kCompactPer = 16;
+constexpr int kCompactSpan = kThreads * kCompactPer;
+
+__device__ __forceinline__ uint32_t count_run(const uint8_t *flags, int64_t n, uint8_t match,
+                                              int64_t first) {
+    uint32_t c = 0;
+#pragma unroll
+    for (int j = 0; j < kCompactPer; ++j) {
+        const int64_t i = first + j;
+        c += (i < n && flags[i] == match) ? 1u : 0u;
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(kThreads) void k_compact_count(const uint8_t *flags, int64_t n,
+                                                            uint8_t match, uint32_t *counts) {
+    __shared__ uint32_t scratch[kThreads / 64];
+    const int64_t first = int64_t(blockIdx.x) * kCompactSpan + int64_t(threadIdx.x) * kCompactPer;
+    const uint32_t c = count_run(flags, n, match, first);
+    uint32_t total = 0;
+    dev::block_exclusive_scan(c, scratch, &total);
+    if (threadIdx.x == 0)
+        counts[blockIdx.x] = total;
+}
+
+// One workgroup turns the per-block counts into exclusive offsets.
+__global__ __launch_bounds__(1024) void k_compact_scan(uint32_t *counts, int64_t nb,
+                                                       unsigned long long *total) {
+    __shared__ uint32_t scratch[1024 / 64];
+    uint64_t running = 0;
+    for (int64_t base = 0; base < nb; base += blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        const uint32_t c = i < nb ? counts[i] : 0u;
+        uint32_t chunk = 0;
+        const uint32_t ex = dev::block_exclusive_scan(c, scratch, &chunk);
+        if (i < nb)
+            counts[i] = static_cast<uint32_t>(running + ex);
+        running += chunk;
+    }
+    if (threadIdx.x == 0)
+        *total = running;
+}
+
+__global__ __launch_bounds__(kThreads) void k_compact_write(const uint8_t *flags, int64_t n,
+                                                            uint8_t match, const uint32_t *offsets,
+                                                            int32_t *out) {
+    __shared__ uint32_t scratch[kThreads / 64];
+    const int64_t first = int64_t(blockIdx.x) * kCompactSpan + int64_t(threadIdx.x) * kCompactPer;
+    const uint32_t c = count_run(flags, n, match, first);
+    uint32_t total = 0;
+    uint32_t pos = offsets[blockIdx.x] + dev::block_exclusive_scan(c, scratch, &total);
+    for (int j = 0; j < kCompactPer; ++j) {
+        const int64_t i = first + j;
+        if (i < n && flags[i] == match)
+            out[pos++] = static_cast<int32_t>(i);
+    }
+}
+
+// ---- graph construction ----
+
+enum : int {
+    kErrRowPtr = 1,    // decreasing row_ptr
+    kErrColumn = 2,    // column outside [0, n)
+    kErrValue = 4,     // non-finite value
+    kErrUnsorted = 8,  // row not strictly increasing (needed by the symmetry check)
+    kErrAsymmetric = 16,
+};
+
+__global__ void k_check_row_ptr(const int64_t *row_ptr, int64_t n, int *err) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        if (row_ptr[i + 1] < row_ptr[i])
+            atomicOr(err, kErrRowPtr);
+}
+
+// One wavefront per row: column range, finite values, and (optionally) strict order.
+__global__ __launch_bounds__(kThreads) void k_check_entries(const int64_t *row_ptr, int64_t n,
+                                                            const int32_t *col, const double *val,
+                                                            int check_sorted, int *err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        int bad = 0;
+        for (int64_t k = b + lane; k < e; k += 64) {
+            const int32_t c = col[k];
+            if (c < 0 || c >= n)
+                bad |= kErrColumn;
+            if (val && !isfinite(val[k]))
+                bad |= kErrValue;
+            if (check_sorted && k + 1 < e && col[k + 1] <= c)
+                bad |= kErrUnsorted;
+        }
+        if (bad)
+            atomicOr(err, bad);
+    }
+}
+
+// Per-row metadata.  Weighted rows get sum |a| and the running sums of |a|
+// in storage order, each a plain left-to-right FP64 sum.
+__global__ void k_graph_meta(const int64_t *row_ptr, int64_t n, const double *val, uint2 *node,
+                             uint8_t *active, uint8_t *bin, double *rowabs, double *cum,
+                             unsigned long long *dmax) {
+    unsigned long long local_max = 0;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        const int64_t d = e - b;
+        node[i] = make_uint2(static_cast<uint32_t>(b), static_cast<uint32_t>(d));
+        active[i] = d > 0 ? 1 : 0;
+        bin[i] = d <= 64 ? 0 : (d <= 4096 ? 1 : 2);
+        local_max = d > static_cast<int64_t>(local_max) ? static_cast<unsigned long long>(d) : local_max;
+        if (val) {
+            double sum = 0.0;
+            for (int64_t k = b; k < e; ++k) {
+                sum = sum + fabs(val[k]);
+                cum[k] = sum;
+            }
+            rowabs[i] = sum;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long other = __shfl_xor(local_max, off, 64);
+        local_max = other > local_max ? other : local_max;
+    }
+    if ((threadIdx.x & 63) == 0)
+        atomicMax(dmax, local_max);
+}
+
+// a_ji == a_ij for every stored a_ij (rows sorted): one wavefront per row,
+// each lane binary-searches row j for i.
+__global__ __launch_bounds__(kThreads) void k_check_symmetric(const uint2 *node, int64_t n,
+                                                              const int32_t *col, const double *val,
+                                                              int *err) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x / 64) + (threadIdx.x >> 6); i < n; i += waves) {
+        const uint2 ri = node[i];
+        int bad = 0;
+        for (uint32_t k = lane; k < ri.y; k += 64) {
+            const int64_t e = int64_t(ri.x) + k;
+            const int32_t j = col[e];
+            const uint2 rj = node[j];
+            uint32_t lo = 0, hi = rj.y;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (col[int64_t(rj.x) + mid] < i)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            if (lo >= rj.y || col[int64_t(rj.x) + lo] != i)
+                bad = kErrAsymmetric;
+            else if (val && val[int64_t(rj.x) + lo] != val[e])
+                bad = kErrAsymmetric;
+        }
+        if (bad)
+            atomicOr(err, bad);
+    }
+}
+
+Status read_scalar(const int64_t *p, int64_t *out, Mem m) {
+    if (m == Mem::Host) {
+        *out = *p;
+        return {};
+    }
+    MCMF_HIP(hipMemcpy(out, p, sizeof(int64_t), hipMemcpyDeviceToHost));
+    return {};
+}
+
+Status copy_in(void *dst, const void *src, size_t bytes, Mem m, hipStream_t s) {
+    if (bytes == 0)
+        return {};
+    MCMF_HIP(hipMemcpyAsync(dst, src, bytes,
+                            m == Mem::Host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    return {};
+}
+
+Status read_flag(int *dflag, int *out, hipStream_t s) {
+    MCMF_HIP(hipMemcpyAsync(out, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    return {};
+}
+
+void free_graph(mcmf_graph *g) {
+    if (!g)
+        return;
+    if (g->stream)
+        (void)hipStreamSynchronize(g->stream);
+    dev_free_sync(g->col, sizeof(int32_t) * g->nnz);
+    dev_free_sync(g->val, sizeof(double) * g->nnz);
+    dev_free_sync(g->rowabs, sizeof(double) * g->n);
+    dev_free_sync(g->cum, sizeof(double) * g->nnz);
+    dev_free_sync(g->node, sizeof(uint2) * g->n);
+    dev_free_sync(g->active, sizeof(int32_t) * g->n_active);
+    dev_free_sync(g->bin_rows, sizeof(int32_t) * g->n);
+    if (g->stream)
+        (void)hipStreamDestroy(g->stream);
+    delete g;
+}
+
+Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32_t *col,
+                   const double *values, uint32_t flags) {
+    const Mem m_rp = classify(row_ptr);
+    const Mem m_col = classify(col);
+    const Mem m_val = classify(values);
+    int64_t first = 0, nnz = 0;
+    MCMF_TRY(read_scalar(row_ptr, &first, m_rp));
+    MCMF_TRY(read_scalar(row_ptr + n, &nnz, m_rp));
+    if (first != 0)
+        return fail(MCMF_E_CSR, "row_ptr[0] = %lld, expected 0", static_cast<long long>(first));
+    if (nnz < 0)
+        return fail(MCMF_E_CSR, "row_ptr[n] = %lld is negative", static_cast<long long>(nnz));
+    if (nnz >= (int64_t(1) << 32))
+        return fail(MCMF_E_UNSUPPORTED, "nnz = %lld: at most 2^32-1 entries are supported",
+                    static_cast<long long>(nnz));
+    if (nnz > 0 && !col)
+        return fail(MCMF_E_ARG, "col_idx is NULL with nnz > 0");
+
+    MCMF_HIP(hipGetDevice(&g->device));
+    MCMF_HIP(hipStreamCreateWithFlags(&g->stream, hipStreamNonBlocking));
+    hipStream_t s = g->stream;
+    g->n = n;
+    g->nnz = nnz;
+    g->weighted = values != nullptr;
+    g->symmetric = (flags & MCMF_SYMMETRIC) != 0;
+
+    DevBuf<int64_t> d_rp;
+    DevBuf<int> d_err;
+    DevBuf<unsigned long long> d_dmax;
+    DevBuf<uint8_t> d_active, d_bin;
+    MCMF_TRY(d_rp.alloc(n + 1, s));
+    MCMF_TRY(d_err.alloc(1, s));
+    MCMF_TRY(d_dmax.alloc(1, s));
+    MCMF_TRY(d_active.alloc(n > 0 ? n : 1, s));
+    MCMF_TRY(d_bin.alloc(n > 0 ? n : 1, s));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->col), sizeof(int32_t) * nnz));
+    if (g->weighted) {
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->val), sizeof(double) * nnz));
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->cum), sizeof(double) * nnz));
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->rowabs), sizeof(double) * n));
+    }
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->node), sizeof(uint2) * n));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->bin_rows), sizeof(int32_t) * n));
+
+    MCMF_TRY(copy_in(d_rp.ptr, row_ptr, sizeof(int64_t) * (n + 1), m_rp, s));
+    MCMF_TRY(copy_in(g->col, col, sizeof(int32_t) * nnz, m_col, s));
+    if (g->weighted)
+        MCMF_TRY(copy_in(g->val, values, sizeof(double) * nnz, m_val, s));
+
+    // Structure first: a decreasing row_ptr would send the entry checks out of range.
+    int err = 0;
+    MCMF_TRY(fill_impl<int>(d_err.ptr, 0, 1, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_check_row_ptr, dim3(grid_for(n)), dim3(kThreads), 0, s, d_rp.ptr, n,
+                           d_err.ptr);
+        MCMF_HIP(hipGetLastError());
+    }
+    MCMF_TRY(read_flag(d_err.ptr, &err, s));
+    if (err & kErrRowPtr)
+        return fail(MCMF_E_CSR, "row_ptr is not non-decreasing");
+    const bool validate = (flags & MCMF_VALIDATE) != 0;
+    const bool check_sym = validate && g->symmetric;
+    if (n > 0) {
+        hipLaunchKernelGGL(k_check_entries, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, d_rp.ptr,
+                           n, g->col, validate ? g->val : nullptr, check_sym ? 1 : 0, d_err.ptr);
+        MCMF_HIP(hipGetLastError());
+    }
+    MCMF_TRY(read_flag(d_err.ptr, &err, s));
+    if (err & kErrColumn)
+        return fail(MCMF_E_CSR, "a column index lies outside [0, n)");
+    if (err & kErrValue)
+        return fail(MCMF_E_CSR, "a stored value is not finite");
+    if (err & kErrUnsorted)
+        return fail(MCMF_E_NOT_SYMMETRIC,
+                    "the symmetry check needs strictly increasing columns within each row");
+
+    MCMF_TRY(fill_impl<unsigned long long>(d_dmax.ptr, 0ull, 1, s));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_graph_meta, dim3(grid_for(n)), dim3(kThreads), 0, s, d_rp.ptr, n,
+                           g->val, g->node, d_active.ptr, d_bin.ptr, g->rowabs, g->cum, d_dmax.ptr);
+        MCMF_HIP(hipGetLastError());
+    }
+    if (check_sym && n > 0) {
+        hipLaunchKernelGGL(k_check_symmetric, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, g->node,
+                           n, g->col, g->val, d_err.ptr);
+        MCMF_HIP(hipGetLastError());
+        MCMF_TRY(read_flag(d_err.ptr, &err, s));
+        if (err & kErrAsymmetric)
+            return fail(MCMF_E_NOT_SYMMETRIC, "A is not equal to its transpose");
+    }
+    unsigned long long dmax = 0;
+    MCMF_HIP(hipMemcpyAsync(&dmax, d_dmax.ptr, sizeof dmax, hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    g->d_max = static_cast<int64_t>(dmax);
+
+    // Rows with entries (walk start rows), then rows by length bin.
+    DevBuf<int32_t> tmp_active;
+    MCMF_TRY(tmp_active.alloc(n > 0 ? n : 1, s));
+    MCMF_TRY(compact(d_active.ptr, n, 1, tmp_active.ptr, &g->n_active, s));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->active), sizeof(int32_t) * g->n_active));
+    if (g->n_active > 0)
+        MCMF_HIP(hipMemcpyAsync(g->active, tmp_active.ptr, sizeof(int32_t) * g->n_active,
+                                hipMemcpyDeviceToDevice, s));
+    int64_t off = 0;
+    for (int b = 0; b < 3; ++b) {
+        g->bin_offset[b] = off;
+        MCMF_TRY(compact(d_bin.ptr, n, static_cast<uint8_t>(b), g->bin_rows + off, &g->bin_count[b], s));
+        off += g->bin_count[b];
+    }
+    MCMF_HIP(hipStreamSynchronize(s));
+    g->bytes = sizeof(int32_t) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
+               (g->weighted ? sizeof(double) * (2 * nnz + n) : 0);
+    return {};
+}
+
+} // namespace
+
+Status fill_u8(uint8_t *out, uint8_t value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }
+Status fill_i32(int32_t *out, int32_t value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }
+Status fill_f64(double *out, double value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }
+Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }
+
+Status compact(const uint8_t *flags, int64_t n, uint8_t match, int32_t *out, int64_t *count,
+               hipStream_t s) {
+    *count = 0;
+    if (n <= 0)
+        return {};
+    const int64_t nb = (n + kCompactSpan - 1) / kCompactSpan;
+    DevBuf<uint32_t> counts;
+    DevBuf<unsigned long long> total;
+    MCMF_TRY(counts.alloc(nb, s));
+    MCMF_TRY(total.alloc(1, s));
+    hipLaunchKernelGGL(k_compact_count, dim3(nb), dim3(kThreads), 0, s, flags, n, match, counts.ptr);
+    MCMF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_compact_scan, dim3(1), dim3(1024), 0, s, counts.ptr, nb, total.ptr);
+    MCMF_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_compact_write, dim3(nb), dim3(kThreads), 0, s, flags, n, match, counts.ptr,
+                       out);
+    MCMF_HIP(hipGetLastError());
+    unsigned long long c = 0;
+    MCMF_HIP(hipMemcpyAsync(&c, total.ptr, sizeof c, hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    *count = static_cast<int64_t>(c);
+    return {};
+}
+
+} // namespace mcmf
+
+using namespace mcmf;
+
+extern "C" mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                                         const double *values, uint32_t flags, mcmf_graph **out) {
+    clear_error();
+    if (!out) {
+        fail(MCMF_E_ARG, "out is NULL");
+        return MCMF_E_ARG;
+    }
+    if (n < 0 || n >= (int64_t(1) << 31)) {
+        fail(MCMF_E_ARG, "n = %lld outside [0, 2^31)", static_cast<long long>(n));
+        return MCMF_E_ARG;
+    }
+    if (!row_ptr) {
+        fail(MCMF_E_ARG, "row_ptr is NULL");
+        return MCMF_E_ARG;
+    }
+    if (flags & ~(MCMF_SYMMETRIC | MCMF_VALIDATE)) {
+        fail(MCMF_E_ARG, "unknown flag bits 0x%x", flags & ~(MCMF_SYMMETRIC | MCMF_VALIDATE));
+        return MCMF_E_ARG;
+    }
+    mcmf_graph *g = new (std::nothrow) mcmf_graph();
+    if (!g) {
+        fail(MCMF_E_NOMEM, "host allocation failed");
+        return MCMF_E_NOMEM;
+    }
+    Status st = build_graph(g, n, row_ptr, col_idx, values, flags);
+    if (st) {
+        const std::string msg = mcmf_last_error();
+        free_graph(g);
+        set_error("%s", msg.c_str());
+        return st.code;
+    }
+    *out = g;
+    return MCMF_OK;
+}
+
+extern "C" void mcmf_graph_destroy(mcmf_graph *g) { free_graph(g); }
+
+extern "C" mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64_t *d_max,
+                                       int64_t *active_rows) {
+    clear_error();
+    if (!g) {
+        fail(MCMF_E_ARG, "graph is NULL");
+        return MCMF_E_ARG;
+    }
+    if (n)
+        *n = g->n;
+    if (nnz)
+        *nnz = g->nnz;
+    if (d_max)
+        *d_max = g->d_max;
+    if (active_rows)
+        *active_rows = g->n_active;
+    return MCMF_OK;
+}

@@ -1,0 +1,63 @@
+// Launchers of the library's kernels, callable from any translation unit.
+#pragma once
+
+#include "common.hpp"
+
+namespace mcmf {
+
+// out[i] = value for i < n (a kernel, so it is also safe inside captured graphs).
+Status fill_u8(uint8_t *out, uint8_t value, int64_t n, hipStream_t s);
+Status fill_i32(int32_t *out, int32_t value, int64_t n, hipStream_t s);
+Status fill_f64(double *out, double value, int64_t n, hipStream_t s);
+Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s);
+
+// Ascending indices i < n with flags[i] == match written to out; *count (host)
+// receives how many.  Synchronises the stream to read the count back.
+Status compact(const uint8_t *flags, int64_t n, uint8_t match, int32_t *out, int64_t *count,
+               hipStream_t s);
+
+// Per-call walk parameters shared by the walk kernels.
+struct WalkParams {
+    const double *coef; // device: c_{t+2} at index t, t = 0..K-2
+    int K;
+    double scale;
+    int64_t n_walks;
+    uint32_t key0, key1;
+    uint32_t request;
+    double cutoff; // 0 = off
+    int precision; // MCMF_PRECISION_*
+};
+
+// Packed per-row record the action walk reads in one 16-byte load.
+struct alignas(16) ActionNode {
+    uint32_t start; // first entry of the row
+    uint32_t deg;   // row length
+    double r;       // (sA v)_row
+};
+
+// r = s A v into the records (every row gets start/deg/r).
+Status spmv_records(const mcmf_graph *g, const double *v, double scale, ActionNode *rec,
+                    hipStream_t s);
+// y = c0 v + c1 r + s A q (q may be null when K < 2: then only c0 v + c1 r).
+Status spmv_assemble(const mcmf_graph *g, const double *v, const ActionNode *rec, const double *q,
+                     double c0, double c1, double scale, double *y, hipStream_t s);
+
+// Action walks: q[k] for every k in starts[0..n_start).  digest/steps optional.
+Status action_walks(const mcmf_graph *g, const ActionNode *rec, const int32_t *starts,
+                    int64_t n_start, const WalkParams &p, double *q, uint64_t *digest,
+                    unsigned long long *steps, hipStream_t s);
+
+// Diag walks for starts[0..n_start): visit records, t-major per start row:
+// state[(kk*(K-1) + t)*N + w], x = c_{t+2} W_t; finished walks store -1.
+Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
+                  int32_t *state, double *x, uint64_t *digest, unsigned long long *steps,
+                  hipStream_t s);
+
+// Diag gather for starts[0..n_start) with their visit records: for each
+// requested neighbour i of k, dacc[i] += s^2 a_ki <Q_k, C_i> / N.
+// in_set == null means every row is requested.
+Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
+                   const int32_t *state, const double *x, const uint8_t *in_set, double *dacc,
+                   unsigned long long *probes, hipStream_t s);
+
+} // namespace mcmf

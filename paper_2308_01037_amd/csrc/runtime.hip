@@ -1,0 +1,222 @@
+// Error state, device-memory accounting, pointer classification and the
+// function-coefficient tables.
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+
+#include "common.hpp"
+
+namespace mcmf {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+Status fail(mcmf_status code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    Status s;
+    s.code = code;
+    return s;
+}
+
+Status hip_fail(hipError_t e, const char *what, const char *file, int line) {
+    const char *base = strrchr(file, '/');
+    Status s = fail(e == hipErrorOutOfMemory ? MCMF_E_NOMEM : MCMF_E_DEVICE, "%s failed: %s (%s:%d)",
+                    what, hipGetErrorString(e), base ? base + 1 : file, line);
+    (void)hipGetLastError();
+    return s;
+}
+
+Mem classify(const void *p) {
+    if (!p)
+        return Mem::Host;
+    hipPointerAttribute_t attr;
+    memset(&attr, 0, sizeof attr);
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return Mem::Host;
+    }
+    return (attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged) ? Mem::Device
+                                                                                 : Mem::Host;
+}
+
+// ---------------------------------------------------------------- memory
+
+static std::atomic<int64_t> g_bytes_in_use{0};
+
+static int64_t budget_bytes() {
+    static int64_t budget = [] {
+        const char *s = getenv("MCMF_HBM_BUDGET_BYTES");
+        return s ? static_cast<int64_t>(strtoll(s, nullptr, 10)) : int64_t(0);
+    }();
+    return budget;
+}
+
+static bool forced_failure() {
+    const char *s = getenv("MCMF_TEST_FAIL_ALLOC");
+    return s && s[0] == '1';
+}
+
+static Status reserve(size_t bytes) {
+    if (forced_failure())
+        return fail(MCMF_E_NOMEM, "device allocation of %zu bytes refused (MCMF_TEST_FAIL_ALLOC)",
+                    bytes);
+    const int64_t b = budget_bytes();
+    const int64_t now = g_bytes_in_use.fetch_add(static_cast<int64_t>(bytes)) + static_cast<int64_t>(bytes);
+    if (b > 0 && now > b) {
+        g_bytes_in_use.fetch_sub(static_cast<int64_t>(bytes));
+        return fail(MCMF_E_NOMEM, "device byte budget exceeded: %lld in use + %zu requested > %lld",
+                    static_cast<long long>(now - static_cast<int64_t>(bytes)), bytes,
+                    static_cast<long long>(b));
+    }
+    return {};
+}
+
+static void unreserve(size_t bytes) { g_bytes_in_use.fetch_sub(static_cast<int64_t>(bytes)); }
+
+static Status ensure_pool(int device) {
+    // Keep freed stream-ordered memory in the pool so that repeated calls do
+    // not return it to the driver.
+    static std::mutex mu;
+    static bool done[64] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0 || device >= 64 || done[device])
+        return {};
+    hipMemPool_t pool;
+    MCMF_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t threshold = UINT64_MAX;
+    MCMF_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
+    done[device] = true;
+    return {};
+}
+
+Status dev_alloc(void **p, size_t bytes, hipStream_t stream) {
+    *p = nullptr;
+    if (bytes == 0)
+        return {};
+    MCMF_TRY(reserve(bytes));
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e == hipSuccess) {
+        Status s = ensure_pool(device);
+        if (s) {
+            unreserve(bytes);
+            return s;
+        }
+        e = hipMallocAsync(p, bytes, stream);
+    }
+    if (e != hipSuccess) {
+        unreserve(bytes);
+        *p = nullptr;
+        return hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
+    }
+    return {};
+}
+
+void dev_free(void *p, size_t bytes, hipStream_t stream) {
+    if (!p)
+        return;
+    (void)hipFreeAsync(p, stream);
+    unreserve(bytes);
+}
+
+Status dev_alloc_sync(void **p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0)
+        return {};
+    MCMF_TRY(reserve(bytes));
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        unreserve(bytes);
+        *p = nullptr;
+        return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
+    }
+    return {};
+}
+
+void dev_free_sync(void *p, size_t bytes) {
+    if (!p)
+        return;
+    (void)hipFree(p);
+    unreserve(bytes);
+}
+
+// ---------------------------------------------------------------- coefficients
+
+Status make_coeffs(const mcmf_fn *f, int K, double *c) {
+    switch (f->kind) {
+    case MCMF_FN_EXP:
+        c[0] = 1.0;
+        for (int k = 1; k <= K; ++k)
+            c[k] = c[k - 1] / static_cast<double>(k);
+        return {};
+    case MCMF_FN_RESOLVENT:
+        for (int k = 0; k <= K; ++k)
+            c[k] = 1.0;
+        return {};
+    case MCMF_FN_COEFFS:
+        if (!f->coeffs)
+            return fail(MCMF_E_ARG, "MCMF_FN_COEFFS needs a coefficient array");
+        if (f->n_coeffs < K + 1)
+            return fail(MCMF_E_ARG, "MCMF_FN_COEFFS has %d coefficients, K=%d needs %d", f->n_coeffs,
+                        K, K + 1);
+        if (classify(f->coeffs) != Mem::Host)
+            return fail(MCMF_E_ARG, "coefficients must be in host memory");
+        for (int k = 0; k <= K; ++k) {
+            if (!std::isfinite(f->coeffs[k]))
+                return fail(MCMF_E_ARG, "coefficient c_%d is not finite", k);
+            c[k] = f->coeffs[k];
+        }
+        return {};
+    default:
+        return fail(MCMF_E_ARG, "unknown function kind %d", f->kind);
+    }
+}
+
+int num_cus() {
+    static int cus = [] {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+            (void)hipGetLastError();
+            return 256;
+        }
+        return prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    }();
+    return cus;
+}
+
+} // namespace mcmf
+
+extern "C" const char *mcmf_status_string(mcmf_status s) {
+    switch (s) {
+    case MCMF_OK: return "MCMF_OK";
+    case MCMF_E_ARG: return "MCMF_E_ARG";
+    case MCMF_E_CSR: return "MCMF_E_CSR";
+    case MCMF_E_NOT_SYMMETRIC: return "MCMF_E_NOT_SYMMETRIC";
+    case MCMF_E_NOMEM: return "MCMF_E_NOMEM";
+    case MCMF_E_DEVICE: return "MCMF_E_DEVICE";
+    case MCMF_E_UNSUPPORTED: return "MCMF_E_UNSUPPORTED";
+    }
+    return "MCMF_E_UNKNOWN";
+}
+
+extern "C" const char *mcmf_last_error(void) { return mcmf::g_last_error.c_str(); }

@@ -1,0 +1,257 @@
+// Random-walk kernels of the estimator (Lemma 2; Algorithm 3 for the action,
+// Eq. rand_funm_Q for the diagonal).  One workgroup per start row k runs
+// that row's walks; lane w runs walk w (and w + blockDim, ...).
+//
+// A walk keeps its state in registers: the current row l, the weight W and
+// the row record of l.  Per recorded step t it either adds c_{t+2} W r_l to a
+// register sum (action) or writes the visit (l, c_{t+2} W) to the visit
+// buffer (diagonal).  A transition draws Philox4x32-10 at counter
+// (k, w, t, request), picks entry j of row l (floor(u deg / 2^64) for
+// unweighted rows, the inverse running-sum search for weighted rows),
+// multiplies W by s * sum_j |a_lj| (negated for a negative entry) and moves
+// to col[start_l + j].
+#include "device.hpp"
+#include "ops.hpp"
+
+namespace mcmf {
+
+namespace {
+
+// First index j < deg with target < cum[j] (cum non-decreasing); deg-1 if none.
+__device__ __forceinline__ uint32_t cdf_search(const double *__restrict__ cum, uint32_t deg,
+                                               double target) {
+    uint32_t lo = 0, hi = deg;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (target < cum[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo < deg ? lo : deg - 1;
+}
+
+struct WalkArgs {
+    const double *coef; // c_{t+2} at index t
+    int K;
+    double scale;
+    int64_t N;
+    uint32_t key0, key1, request;
+    double cutoff;
+};
+
+WalkArgs to_args(const WalkParams &p) {
+    WalkArgs a;
+    a.coef = p.coef;
+    a.K = p.K;
+    a.scale = p.scale;
+    a.N = p.n_walks;
+    a.key0 = p.key0;
+    a.key1 = p.key1;
+    a.request = p.request;
+    a.cutoff = p.cutoff;
+    return a;
+}
+
+// Action: q[k] = (1/N) sum_w sum_t c_{t+2} W_t r_{l_t}.
+template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
+__global__ __launch_bounds__(256) void k_action_walk(
+    const ActionNode *__restrict__ rec, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ rowabs,
+    const double *__restrict__ cum, const int32_t *__restrict__ starts, int64_t n_start,
+    WalkArgs a, double *__restrict__ q, uint64_t *__restrict__ digest, unsigned long long *steps) {
+    __shared__ double red[4];
+    __shared__ unsigned long long redu[4];
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+    const uint32_t k = static_cast<uint32_t>(starts[kk]);
+    const int last = a.K - 2;
+    double acc = 0.0;
+    uint64_t dig = 0;
+    unsigned long long nsteps = 0;
+    for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+        const uint32_t w = static_cast<uint32_t>(w64);
+        uint32_t l = k;
+        double W = 1.0;
+        double wacc = 0.0;
+        uint64_t h = dev::kFnvBasis;
+        ActionNode R = rec[l];
+        for (int t = 0; t <= last; ++t) {
+            if (CUTOFF && !(fabs(W) > a.cutoff))
+                break;
+            wacc += a.coef[t] * W * R.r;
+            if (DIGEST)
+                h = dev::fnv_step(h, l);
+            ++nsteps;
+            if (t == last || R.deg == 0)
+                break;
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            uint32_t j;
+            double m;
+            if (!WEIGHTED) {
+                j = dev::uniform_index(x.x, x.y, R.deg);
+                m = a.scale * static_cast<double>(R.deg);
+            } else {
+                const double ra = rowabs[l];
+                j = cdf_search(cum + R.start, R.deg, dev::unit53(x.x, x.y) * ra);
+                m = a.scale * ra;
+            }
+            W = W * m;
+            if (WEIGHTED && val[R.start + j] < 0.0)
+                W = -W;
+            l = static_cast<uint32_t>(col[R.start + j]);
+            R = rec[l];
+        }
+        acc += wacc;
+        if (DIGEST)
+            dig += h;
+    }
+    const double total = dev::block_sum(acc, red);
+    const unsigned long long st = dev::block_sum(nsteps, redu);
+    if (DIGEST) {
+        const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu + 0);
+        if (threadIdx.x == 0)
+            digest[k] = dg;
+    }
+    if (threadIdx.x == 0) {
+        q[k] = total / static_cast<double>(a.N);
+        if (steps)
+            atomicAdd(steps, st);
+    }
+    }
+}
+
+// Diagonal: visit records of start row kk, t-major: slot (kk*(K-1) + t)*N + w
+// holds (l_t, c_{t+2} W_t); after a walk ends early its slots hold state -1.
+template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
+__global__ __launch_bounds__(256) void k_diag_walk(
+    const uint2 *__restrict__ node, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ rowabs,
+    const double *__restrict__ cum, const int32_t *__restrict__ starts, int64_t n_start,
+    WalkArgs a, int32_t *__restrict__ vstate, double *__restrict__ vx,
+    uint64_t *__restrict__ digest, unsigned long long *steps) {
+    __shared__ unsigned long long redu[4];
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+    const uint32_t k = static_cast<uint32_t>(starts[kk]);
+    const int last = a.K - 2;
+    const int64_t row_base = kk * (a.K - 1) * a.N;
+    uint64_t dig = 0;
+    unsigned long long nsteps = 0;
+    for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+        const uint32_t w = static_cast<uint32_t>(w64);
+        uint32_t l = k;
+        double W = 1.0;
+        uint64_t h = dev::kFnvBasis;
+        uint2 R = node[l];
+        int t = 0;
+        for (; t <= last; ++t) {
+            if (CUTOFF && !(fabs(W) > a.cutoff))
+                break;
+            const int64_t slot = row_base + int64_t(t) * a.N + w64;
+            vstate[slot] = static_cast<int32_t>(l);
+            vx[slot] = a.coef[t] * W;
+            if (DIGEST)
+                h = dev::fnv_step(h, l);
+            ++nsteps;
+            if (t == last || R.y == 0) {
+                ++t;
+                break;
+            }
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            uint32_t j;
+            double m;
+            if (!WEIGHTED) {
+                j = dev::uniform_index(x.x, x.y, R.y);
+                m = a.scale * static_cast<double>(R.y);
+            } else {
+                const double ra = rowabs[l];
+                j = cdf_search(cum + R.x, R.y, dev::unit53(x.x, x.y) * ra);
+                m = a.scale * ra;
+            }
+            W = W * m;
+            if (WEIGHTED && val[R.x + j] < 0.0)
+                W = -W;
+            l = static_cast<uint32_t>(col[R.x + j]);
+            R = node[l];
+        }
+        for (; t <= last; ++t)
+            vstate[row_base + int64_t(t) * a.N + w64] = -1;
+        if (DIGEST)
+            dig += h;
+    }
+    const unsigned long long st = dev::block_sum(nsteps, redu);
+    if (DIGEST) {
+        const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+        if (threadIdx.x == 0)
+            digest[k] = dg;
+    }
+    if (threadIdx.x == 0 && steps)
+        atomicAdd(steps, st);
+    }
+}
+
+int walk_block(int64_t N) {
+    if (N >= 256)
+        return 256;
+    return static_cast<int>(((N + 63) / 64) * 64);
+}
+
+// Workgroups loop over start rows, so the grid stays within the 32-bit
+// work-item count of a dispatch whatever the number of start rows.
+dim3 walk_grid(int64_t n_start) {
+    const int64_t cap = int64_t(1) << 22;
+    return dim3(static_cast<uint32_t>(n_start < cap ? n_start : cap));
+}
+
+} // namespace
+
+Status action_walks(const mcmf_graph *g, const ActionNode *rec, const int32_t *starts,
+                    int64_t n_start, const WalkParams &p, double *q, uint64_t *digest,
+                    unsigned long long *steps, hipStream_t s) {
+    if (n_start <= 0 || p.K < 2)
+        return {};
+    const WalkArgs a = to_args(p);
+    const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
+    const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
+#define MCMF_LAUNCH_ACTION(W_, D_, C_)                                                             \
+    hipLaunchKernelGGL((k_action_walk<W_, D_, C_>), grid, block, 0, s, rec, g->col, g->val,          \
+                       g->rowabs, g->cum, starts, n_start, a, q, digest, steps)
+    if (!w && !d && !c) MCMF_LAUNCH_ACTION(false, false, false);
+    else if (!w && !d && c) MCMF_LAUNCH_ACTION(false, false, true);
+    else if (!w && d && !c) MCMF_LAUNCH_ACTION(false, true, false);
+    else if (!w && d && c) MCMF_LAUNCH_ACTION(false, true, true);
+    else if (w && !d && !c) MCMF_LAUNCH_ACTION(true, false, false);
+    else if (w && !d && c) MCMF_LAUNCH_ACTION(true, false, true);
+    else if (w && d && !c) MCMF_LAUNCH_ACTION(true, true, false);
+    else MCMF_LAUNCH_ACTION(true, true, true);
+#undef MCMF_LAUNCH_ACTION
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
+                  int32_t *state, double *x, uint64_t *digest, unsigned long long *steps,
+                  hipStream_t s) {
+    if (n_start <= 0 || p.K < 2)
+        return {};
+    const WalkArgs a = to_args(p);
+    const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
+    const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
+#define MCMF_LAUNCH_DIAG(W_, D_, C_)                                                               \
+    hipLaunchKernelGGL((k_diag_walk<W_, D_, C_>), grid, block, 0, s, g->node, g->col, g->val,       \
+                       g->rowabs, g->cum, starts, n_start, a, state, x, digest, steps)
+    if (!w && !d && !c) MCMF_LAUNCH_DIAG(false, false, false);
+    else if (!w && !d && c) MCMF_LAUNCH_DIAG(false, false, true);
+    else if (!w && d && !c) MCMF_LAUNCH_DIAG(false, true, false);
+    else if (!w && d && c) MCMF_LAUNCH_DIAG(false, true, true);
+    else if (w && !d && !c) MCMF_LAUNCH_DIAG(true, false, false);
+    else if (w && !d && c) MCMF_LAUNCH_DIAG(true, false, true);
+    else if (w && d && !c) MCMF_LAUNCH_DIAG(true, true, false);
+    else MCMF_LAUNCH_DIAG(true, true, true);
+#undef MCMF_LAUNCH_DIAG
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+} // namespace mcmf

@@ -1,0 +1,85 @@
+"""The C ABI on the CPU: the library loads, exports every function the header
+declares, and rejects bad arguments before touching the device."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import graphgen as G
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mcmf.h")
+LIB = os.path.join(ROOT, "paper_2308_01037_amd", "libmcmf.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libmcmf.so not built")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mcmf_[a-z_]+)\s*\(", text)))
+
+
+def test_every_declared_function_is_exported():
+    names = _declared()
+    assert {"mcmf_graph_create", "mcmf_diag", "mcmf_action"} <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (mcmf_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    from paper_2308_01037_amd import mcmf as M
+    assert sorted(M.EXPORTED) == names
+
+
+def test_status_strings():
+    from paper_2308_01037_amd import mcmf as M
+    assert M.mcmf_status_string(M.MCMF_OK) == "MCMF_OK"
+    assert M.mcmf_status_string(M.MCMF_E_NOT_SYMMETRIC) == "MCMF_E_NOT_SYMMETRIC"
+    assert M.mcmf_status_string(99) == "MCMF_E_UNKNOWN"
+
+
+def test_argument_errors_need_no_device():
+    import ctypes
+    from paper_2308_01037_amd import mcmf as M
+    g = G.path(5)
+    lib = M._lib
+    assert lib.mcmf_graph_create(5, g.row_ptr.ctypes.data, g.col.ctypes.data, None, 1, None) == M.MCMF_E_ARG
+    out = ctypes.c_void_p()
+    assert lib.mcmf_graph_create(-1, g.row_ptr.ctypes.data, g.col.ctypes.data, None, 1,
+                                 ctypes.byref(out)) == M.MCMF_E_ARG
+    assert lib.mcmf_graph_create(5, None, g.col.ctypes.data, None, 1, ctypes.byref(out)) == M.MCMF_E_ARG
+    assert lib.mcmf_graph_create(5, g.row_ptr.ctypes.data, g.col.ctypes.data, None, 64,
+                                 ctypes.byref(out)) == M.MCMF_E_ARG
+    rp = g.row_ptr.copy()
+    rp[0] = 1
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_graph_create(5, rp, g.col)
+    assert e.value.status == M.MCMF_E_CSR and "row_ptr[0]" in M.mcmf_last_error()
+    big = np.array([0, 2**32], dtype=np.int64)
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_graph_create(1, big, np.zeros(1, np.int32))
+    assert e.value.status == M.MCMF_E_UNSUPPORTED
+    y = np.zeros(5)
+    f = M.make_fn()
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_action(None, f, np.ones(5), 10, 5, None, y)
+    assert e.value.status == M.MCMF_E_ARG and "graph" in M.mcmf_last_error()
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_diag(None, f, None, 0, 10, 5, None, y)
+    assert e.value.status == M.MCMF_E_ARG
+    assert np.all(y == 0)
+
+
+def test_import_fails_loudly_without_library(tmp_path):
+    # A copy of the binding next to no library must refuse to import.
+    import shutil
+    import sys
+    pkg = tmp_path / "pkgcopy"
+    pkg.mkdir()
+    shutil.copy(os.path.join(ROOT, "paper_2308_01037_amd", "mcmf.py"), pkg / "mcmf.py")
+    code = f"import sys; sys.path.insert(0, {str(pkg)!r}); import mcmf"
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
+    assert res.returncode != 0 and "libmcmf.so is missing" in res.stderr

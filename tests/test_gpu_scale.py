@@ -1,0 +1,104 @@
+"""GPU checks at full size.
+
+* Exact cases with no oracle needed: the 2D torus (4-regular: f(sA) 1 is
+  sum_k c_k (4s)^k on every walk) at 10^6 nodes, and K_{p,q} with a hub side
+  of 20000 entries per row (the diagonal is the closed form on every walk).
+* The R-MAT scale-20 workload in the launch configuration the benchmark
+  times: full diagonal and full action for exp(beta A), beta = 1/d_max, and
+  the resolvent with gamma = 0.85/lambda_max, K = 40, N = 256.  Sampled
+  output rows are recomputed by the oracle (it replays only the walks those
+  rows need) and must match to 1e-10 with bit-exact path digests; every
+  output must also satisfy x >= h (all terms are non-negative).
+"""
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from _gpu import assert_close, gpu_action, gpu_diag, graph  # noqa: E402
+
+
+def test_torus_million_nodes_exact():
+    csr = G.torus2d(1000, 1000)
+    K, s = 40, 0.2
+    c = oracle.coeffs(oracle.FN_EXP, K)
+    want = sum(c[k] * (4 * s) ** k for k in range(K + 1))
+    with graph(csr) as g:
+        r = gpu_action(g, "exp", np.ones(csr.n), 64, K, s, seed=3, stats=True)
+    assert_close(r["y"], np.full(csr.n, want), 1e-13, what="torus")
+    assert r["stats"]["walk_steps"] == csr.n * 64 * (K - 1)
+
+
+def test_complete_bipartite_hub_rows_exact():
+    p, q = 3, 20000
+    csr = G.complete_bipartite(p, q)
+    K, s = 12, 1.0 / q
+    c = oracle.coeffs(oracle.FN_RESOLVENT, K)
+
+    def closed(own, other):
+        return c[0] + sum(c[2 * m] * s ** (2 * m) * own * (own * other) ** (m - 1)
+                          for m in range(1, K // 2 + 1))
+    want = np.array([closed(q, p)] * p + [closed(p, q)] * q)
+    rows = np.array([0, 1, 2, 3, 4, 19000], dtype=np.int32)
+    with graph(csr) as g:
+        d = gpu_diag(g, "resolvent", 32, K, s)["d"]
+        ds = gpu_diag(g, "resolvent", 32, K, s, rows=rows)["d"]
+    assert_close(d, want, 1e-12, what="K_pq diag")
+    assert_close(ds, want[rows], 1e-12, what="K_pq subset")
+
+
+@pytest.fixture(scope="module")
+def rmat20():
+    csr = G.rmat(20, edge_factor=16, seed=0)
+    lam = G.lambda_max(csr, 50)
+    return csr, lam
+
+
+def _sample_rows(csr, seed):
+    deg = csr.deg
+    rng = np.random.default_rng(seed)
+    small = np.nonzero((deg > 0) & (deg <= 200))[0]
+    mid = np.nonzero((deg > 2048) & (deg <= 4000))[0]
+    rows = list(rng.choice(small, 14, replace=False))
+    if mid.size:
+        rows.append(int(rng.choice(mid)))
+    iso = np.nonzero(deg == 0)[0]
+    rows.append(int(iso[0]))
+    return np.array(rows, dtype=np.int32)
+
+
+@pytest.mark.parametrize("fn", ["exp", "resolvent"])
+def test_rmat20_bench_configuration(rmat20, fn):
+    csr, lam = rmat20
+    K, N = 40, 256
+    scale = 1.0 / csr.d_max if fn == "exp" else 0.85 / lam
+    rows = _sample_rows(csr, seed=5 if fn == "exp" else 6)
+    with graph(csr) as g:
+        ra = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, want_digest=True, stats=True)
+        rd = gpu_diag(g, fn, N, K, scale, seed=1, want_digest=True, stats=True)
+    active = int(np.count_nonzero(csr.deg))
+    assert ra["stats"]["walk_steps"] == active * N * (K - 1)
+    assert rd["stats"]["walk_steps"] == active * N * (K - 1)
+    ofn = oracle.FN_EXP if fn == "exp" else oracle.FN_RESOLVENT
+    oa = oracle.action(csr, ofn, np.ones(csr.n), N=N, K=K, scale=scale, seed=1, rows=rows,
+                       want_digest=True)
+    od = oracle.diag(csr, ofn, N=N, K=K, scale=scale, seed=1, rows=rows, assume_symmetric=True,
+                     want_digest=True)
+    started = oa["digest"] != 0
+    assert np.array_equal(ra["digest"][started], oa["digest"][started])
+    started = od["digest"] != 0
+    assert np.array_equal(rd["digest"][started], od["digest"][started])
+    assert_close(ra["y"][rows], oa["y"], 1e-10, what="action sample")
+    assert_close(rd["d"][rows], od["d"], 1e-10, what="diag sample")
+    # Every term of the series is non-negative here: x >= h = c0 v + c1 s A v.
+    c = oracle.coeffs(ofn, K)
+    h_action = c[0] + c[1] * scale * csr.deg
+    assert np.all(np.isfinite(ra["y"])) and np.all(ra["y"] >= h_action * (1 - 1e-15))
+    assert np.all(np.isfinite(rd["d"])) and np.all(rd["d"] >= c[0])

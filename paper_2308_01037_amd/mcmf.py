@@ -200,11 +200,18 @@ def mcmf_graph_info(g: int) -> dict:
     return dict(zip(("n", "nnz", "d_max", "active_rows"), (v.value for v in vals)))
 
 
+_EMPTY_ROWS = ctypes.c_int32(0)
+
+
 def mcmf_diag(g: int, f: mcmf_fn, rows, n_rows: int, n_walks: int, K: int,
               opts: Optional[mcmf_opts], out, stats: Optional[mcmf_stats] = None) -> None:
     _check_dtype(rows, np.int32, "rows")
     _check_dtype(out, np.float64, "out")
-    _raise(_lib.mcmf_diag(g, ctypes.byref(f), _addr(rows), n_rows, n_walks, K,
+    rows_addr = _addr(rows)
+    if rows is not None and not rows_addr:
+        # An empty array may have no storage; NULL would mean "every row".
+        rows_addr = ctypes.addressof(_EMPTY_ROWS)
+    _raise(_lib.mcmf_diag(g, ctypes.byref(f), rows_addr, n_rows, n_walks, K,
                           ctypes.byref(opts) if opts is not None else None, _addr(out),
                           ctypes.byref(stats) if stats is not None else None))
 

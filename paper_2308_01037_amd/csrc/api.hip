@@ -329,9 +329,9 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     DevBuf<uint8_t> in_set, start_flags;
     DevBuf<int32_t> start_list;
     DevBuf<int> bad;
-    DevBuf<unsigned long long> counters; // steps, probes
-    MCMF_TRY(counters.alloc(2, s));
-    MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, 2, s));
+    DevBuf<unsigned long long> counters; // steps, probes, table overflows
+    MCMF_TRY(counters.alloc(3, s));
+    MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, 3, s));
     if (digest) {
         MCMF_TRY(dig.out(digest, n, s));
         MCMF_TRY(fill_u64(dig.ptr, 0, n, s));
@@ -407,7 +407,8 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
             if (stats)
                 MCMF_HIP(hipEventRecord(chunk_events[2 * ci + 1], s));
             MCMF_TRY(diag_gather(g, starts + c0, rows_here, p, vstate.ptr, vx.ptr,
-                                 all ? nullptr : in_set.ptr, dacc.ptr, counters.ptr + 1, s));
+                                 all ? nullptr : in_set.ptr, dacc.ptr, counters.ptr + 1,
+                                 counters.ptr + 2, s));
         }
         if (stats)
             MCMF_HIP(hipEventRecord(chunk_events.back(), s));
@@ -423,12 +424,14 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     MCMF_TRY(dout.copy_back(out, count, s));
     if (digest)
         MCMF_TRY(dig.copy_back(digest, n, s));
-    unsigned long long hc[2] = {0, 0};
-    if (stats)
-        MCMF_HIP(hipMemcpyAsync(hc, counters.ptr, sizeof hc, hipMemcpyDeviceToHost, s));
+    unsigned long long hc[3] = {0, 0, 0};
     const bool sync = !(o && o->stream) || stats || dout.host || (digest && dig.host) || rv.host;
     if (sync)
+        MCMF_HIP(hipMemcpyAsync(hc, counters.ptr, sizeof hc, hipMemcpyDeviceToHost, s));
+    if (sync)
         MCMF_HIP(hipStreamSynchronize(s));
+    if (hc[2] != 0)
+        return fail(MCMF_E_DEVICE, "internal error: a Q_k table overflowed (%llu inserts lost)", hc[2]);
     if (stats) {
         for (size_t e = 0; e + 1 < chunk_events.size(); ++e) {
             float t = 0.f;

@@ -1,19 +1,22 @@
 // RandFunmDiag gather (Section 3.3, Eq. rand_funm_formula_diag): one
-// workgroup per start row k.
+// 1024-thread workgroup per start row k.
 //
-//  1. Q_k is built in LDS from the row's visit records: an open-addressing
-//     hash table (keys int32, values FP64, linear probing, LDS atomics)
-//     plus a one-bit-per-bucket filter that answers most misses with a
-//     single LDS read.
-//  2. For every requested row i adjacent to k, the column C_i (= row i, A is
-//     symmetric) is streamed from memory and probed against Q_k:
-//         dacc[i] += s a_ki * s <Q_k, C_i> / N      (FP64 atomic add)
-//     Rows up to kBigRow entries go one per wavefront; longer rows are
-//     streamed by the whole workgroup.
+//  1. Q_k is built in LDS from the row's visit records: open addressing over
+//     8-slot buckets (keys int32, values FP64, LDS atomics on insert) and a
+//     blocked three-bit filter that rejects most absent keys with one LDS
+//     read.  A lookup reads a whole bucket (two 16-byte reads) per step.
+//  2. The columns C_i (= row i, A is symmetric) of the requested neighbours i
+//     of k, 256 neighbours at a time, are cut into chunks of kChunk entries.
+//     A group of 16 lanes takes one chunk (8 entries per lane, coalesced, all
+//     loads in flight together), probes Q_k for each entry, sums over the
+//     group and adds the sum into the neighbour's LDS total; after the batch
+//     each neighbour's total goes out with one FP64 atomic:
+//         dacc[i] += s a_ki * s <Q_k, C_i> / N.
 //  When the row's visits cannot fit the table at once, the walks are taken
 //  in passes (Q_k is linear in the walks) and the gather repeats per pass.
 #include "device.hpp"
 #include "ops.hpp"
+#include "plan.hpp"
 
 namespace mcmf {
 
@@ -21,53 +24,129 @@ namespace {
 
 constexpr int kGatherThreads = 1024;
 constexpr int kWaves = kGatherThreads / 64;
-constexpr uint32_t kFilterLog2 = 16; // 65536 filter bits = 8 KiB
-constexpr uint32_t kFilterWords = (1u << kFilterLog2) / 32;
-constexpr uint32_t kBigRow = 2048;
-constexpr uint32_t kBigQueue = 1024; // long rows queued per start row and pass
+constexpr uint32_t kFilterLog2Words = 11; // 2048 words = 8 KiB
+constexpr uint32_t kFilterWords = 1u << kFilterLog2Words;
+constexpr int kBatch = 256;                // neighbours per batch
+constexpr int kGroup = 16;                 // lanes per chunk
+constexpr int kPerLane = 8;                // entries per lane per chunk
+constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
+constexpr int kGroups = kGatherThreads / kGroup;
+constexpr int kSlots = 8;                  // slots per bucket
 constexpr int32_t kEmpty = -1;
 
-__device__ __forceinline__ uint32_t slot_of(int32_t key, uint32_t cap) {
-    const uint32_t h = static_cast<uint32_t>(key) * 0x9E3779B1u;
-    return __umulhi(h, cap);
-}
-
-__device__ __forceinline__ uint32_t filter_bit(int32_t key) {
-    return (static_cast<uint32_t>(key) * 0x85EBCA77u) >> (32 - kFilterLog2);
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // Multiply-xorshift integer hash (the finaliser of MurmurHash3).
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
 }
 
 struct Table {
-    int32_t *keys;
+    int32_t *keys; // nb buckets x kSlots slots, 32-byte aligned
     double *vals;
     uint32_t *filter;
-    uint32_t cap;
+    uint32_t nb;
 
-    __device__ void insert(int32_t key, double x) {
-        const uint32_t fb = filter_bit(key);
-        atomicOr(&filter[fb >> 5], 1u << (fb & 31));
-        uint32_t s = slot_of(key, cap);
-        while (true) {
-            const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
-            if (prev == kEmpty || prev == key) {
-                atomicAdd(&vals[s], x);
-                return;
-            }
-            s = (s + 1 == cap) ? 0 : s + 1;
-        }
+    // Multiplicative hashing: node ids of the graphs here carry no structure
+    // that a multiply-shift hash would keep.
+    __device__ __forceinline__ uint32_t bucket_of(int32_t key) const {
+        return __umulhi(static_cast<uint32_t>(key) * 0x85EBCA77u, nb);
+    }
+    __device__ __forceinline__ static uint32_t fhash(int32_t key) {
+        return static_cast<uint32_t>(key) * 0x9E3779B1u;
+    }
+    // Top bits pick the filter word, three 5-bit fields below them the bits.
+    __device__ __forceinline__ static uint32_t filter_word(uint32_t h) {
+        return h >> (32 - kFilterLog2Words);
+    }
+    __device__ __forceinline__ static uint32_t filter_mask(uint32_t h) {
+        return (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31)) | (1u << (h & 31));
     }
 
-    __device__ double lookup(int32_t key) const {
-        const uint32_t fb = filter_bit(key);
-        if (!((filter[fb >> 5] >> (fb & 31)) & 1u))
-            return 0.0;
-        uint32_t s = slot_of(key, cap);
-        while (true) {
-            const int32_t kv = keys[s];
-            if (kv == key)
-                return vals[s];
-            if (kv == kEmpty)
-                return 0.0;
-            s = (s + 1 == cap) ? 0 : s + 1;
+    // Returns false only if every bucket is full (the plan rules that out).
+    __device__ bool insert(int32_t key, double x) {
+        const uint32_t h = fhash(key);
+        atomicOr(&filter[filter_word(h)], filter_mask(h));
+        uint32_t b = bucket_of(key);
+        for (uint32_t tries = 0; tries < nb; ++tries) {
+#pragma unroll
+            for (int j = 0; j < kSlots; ++j) {
+                const uint32_t s = kSlots * b + j;
+                const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
+                if (prev == kEmpty || prev == key) {
+                    atomicAdd(&vals[s], x);
+                    return true;
+                }
+            }
+            b = (b + 1 == nb) ? 0 : b + 1;
+        }
+        return false;
+    }
+
+    // Value of key in bucket b, or: 0 with *more = false when the key is absent
+    // (an empty slot ends the probe sequence), *more = true when the bucket is
+    // full without it (continue with the next bucket).
+    __device__ __forceinline__ double probe_bucket(int32_t key, uint32_t b, bool *more) const {
+        const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
+        const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
+        int j = -1;
+        j = (lo.x == key) ? 0 : j;
+        j = (lo.y == key) ? 1 : j;
+        j = (lo.z == key) ? 2 : j;
+        j = (lo.w == key) ? 3 : j;
+        j = (hi.x == key) ? 4 : j;
+        j = (hi.y == key) ? 5 : j;
+        j = (hi.z == key) ? 6 : j;
+        j = (hi.w == key) ? 7 : j;
+        *more = false;
+        if (j >= 0)
+            return vals[kSlots * b + j];
+        *more = hi.w != kEmpty; // slots fill in order: the last one is the test
+        return 0.0;
+    }
+
+    // Lookup of N keys stage by stage so that their LDS reads overlap: filter
+    // words, then home buckets, then the rare keys that need further buckets.
+    // key < 0 means "no key" (result 0).
+    template <int N>
+    __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
+        uint32_t fw[N], m[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const uint32_t h = fhash(key[u]);
+            m[u] = filter_mask(h);
+            fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
+        }
+        uint32_t pending = 0;
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            out[u] = 0.0;
+            if ((fw[u] & m[u]) == m[u] && key[u] >= 0) {
+                bool more;
+                out[u] = probe_bucket(key[u], bucket_of(key[u]), &more);
+                pending |= more ? (1u << u) : 0u;
+            }
+        }
+        while (pending) {
+            const int u = __ffs(pending) - 1;
+            pending &= pending - 1;
+            int32_t kx = key[0];
+#pragma unroll
+            for (int v = 1; v < N; ++v)
+                kx = (v == u) ? key[v] : kx;
+            uint32_t b = bucket_of(kx);
+            double r = 0.0;
+            bool more = true;
+            for (uint32_t tries = 1; more && tries < nb; ++tries) {
+                b = (b + 1 == nb) ? 0 : b + 1;
+                r = probe_bucket(kx, b, &more);
+            }
+#pragma unroll
+            for (int v = 0; v < N; ++v)
+                out[v] = (v == u) ? r : out[v];
         }
     }
 };
@@ -85,38 +164,34 @@ struct GatherArgs {
     const double *vx;
     const uint8_t *in_set; // null: every row requested
     double scale;
-    uint32_t cap;
+    uint32_t nb; // buckets
     double *dacc;
     unsigned long long *probes;
+    unsigned long long *overflow; // set if a table ever fills (a planning error)
 };
 
-template <bool WEIGHTED>
-__device__ __forceinline__ double probe_row(const Table &tab, const GatherArgs &a, uint2 ri,
-                                            uint32_t first, uint32_t stride) {
-    double sum = 0.0;
-    for (uint32_t e = first; e < ri.y; e += stride) {
-        const int64_t idx = int64_t(ri.x) + e;
-        const double qv = tab.lookup(a.col[idx]);
-        sum += WEIGHTED ? a.val[idx] * qv : qv;
-    }
-    return sum;
-}
+// Per-batch neighbour metadata in LDS.
+struct Batch {
+    uint32_t prefix[kBatch + 1]; // first chunk of each neighbour's column
+    uint32_t start[kBatch];      // first entry of the column in col[]
+    uint32_t len[kBatch];        // column length
+    int32_t row[kBatch];         // neighbour i (-1: not requested)
+    double aki[kBatch];          // s * a_ki
+    double sum[kBatch];          // <Q_k, C_i> partial sums
+};
 
 template <bool WEIGHTED>
 __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[kWaves];
-    __shared__ uint32_t big_queue[kBigQueue];
-    __shared__ uint32_t big_count_s;
-    uint32_t *big_count = &big_count_s;
+    __shared__ Batch bt;
+    __shared__ uint32_t scan_scratch[kWaves];
+    __shared__ unsigned long long red[kWaves];
     Table tab;
-    tab.cap = a.cap;
+    tab.nb = a.nb;
+    const uint32_t cap = kSlots * a.nb;
     tab.vals = reinterpret_cast<double *>(smem);
-    tab.keys = reinterpret_cast<int32_t *>(smem + sizeof(double) * a.cap);
-    tab.filter = reinterpret_cast<uint32_t *>(smem + sizeof(double) * a.cap +
-                                              sizeof(int32_t) * ((a.cap + 3) & ~3u));
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    tab.keys = reinterpret_cast<int32_t *>(smem + sizeof(double) * cap);
+    tab.filter = reinterpret_cast<uint32_t *>(smem + sizeof(double) * cap + sizeof(int32_t) * cap);
     const int64_t span = int64_t(a.K - 1) * a.N;
     const double inv_n = 1.0 / static_cast<double>(a.N);
     unsigned long long probes = 0;
@@ -130,79 +205,105 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
             const int64_t nw = (a.N - w0 < a.walks_per_pass) ? (a.N - w0) : a.walks_per_pass;
             // (1) Q_k from walks [w0, w0 + nw).
             __syncthreads();
-            for (uint32_t i = threadIdx.x; i < a.cap; i += blockDim.x) {
+            for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
                 tab.keys[i] = kEmpty;
                 tab.vals[i] = 0.0;
             }
             for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
                 tab.filter[i] = 0u;
-            if (threadIdx.x == 0)
-                *big_count = 0u;
             __syncthreads();
             const int64_t count = nw * (a.K - 1);
             if (nw == a.N) {
                 for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
                     const int32_t s = st[i];
-                    if (s >= 0)
-                        tab.insert(s, xs[i]);
+                    if (s >= 0 && !tab.insert(s, xs[i]))
+                        atomicAdd(a.overflow, 1ull);
                 }
             } else {
                 for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
                     const int64_t t = i / nw;
                     const int64_t slot = t * a.N + w0 + (i - t * nw);
                     const int32_t s = st[slot];
-                    if (s >= 0)
-                        tab.insert(s, xs[slot]);
+                    if (s >= 0 && !tab.insert(s, xs[slot]))
+                        atomicAdd(a.overflow, 1ull);
                 }
             }
-            __syncthreads();
-            // (2a) requested neighbours with short rows: one wavefront each.
-            //      Long rows are queued for (2b); a full queue makes the
-            //      wavefront take the row itself.
-            for (uint32_t p = wave; p < rk.y; p += kWaves) {
-                const int64_t e = int64_t(rk.x) + p;
-                const int32_t i = a.col[e];
-                if (a.in_set && !a.in_set[i])
-                    continue;
-                const uint2 ri = a.node[i];
-                if (ri.y > kBigRow) {
-                    uint32_t pos = 0;
-                    if (lane == 0)
-                        pos = atomicAdd(big_count, 1u);
-                    pos = __shfl(pos, 0, 64);
-                    if (pos < kBigQueue) {
-                        if (lane == 0)
-                            big_queue[pos] = p;
-                        continue;
+            // (2) columns of the requested neighbours, kBatch neighbours at a time.
+            for (uint32_t p0 = 0; p0 < rk.y; p0 += kBatch) {
+                const uint32_t m = (rk.y - p0 < uint32_t(kBatch)) ? rk.y - p0 : uint32_t(kBatch);
+                __syncthreads(); // table complete / previous batch flushed
+                uint32_t nchunks = 0;
+                if (threadIdx.x < kBatch) {
+                    const int t = threadIdx.x;
+                    bt.sum[t] = 0.0;
+                    bt.row[t] = -1;
+                    bt.len[t] = 0;
+                    if (uint32_t(t) < m) {
+                        const int64_t e = int64_t(rk.x) + p0 + t;
+                        const int32_t i = a.col[e];
+                        if (!a.in_set || a.in_set[i]) {
+                            const uint2 ri = a.node[i];
+                            nchunks = (ri.y + kChunk - 1) / kChunk;
+                            bt.start[t] = ri.x;
+                            bt.len[t] = ri.y;
+                            bt.row[t] = i;
+                            bt.aki[t] = a.scale * (WEIGHTED ? a.val[e] : 1.0);
+                        }
                     }
                 }
-                const double sum = dev::wave_sum(probe_row<WEIGHTED>(tab, a, ri, lane, 64));
-                probes += lane == 0 ? ri.y : 0;
-                if (lane == 0) {
-                    const double aki = WEIGHTED ? a.val[e] : 1.0;
-                    atomicAdd(&a.dacc[i], (a.scale * aki) * (a.scale * sum) * inv_n);
+                uint32_t total = 0;
+                const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
+                if (threadIdx.x < kBatch)
+                    bt.prefix[threadIdx.x] = before;
+                if (threadIdx.x == 0)
+                    bt.prefix[kBatch] = total;
+                __syncthreads();
+                // Chunks to groups of kGroup lanes.
+                const int group = threadIdx.x / kGroup;
+                const int gl = threadIdx.x % kGroup;
+                for (uint32_t c = group; c < total; c += kGroups) {
+                    // Neighbour owning chunk c: last r with prefix[r] <= c (the
+                    // search is uniform across the group).
+                    int lo = 0, hi = kBatch;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (bt.prefix[mid] <= c)
+                            lo = mid;
+                        else
+                            hi = mid;
+                    }
+                    const uint32_t first = (c - bt.prefix[lo]) * kChunk + gl;
+                    const uint32_t len = bt.len[lo];
+                    const int64_t base = int64_t(bt.start[lo]);
+                    int32_t key[kPerLane];
+                    double wv[kPerLane];
+#pragma unroll
+                    for (int u = 0; u < kPerLane; ++u) {
+                        const uint32_t off = first + u * kGroup;
+                        key[u] = off < len ? a.col[base + off] : -1;
+                        wv[u] = (WEIGHTED && off < len) ? a.val[base + off] : 1.0;
+                        probes += off < len ? 1 : 0;
+                    }
+                    double qv[kPerLane];
+                    tab.lookup_n<kPerLane>(key, qv);
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < kPerLane; ++u)
+                        acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
+                    acc = dev::group_sum<kGroup>(acc);
+                    if (gl == 0 && acc != 0.0)
+                        atomicAdd(&bt.sum[lo], acc);
                 }
-            }
-            __syncthreads();
-            // (2b) queued long rows: the whole workgroup streams each one.
-            const uint32_t nbig = *big_count < kBigQueue ? *big_count : kBigQueue;
-            for (uint32_t b = 0; b < nbig; ++b) {
-                const uint32_t p = big_queue[b];
-                const int64_t e = int64_t(rk.x) + p;
-                const int32_t i = a.col[e];
-                const uint2 ri = a.node[i];
-                const double part = probe_row<WEIGHTED>(tab, a, ri, threadIdx.x, blockDim.x);
-                const double sum = dev::block_sum(part, red);
-                if (threadIdx.x == 0) {
-                    probes += ri.y;
-                    const double aki = WEIGHTED ? a.val[e] : 1.0;
-                    atomicAdd(&a.dacc[i], (a.scale * aki) * (a.scale * sum) * inv_n);
+                __syncthreads();
+                if (threadIdx.x < m && bt.row[threadIdx.x] >= 0) {
+                    const int t = threadIdx.x;
+                    atomicAdd(&a.dacc[bt.row[t]], bt.aki[t] * (a.scale * bt.sum[t]) * inv_n);
                 }
             }
         }
     }
     if (a.probes) {
-        const unsigned long long total = dev::block_sum(probes, reinterpret_cast<unsigned long long *>(red));
+        const unsigned long long total = dev::block_sum(probes, red);
         if (threadIdx.x == 0)
             atomicAdd(a.probes, total);
     }
@@ -210,40 +311,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
 
 } // namespace
 
-// Table capacity and walks per pass for a row with N walks of K-1 visits.
-void gather_plan(int64_t n, int64_t N, int K, uint32_t *cap, int64_t *walks_per_pass,
-                 size_t *lds_bytes) {
-    const size_t lds_max = 160 * 1024;
-    const size_t fixed = sizeof(uint32_t) * kFilterWords + sizeof(double) * kWaves +
-                         sizeof(uint32_t) * (kBigQueue + 1) + 256;
-    const uint32_t cap_max = static_cast<uint32_t>(((lds_max - fixed) / 12) & ~63u);
-    const int64_t visits = N * (K - 1);
-    int64_t distinct = visits < n ? visits : n;
-    int64_t wpp = N;
-    // Load factor at most 0.8 in the worst case (every visit distinct).
-    if (distinct * 5 > int64_t(cap_max) * 4) {
-        wpp = (int64_t(cap_max) * 4 / 5) / (K - 1);
-        if (wpp < 1)
-            wpp = 1;
-        if (n * 5 <= int64_t(cap_max) * 4)
-            wpp = N; // few nodes: the table holds them all whatever the walk count
-        const int64_t v = wpp * (K - 1);
-        distinct = v < n ? v : n;
-    }
-    uint32_t c = static_cast<uint32_t>((distinct * 5 + 3) / 4 + 1);
-    c = (c + 63) & ~63u;
-    if (c < 64)
-        c = 64;
-    if (c > cap_max)
-        c = cap_max;
-    *cap = c;
-    *walks_per_pass = wpp;
-    *lds_bytes = sizeof(double) * c + sizeof(int32_t) * ((c + 3) & ~3u) + sizeof(uint32_t) * kFilterWords;
-}
-
 Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
                    const int32_t *state, const double *x, const uint8_t *in_set, double *dacc,
-                   unsigned long long *probes, hipStream_t s) {
+                   unsigned long long *probes, unsigned long long *overflow, hipStream_t s) {
     if (n_start <= 0 || p.K < 2)
         return {};
     GatherArgs a = {};
@@ -260,8 +330,17 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
     a.scale = p.scale;
     a.dacc = dacc;
     a.probes = probes;
-    size_t lds = 0;
-    gather_plan(g->n, p.n_walks, p.K, &a.cap, &a.walks_per_pass, &lds);
+    const size_t static_lds = sizeof(Batch) + sizeof(uint32_t) * kWaves +
+                              sizeof(unsigned long long) * kWaves + 512;
+    const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - static_lds,
+                                        sizeof(uint32_t) * kFilterWords, kSlots);
+    if (!plan.ok)
+        return fail(MCMF_E_UNSUPPORTED, "no Q_k table layout fits LDS for N=%lld, K=%d",
+                    static_cast<long long>(p.n_walks), p.K);
+    a.nb = static_cast<uint32_t>(plan.cap / kSlots);
+    a.walks_per_pass = plan.walks_per_pass;
+    a.overflow = overflow;
+    const size_t lds = plan.lds_bytes;
     const int64_t cap_blocks = int64_t(1) << 20;
     const dim3 grid(static_cast<uint32_t>(n_start < cap_blocks ? n_start : cap_blocks));
     if (g->weighted) {

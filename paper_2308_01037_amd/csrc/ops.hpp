@@ -58,6 +58,6 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
 // in_set == null means every row is requested.
 Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
                    const int32_t *state, const double *x, const uint8_t *in_set, double *dacc,
-                   unsigned long long *probes, hipStream_t s);
+                   unsigned long long *probes, unsigned long long *overflow, hipStream_t s);
 
 } // namespace mcmf

@@ -1,5 +1,5 @@
 // RandFunmAction (Section 3.4, Algorithm 3):
-//   r = s A v                         (one sparse product, into the row records)
+//   r = s A v                         (one sparse product)
 //   q_k from the walks                (walk.hip)
 //   y = c0 v + c1 r + s A q            (one sparse product, Eq. rand_funm_action_formula)
 //
@@ -43,11 +43,11 @@ struct SpmvArgs {
     int64_t count;
     const double *x;     // v (records) or q (assemble)
     double scale;
-    // Records
-    ActionNode *rec;
+    // Records: r out
+    double *rout;
     // Assemble
     const double *v;
-    const ActionNode *rin;
+    const double *rin;
     double c0, c1;
     double *y;
 };
@@ -55,13 +55,9 @@ struct SpmvArgs {
 template <Out OUT>
 __device__ __forceinline__ void emit(const SpmvArgs &a, int32_t i, uint2 nd, double dot) {
     if (OUT == Out::Records) {
-        ActionNode r;
-        r.start = nd.x;
-        r.deg = nd.y;
-        r.r = a.scale * dot;
-        a.rec[i] = r;
+        a.rout[i] = a.scale * dot;
     } else {
-        double yi = a.c0 * a.v[i] + a.c1 * a.rin[i].r;
+        double yi = a.c0 * a.v[i] + a.c1 * a.rin[i];
         if (a.x)
             yi += a.scale * dot;
         a.y[i] = yi;
@@ -149,16 +145,15 @@ Status launch_spmv(const mcmf_graph *g, SpmvArgs a, hipStream_t s) {
 
 } // namespace
 
-Status spmv_records(const mcmf_graph *g, const double *v, double scale, ActionNode *rec,
-                    hipStream_t s) {
+Status spmv_r(const mcmf_graph *g, const double *v, double scale, double *r, hipStream_t s) {
     SpmvArgs a = {};
     a.x = v;
     a.scale = scale;
-    a.rec = rec;
+    a.rout = r;
     return launch_spmv<Out::Records>(g, a, s);
 }
 
-Status spmv_assemble(const mcmf_graph *g, const double *v, const ActionNode *rec, const double *q,
+Status spmv_assemble(const mcmf_graph *g, const double *v, const double *rec, const double *q,
                      double c0, double c1, double scale, double *y, hipStream_t s) {
     SpmvArgs a = {};
     a.x = q;

@@ -227,7 +227,7 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
     View<uint64_t> dig;
     MCMF_TRY(vin.in(v, n, s));
     MCMF_TRY(yout.out(out, n, s));
-    DevBuf<ActionNode> rec;
+    DevBuf<double> rec; // r = s A v
     DevBuf<double> q, coef;
     DevBuf<unsigned long long> steps;
     MCMF_TRY(rec.alloc(n > 0 ? n : 1, s));
@@ -251,7 +251,7 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
         MCMF_TRY(fill_u64(dig.ptr, 0, n, s));
     }
     MCMF_TRY(tm.mark(1));
-    MCMF_TRY(spmv_records(g, vin.ptr, f->scale, rec.ptr, s));
+    MCMF_TRY(spmv_r(g, vin.ptr, f->scale, rec.ptr, s));
     MCMF_TRY(tm.mark(2));
     if (K >= 2) {
         const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);

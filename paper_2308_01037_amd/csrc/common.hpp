@@ -109,6 +109,10 @@ struct mcmf_graph {
     double *cum = nullptr;      // [nnz] running sums of |a| per row (weighted only)
     double *diagval = nullptr;  // [n] a_ii (only when the graph has loops)
     uint2 *node = nullptr;      // [n] {first entry, row length}
+    // [nnz] per stored entry a_ij: {j, first entry of row j, length of row j, 0}.
+    // A walk step then needs one dependent load: the entry it picks already
+    // carries the record of the row it moves to.
+    uint4 *edge = nullptr;
     int32_t *active = nullptr;  // [n_active] rows with entries, ascending
     // Rows grouped by length for the sparse products: short (<= 64 entries,
     // including empty rows), medium (<= 4096), long.

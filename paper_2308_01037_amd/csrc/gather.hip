@@ -108,41 +108,73 @@ struct Table {
         return 0.0;
     }
 
-    // Lookup of N keys stage by stage so that their LDS reads overlap: filter
-    // words, then home buckets, then the rare keys that need further buckets.
-    // key < 0 means "no key" (result 0).
+    // Lookup of N keys stage by stage so that their LDS reads overlap: all
+    // filter words, then all home buckets, then all values, then the rare
+    // keys that need further buckets.  key < 0 means "no key" (result 0).
     template <int N>
     __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
-        uint32_t fw[N], m[N];
+        uint32_t fw[N], m[N], b[N];
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const uint32_t h = fhash(key[u]);
             m[u] = filter_mask(h);
+            b[u] = bucket_of(key[u]);
             fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
         }
+        // Every lane issues its reads; lanes without a candidate read bucket 0,
+        // a single address the LDS serves as a broadcast.  Unconditional reads
+        // keep all N requests in flight together.
+        bool cand[N];
+        int4 lo[N], hi[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            cand[u] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
+            const uint32_t off = cand[u] ? kSlots * b[u] : 0u;
+            lo[u] = *reinterpret_cast<const int4 *>(keys + off);
+            hi[u] = *reinterpret_cast<const int4 *>(keys + off + 4);
+        }
+        int slot[N];
         uint32_t pending = 0;
 #pragma unroll
         for (int u = 0; u < N; ++u) {
-            out[u] = 0.0;
-            if ((fw[u] & m[u]) == m[u] && key[u] >= 0) {
-                bool more;
-                out[u] = probe_bucket(key[u], bucket_of(key[u]), &more);
-                pending |= more ? (1u << u) : 0u;
+            int j = -1;
+            if (cand[u]) {
+                const int32_t k = key[u];
+                j = (lo[u].x == k) ? 0 : j;
+                j = (lo[u].y == k) ? 1 : j;
+                j = (lo[u].z == k) ? 2 : j;
+                j = (lo[u].w == k) ? 3 : j;
+                j = (hi[u].x == k) ? 4 : j;
+                j = (hi[u].y == k) ? 5 : j;
+                j = (hi[u].z == k) ? 6 : j;
+                j = (hi[u].w == k) ? 7 : j;
+                // Slots fill in order, so a full bucket ends with a used last slot.
+                pending |= (j < 0 && hi[u].w != kEmpty) ? (1u << u) : 0u;
             }
+            slot[u] = j;
         }
+        double got[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+            got[u] = vals[slot[u] >= 0 ? kSlots * b[u] + slot[u] : 0u];
+#pragma unroll
+        for (int u = 0; u < N; ++u)
+            out[u] = slot[u] >= 0 ? got[u] : 0.0;
         while (pending) {
             const int u = __ffs(pending) - 1;
             pending &= pending - 1;
             int32_t kx = key[0];
+            uint32_t bx = b[0];
 #pragma unroll
-            for (int v = 1; v < N; ++v)
+            for (int v = 1; v < N; ++v) {
                 kx = (v == u) ? key[v] : kx;
-            uint32_t b = bucket_of(kx);
+                bx = (v == u) ? b[v] : bx;
+            }
             double r = 0.0;
             bool more = true;
             for (uint32_t tries = 1; more && tries < nb; ++tries) {
-                b = (b + 1 == nb) ? 0 : b + 1;
-                r = probe_bucket(kx, b, &more);
+                bx = (bx + 1 == nb) ? 0 : bx + 1;
+                r = probe_bucket(kx, bx, &more);
             }
 #pragma unroll
             for (int v = 0; v < N; ++v)

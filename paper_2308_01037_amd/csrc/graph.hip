@@ -169,6 +169,16 @@ __global__ void k_graph_meta(const int64_t *row_ptr, int64_t n, const double *va
         atomicMax(dmax, local_max);
 }
 
+// edge[e] = {col[e], record of row col[e]} for every stored entry.
+__global__ void k_build_edges(const int32_t *col, int64_t nnz, const uint2 *node, uint4 *edge) {
+    for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nnz;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t j = col[e];
+        const uint2 rj = node[j];
+        edge[e] = make_uint4(static_cast<uint32_t>(j), rj.x, rj.y, 0u);
+    }
+}
+
 // a_ji == a_ij for every stored a_ij (rows sorted): one wavefront per row,
 // each lane binary-searches row j for i.
 __global__ __launch_bounds__(kThreads) void k_check_symmetric(const uint2 *node, int64_t n,
@@ -234,6 +244,7 @@ void free_graph(mcmf_graph *g) {
     dev_free_sync(g->rowabs, sizeof(double) * g->n);
     dev_free_sync(g->cum, sizeof(double) * g->nnz);
     dev_free_sync(g->node, sizeof(uint2) * g->n);
+    dev_free_sync(g->edge, sizeof(uint4) * g->nnz);
     dev_free_sync(g->active, sizeof(int32_t) * g->n_active);
     dev_free_sync(g->bin_rows, sizeof(int32_t) * g->n);
     if (g->stream)
@@ -283,6 +294,7 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
         MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->rowabs), sizeof(double) * n));
     }
     MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->node), sizeof(uint2) * n));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->edge), sizeof(uint4) * nnz));
     MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->bin_rows), sizeof(int32_t) * n));
 
     MCMF_TRY(copy_in(d_rp.ptr, row_ptr, sizeof(int64_t) * (n + 1), m_rp, s));
@@ -323,6 +335,11 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
                            g->val, g->node, d_active.ptr, d_bin.ptr, g->rowabs, g->cum, d_dmax.ptr);
         MCMF_HIP(hipGetLastError());
     }
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_build_edges, dim3(grid_for(nnz)), dim3(kThreads), 0, s, g->col, nnz,
+                           g->node, g->edge);
+        MCMF_HIP(hipGetLastError());
+    }
     if (check_sym && n > 0) {
         hipLaunchKernelGGL(k_check_symmetric, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, g->node,
                            n, g->col, g->val, d_err.ptr);
@@ -351,7 +368,7 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
         off += g->bin_count[b];
     }
     MCMF_HIP(hipStreamSynchronize(s));
-    g->bytes = sizeof(int32_t) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
+    g->bytes = (sizeof(int32_t) + sizeof(uint4)) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
                (g->weighted ? sizeof(double) * (2 * nnz + n) : 0);
     return {};
 }

@@ -28,24 +28,16 @@ struct WalkParams {
     int precision; // MCMF_PRECISION_*
 };
 
-// Packed per-row record the action walk reads in one 16-byte load.
-struct alignas(16) ActionNode {
-    uint32_t start; // first entry of the row
-    uint32_t deg;   // row length
-    double r;       // (sA v)_row
-};
-
-// r = s A v into the records (every row gets start/deg/r).
-Status spmv_records(const mcmf_graph *g, const double *v, double scale, ActionNode *rec,
-                    hipStream_t s);
+// r = s A v.
+Status spmv_r(const mcmf_graph *g, const double *v, double scale, double *r, hipStream_t s);
 // y = c0 v + c1 r + s A q (q may be null when K < 2: then only c0 v + c1 r).
-Status spmv_assemble(const mcmf_graph *g, const double *v, const ActionNode *rec, const double *q,
+Status spmv_assemble(const mcmf_graph *g, const double *v, const double *r, const double *q,
                      double c0, double c1, double scale, double *y, hipStream_t s);
 
 // Action walks: q[k] for every k in starts[0..n_start).  digest/steps optional.
-Status action_walks(const mcmf_graph *g, const ActionNode *rec, const int32_t *starts,
-                    int64_t n_start, const WalkParams &p, double *q, uint64_t *digest,
-                    unsigned long long *steps, hipStream_t s);
+Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
+                    const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
+                    hipStream_t s);
 
 // Diag walks for starts[0..n_start): visit records, t-major per start row:
 // state[(kk*(K-1) + t)*N + w], x = c_{t+2} W_t; finished walks store -1.

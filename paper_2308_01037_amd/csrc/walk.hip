@@ -2,14 +2,19 @@
 // Eq. rand_funm_Q for the diagonal).  One workgroup per start row k runs
 // that row's walks; lane w runs walk w (and w + blockDim, ...).
 //
-// A walk keeps its state in registers: the current row l, the weight W and
-// the row record of l.  Per recorded step t it either adds c_{t+2} W r_l to a
-// register sum (action) or writes the visit (l, c_{t+2} W) to the visit
-// buffer (diagonal).  A transition draws Philox4x32-10 at counter
-// (k, w, t, request), picks entry j of row l (floor(u deg / 2^64) for
-// unweighted rows, the inverse running-sum search for weighted rows),
-// multiplies W by s * sum_j |a_lj| (negated for a negative entry) and moves
-// to col[start_l + j].
+// A walk keeps its state in registers: the current row l with its record
+// (first entry, length) and the weight W.  Per recorded step t it either adds
+// c_{t+2} W r_l to a register sum (action) or writes the visit
+// (l, c_{t+2} W) to the visit buffer (diagonal).  A transition draws
+// Philox4x32-10 at counter (k, w, t, request), picks entry j of row l and
+// moves to its column, multiplying W by s * sum_j |a_lj| (negated for a
+// negative entry).
+//
+// Unweighted rows pick j = floor(u deg / 2^64) and read one 16-byte edge
+// record {next row, its first entry, its length}: one dependent load per
+// step.  The transition of step t is issued before step t is recorded, so
+// the record's load overlaps the bookkeeping; the action's r_l load sits off
+// that dependency chain.  Weighted rows search the running sums of |a|.
 #include "device.hpp"
 #include "ops.hpp"
 
@@ -53,141 +58,183 @@ WalkArgs to_args(const WalkParams &p) {
     return a;
 }
 
+struct GraphView {
+    const uint2 *node;
+    const uint4 *edge;
+    const int32_t *col;
+    const double *val;
+    const double *rowabs;
+    const double *cum;
+};
+
+GraphView view(const mcmf_graph *g) {
+    GraphView v;
+    v.node = g->node;
+    v.edge = g->edge;
+    v.col = g->col;
+    v.val = g->val;
+    v.rowabs = g->rowabs;
+    v.cum = g->cum;
+    return v;
+}
+
+// Walk state of one walk: row, its record, weight.
+struct Pos {
+    uint32_t l, start, deg;
+};
+
+// One transition out of row p (deg > 0) with the block of random words x.
+// Updates W (times s * sum |a|, sign of the entry) and returns the new row.
+template <bool WEIGHTED>
+__device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
+                                    double &W) {
+    Pos n;
+    if constexpr (!WEIGHTED) {
+        const uint32_t j = dev::uniform_index(x.x, x.y, p.deg);
+        W = W * (scale * static_cast<double>(p.deg));
+        const uint4 e = g.edge[int64_t(p.start) + j];
+        n.l = e.x;
+        n.start = e.y;
+        n.deg = e.z;
+    } else {
+        const double ra = g.rowabs[p.l];
+        const uint32_t j = cdf_search(g.cum + p.start, p.deg, dev::unit53(x.x, x.y) * ra);
+        W = W * (scale * ra);
+        if (g.val[int64_t(p.start) + j] < 0.0)
+            W = -W;
+        n.l = static_cast<uint32_t>(g.col[int64_t(p.start) + j]);
+        const uint2 r = g.node[n.l];
+        n.start = r.x;
+        n.deg = r.y;
+    }
+    return n;
+}
+
 // Action: q[k] = (1/N) sum_w sum_t c_{t+2} W_t r_{l_t}.
 template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
-__global__ __launch_bounds__(256) void k_action_walk(
-    const ActionNode *__restrict__ rec, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ rowabs,
-    const double *__restrict__ cum, const int32_t *__restrict__ starts, int64_t n_start,
-    WalkArgs a, double *__restrict__ q, uint64_t *__restrict__ digest, unsigned long long *steps) {
+__global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *__restrict__ r,
+                                                     const int32_t *__restrict__ starts,
+                                                     int64_t n_start, WalkArgs a,
+                                                     double *__restrict__ q,
+                                                     uint64_t *__restrict__ digest,
+                                                     unsigned long long *steps) {
     __shared__ double red[4];
     __shared__ unsigned long long redu[4];
-    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
-    const uint32_t k = static_cast<uint32_t>(starts[kk]);
     const int last = a.K - 2;
-    double acc = 0.0;
-    uint64_t dig = 0;
-    unsigned long long nsteps = 0;
-    for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
-        const uint32_t w = static_cast<uint32_t>(w64);
-        uint32_t l = k;
-        double W = 1.0;
-        double wacc = 0.0;
-        uint64_t h = dev::kFnvBasis;
-        ActionNode R = rec[l];
-        for (int t = 0; t <= last; ++t) {
-            if (CUTOFF && !(fabs(W) > a.cutoff))
-                break;
-            wacc += a.coef[t] * W * R.r;
-            if (DIGEST)
-                h = dev::fnv_step(h, l);
-            ++nsteps;
-            if (t == last || R.deg == 0)
-                break;
-            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
-                                               a.key0, a.key1);
-            uint32_t j;
-            double m;
-            if (!WEIGHTED) {
-                j = dev::uniform_index(x.x, x.y, R.deg);
-                m = a.scale * static_cast<double>(R.deg);
-            } else {
-                const double ra = rowabs[l];
-                j = cdf_search(cum + R.start, R.deg, dev::unit53(x.x, x.y) * ra);
-                m = a.scale * ra;
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+        const uint32_t k = static_cast<uint32_t>(starts[kk]);
+        const uint2 rk = g.node[k];
+        const double r_k = r[k];
+        double acc = 0.0;
+        uint64_t dig = 0;
+        unsigned long long nsteps = 0;
+        for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+            const uint32_t w = static_cast<uint32_t>(w64);
+            Pos p{k, rk.x, rk.y};
+            double rl = r_k;
+            double W = 1.0;
+            double wacc = 0.0;
+            uint64_t h = dev::kFnvBasis;
+            for (int t = 0; t <= last; ++t) {
+                if (CUTOFF && !(fabs(W) > a.cutoff))
+                    break;
+                const bool more = t < last && p.deg > 0;
+                Pos nxt = p;
+                double Wn = W;
+                if (more) {
+                    const uint4 x = dev::philox4x32_10(
+                        make_uint4(k, w, static_cast<uint32_t>(t), a.request), a.key0, a.key1);
+                    nxt = step<WEIGHTED>(g, p, x, a.scale, Wn);
+                }
+                wacc += a.coef[t] * W * rl;
+                if (DIGEST)
+                    h = dev::fnv_step(h, p.l);
+                ++nsteps;
+                if (!more)
+                    break;
+                p = nxt;
+                W = Wn;
+                rl = r[p.l];
             }
-            W = W * m;
-            if (WEIGHTED && val[R.start + j] < 0.0)
-                W = -W;
-            l = static_cast<uint32_t>(col[R.start + j]);
-            R = rec[l];
+            acc += wacc;
+            if (DIGEST)
+                dig += h;
         }
-        acc += wacc;
-        if (DIGEST)
-            dig += h;
-    }
-    const double total = dev::block_sum(acc, red);
-    const unsigned long long st = dev::block_sum(nsteps, redu);
-    if (DIGEST) {
-        const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu + 0);
-        if (threadIdx.x == 0)
-            digest[k] = dg;
-    }
-    if (threadIdx.x == 0) {
-        q[k] = total / static_cast<double>(a.N);
-        if (steps)
-            atomicAdd(steps, st);
-    }
+        const double total = dev::block_sum(acc, red);
+        const unsigned long long st = dev::block_sum(nsteps, redu);
+        if (DIGEST) {
+            const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+            if (threadIdx.x == 0)
+                digest[k] = dg;
+        }
+        if (threadIdx.x == 0) {
+            q[k] = total / static_cast<double>(a.N);
+            if (steps)
+                atomicAdd(steps, st);
+        }
     }
 }
 
 // Diagonal: visit records of start row kk, t-major: slot (kk*(K-1) + t)*N + w
 // holds (l_t, c_{t+2} W_t); after a walk ends early its slots hold state -1.
 template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
-__global__ __launch_bounds__(256) void k_diag_walk(
-    const uint2 *__restrict__ node, const int32_t *__restrict__ col,
-    const double *__restrict__ val, const double *__restrict__ rowabs,
-    const double *__restrict__ cum, const int32_t *__restrict__ starts, int64_t n_start,
-    WalkArgs a, int32_t *__restrict__ vstate, double *__restrict__ vx,
-    uint64_t *__restrict__ digest, unsigned long long *steps) {
+__global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *__restrict__ starts,
+                                                   int64_t n_start, WalkArgs a,
+                                                   int32_t *__restrict__ vstate,
+                                                   double *__restrict__ vx,
+                                                   uint64_t *__restrict__ digest,
+                                                   unsigned long long *steps) {
     __shared__ unsigned long long redu[4];
-    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
-    const uint32_t k = static_cast<uint32_t>(starts[kk]);
     const int last = a.K - 2;
-    const int64_t row_base = kk * (a.K - 1) * a.N;
-    uint64_t dig = 0;
-    unsigned long long nsteps = 0;
-    for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
-        const uint32_t w = static_cast<uint32_t>(w64);
-        uint32_t l = k;
-        double W = 1.0;
-        uint64_t h = dev::kFnvBasis;
-        uint2 R = node[l];
-        int t = 0;
-        for (; t <= last; ++t) {
-            if (CUTOFF && !(fabs(W) > a.cutoff))
-                break;
-            const int64_t slot = row_base + int64_t(t) * a.N + w64;
-            vstate[slot] = static_cast<int32_t>(l);
-            vx[slot] = a.coef[t] * W;
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+        const uint32_t k = static_cast<uint32_t>(starts[kk]);
+        const uint2 rk = g.node[k];
+        const int64_t row_base = kk * (a.K - 1) * a.N;
+        uint64_t dig = 0;
+        unsigned long long nsteps = 0;
+        for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+            const uint32_t w = static_cast<uint32_t>(w64);
+            Pos p{k, rk.x, rk.y};
+            double W = 1.0;
+            uint64_t h = dev::kFnvBasis;
+            int t = 0;
+            for (; t <= last; ++t) {
+                if (CUTOFF && !(fabs(W) > a.cutoff))
+                    break;
+                const bool more = t < last && p.deg > 0;
+                Pos nxt = p;
+                double Wn = W;
+                if (more) {
+                    const uint4 x = dev::philox4x32_10(
+                        make_uint4(k, w, static_cast<uint32_t>(t), a.request), a.key0, a.key1);
+                    nxt = step<WEIGHTED>(g, p, x, a.scale, Wn);
+                }
+                const int64_t slot = row_base + int64_t(t) * a.N + w64;
+                vstate[slot] = static_cast<int32_t>(p.l);
+                vx[slot] = a.coef[t] * W;
+                if (DIGEST)
+                    h = dev::fnv_step(h, p.l);
+                ++nsteps;
+                if (!more) {
+                    ++t;
+                    break;
+                }
+                p = nxt;
+                W = Wn;
+            }
+            for (; t <= last; ++t)
+                vstate[row_base + int64_t(t) * a.N + w64] = -1;
             if (DIGEST)
-                h = dev::fnv_step(h, l);
-            ++nsteps;
-            if (t == last || R.y == 0) {
-                ++t;
-                break;
-            }
-            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
-                                               a.key0, a.key1);
-            uint32_t j;
-            double m;
-            if (!WEIGHTED) {
-                j = dev::uniform_index(x.x, x.y, R.y);
-                m = a.scale * static_cast<double>(R.y);
-            } else {
-                const double ra = rowabs[l];
-                j = cdf_search(cum + R.x, R.y, dev::unit53(x.x, x.y) * ra);
-                m = a.scale * ra;
-            }
-            W = W * m;
-            if (WEIGHTED && val[R.x + j] < 0.0)
-                W = -W;
-            l = static_cast<uint32_t>(col[R.x + j]);
-            R = node[l];
+                dig += h;
         }
-        for (; t <= last; ++t)
-            vstate[row_base + int64_t(t) * a.N + w64] = -1;
-        if (DIGEST)
-            dig += h;
-    }
-    const unsigned long long st = dev::block_sum(nsteps, redu);
-    if (DIGEST) {
-        const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
-        if (threadIdx.x == 0)
-            digest[k] = dg;
-    }
-    if (threadIdx.x == 0 && steps)
-        atomicAdd(steps, st);
+        const unsigned long long st = dev::block_sum(nsteps, redu);
+        if (DIGEST) {
+            const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+            if (threadIdx.x == 0)
+                digest[k] = dg;
+        }
+        if (threadIdx.x == 0 && steps)
+            atomicAdd(steps, st);
     }
 }
 
@@ -206,17 +253,18 @@ dim3 walk_grid(int64_t n_start) {
 
 } // namespace
 
-Status action_walks(const mcmf_graph *g, const ActionNode *rec, const int32_t *starts,
-                    int64_t n_start, const WalkParams &p, double *q, uint64_t *digest,
-                    unsigned long long *steps, hipStream_t s) {
+Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
+                    const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
+                    hipStream_t s) {
     if (n_start <= 0 || p.K < 2)
         return {};
     const WalkArgs a = to_args(p);
+    const GraphView gv = view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
     const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
 #define MCMF_LAUNCH_ACTION(W_, D_, C_)                                                             \
-    hipLaunchKernelGGL((k_action_walk<W_, D_, C_>), grid, block, 0, s, rec, g->col, g->val,          \
-                       g->rowabs, g->cum, starts, n_start, a, q, digest, steps)
+    hipLaunchKernelGGL((k_action_walk<W_, D_, C_>), grid, block, 0, s, gv, r, starts, n_start, a,   \
+                       q, digest, steps)
     if (!w && !d && !c) MCMF_LAUNCH_ACTION(false, false, false);
     else if (!w && !d && c) MCMF_LAUNCH_ACTION(false, false, true);
     else if (!w && d && !c) MCMF_LAUNCH_ACTION(false, true, false);
@@ -236,11 +284,12 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
     if (n_start <= 0 || p.K < 2)
         return {};
     const WalkArgs a = to_args(p);
+    const GraphView gv = view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
     const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
 #define MCMF_LAUNCH_DIAG(W_, D_, C_)                                                               \
-    hipLaunchKernelGGL((k_diag_walk<W_, D_, C_>), grid, block, 0, s, g->node, g->col, g->val,       \
-                       g->rowabs, g->cum, starts, n_start, a, state, x, digest, steps)
+    hipLaunchKernelGGL((k_diag_walk<W_, D_, C_>), grid, block, 0, s, gv, starts, n_start, a, state, \
+                       x, digest, steps)
     if (!w && !d && !c) MCMF_LAUNCH_DIAG(false, false, false);
     else if (!w && !d && c) MCMF_LAUNCH_DIAG(false, false, true);
     else if (!w && d && !c) MCMF_LAUNCH_DIAG(false, true, false);

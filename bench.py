@@ -36,26 +36,134 @@ def parse():
     ap.add_argument("--walks", type=int, default=256)
     ap.add_argument("--K", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=100,
+    ap.add_argument("--cpu-rows", type=int, default=40,
                     help="output rows per query in the oracle's timed sample")
     ap.add_argument("--only", choices=["all", "action", "diag"], default="all")
+    ap.add_argument("--copy-probe-bytes", type=int, default=0,
+                    help="after timing, run one device copy of this many bytes (counter calibration)")
+    ap.add_argument("--summarize", metavar="DIR",
+                    help="print a markdown summary of rocprofv3 CSV output in DIR and exit")
+    ap.add_argument("--probe-bytes", type=int, default=0,
+                    help="with --summarize: size of the calibration copy in that run")
     return ap.parse_args()
 
 
 def algorithmic_bytes(kind, st, K):
-    """Bytes each kernel must move per launch set:
-    action walk: 16 B row record per recorded state + 4 B column per transition;
-    diag walk:   8 B row record per state + 4 B column per transition + 12 B visit record out;
-    gather:      12 B visit record in per state + 4 B column entry per probe."""
+    """Bytes each kernel must move:
+    action walk: 16 B edge record per transition + 8 B r per recorded state
+                 + 16 B per start row (row record, r, q out);
+    diag walk:   16 B edge record per transition + 12 B visit record written per state
+                 + 8 B per start row;
+    gather:      12 B visit record read per state + 4 B column entry per probe."""
     steps = st["walk_steps"]
     transitions = steps - st["walks"]
     if kind == "action_walk":
-        return 16 * steps + 4 * transitions + 12 * st["start_rows"]
+        return 16 * transitions + 8 * steps + 16 * st["start_rows"]
     if kind == "diag_walk":
-        return 8 * steps + 4 * transitions + 12 * steps
+        return 16 * transitions + 12 * steps + 8 * st["start_rows"]
     if kind == "diag_gather":
         return 12 * steps + 4 * st["gather_probes"]
     raise ValueError(kind)
+
+
+# Kernel name fragment -> (roofline name, source file whose hash tags counter data).
+KERNELS = {"k_diag_gather": ("diag_gather", "gather.hip"),
+           "k_diag_walk": ("diag_walk", "walk.hip"),
+           "k_action_walk": ("action_walk", "walk.hip")}
+# Calibration: an elementwise kernel that reads and writes a known byte count
+# (device-to-device memcpy may run on a DMA engine and show no kernel).
+COPY_KERNEL = "neg_kernel"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rmat20.md")
+
+
+def source_sha(fname):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2308_01037_amd", "csrc", fname)
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def kernel_label(name):
+    """Short kernel name: the library's k_* kernels with their template
+    arguments, other kernels up to their parameter list."""
+    import re
+    m = re.search(r"(k_\w+(?:<[^()]*>)?)", name)
+    if m:
+        return m.group(1)
+    return name.replace("void ", "").split("(")[0][:60]
+
+
+def summarize(directory, probe_bytes):
+    """Markdown summary of rocprofv3 --kernel-trace/--pmc CSV files."""
+    import csv
+    import glob
+    lines = []
+    traces = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    counters = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    if traces:
+        per = {}
+        for path in traces:
+            for r in csv.DictReader(open(path)):
+                ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                k = per.setdefault(kernel_label(r["Kernel_Name"]), [0, 0])
+                k[0] += 1
+                k[1] += ns
+        lines.append("| kernel | launches | total ms | avg ms |")
+        lines.append("|---|---|---|---|")
+        for name, (cnt, ns) in sorted(per.items(), key=lambda kv: -kv[1][1])[:20]:
+            lines.append(f"| `{name}` | {cnt} | {ns / 1e6:.2f} | {ns / cnt / 1e6:.3f} |")
+    if counters:
+        agg = {}
+        for path in counters:
+            for r in csv.DictReader(open(path)):
+                name = kernel_label(r["Kernel_Name"])
+                key = (name, r["Counter_Name"])
+                a = agg.setdefault(key, [0.0, set()])
+                a[0] += float(r["Counter_Value"])
+                a[1].add(r["Dispatch_Id"])
+        lines.append("")
+        lines.append("| kernel | counter | dispatches | KiB per dispatch |")
+        lines.append("|---|---|---|---|")
+        for (name, ctr), (tot, disp) in sorted(agg.items()):
+            if any(f in name for f in list(KERNELS) + [COPY_KERNEL]):
+                lines.append(f"| `{name}` | {ctr} | {len(disp)} | {tot / len(disp):.1f} |")
+        traffic = {}
+        for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
+            copy = [(tot, disp) for (name, c), (tot, disp) in agg.items()
+                    if c == ctr and COPY_KERNEL in name]
+            if not copy or not probe_bytes:
+                continue
+            # The calibration copy is the largest copy in the run.
+            tot, disp = max(copy, key=lambda t: t[0] / len(t[1]))
+            factor = probe_bytes / (tot / len(disp) * 1024.0)
+            lines.append(f"\n{ctr}: copy of {probe_bytes} bytes reads {tot / len(disp):.1f} KiB "
+                         f"per dispatch -> factor {factor:.4f}")
+            for frag, (kname, src) in KERNELS.items():
+                hits = [(tot2, d2) for (name, c), (tot2, d2) in agg.items() if c == ctr and frag in name]
+                if hits:
+                    tot2 = sum(h[0] for h in hits)
+                    nd = sum(len(h[1]) for h in hits)
+                    t = traffic.setdefault(kname, {"source": src, "sha": source_sha(src)})
+                    t[ctr.lower() + "_bytes_per_launch"] = tot2 / nd * 1024.0 * factor
+        if traffic:
+            lines.append("")
+            lines.append("traffic: " + json.dumps(traffic))
+    return "\n".join(lines)
+
+
+def load_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None when there is none or the kernel's source changed since it was taken."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("traffic: "):
+                t = json.loads(line[len("traffic: "):]).get(kernel)
+                if not t or t["sha"] != source_sha(t["source"]):
+                    return None
+                if "fetch_size_bytes_per_launch" in t and "write_size_bytes_per_launch" in t:
+                    return t["fetch_size_bytes_per_launch"] + t["write_size_bytes_per_launch"]
+    except OSError:
+        pass
+    return None
 
 
 def cpu_baseline(csr, queries, rows, K, N):
@@ -83,6 +191,9 @@ def cpu_baseline(csr, queries, rows, K, N):
 
 def main():
     args = parse()
+    if args.summarize:
+        print(summarize(args.summarize, args.probe_bytes))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the estimator's "
               "multi-GPU sharding is a design note, not built", file=sys.stderr)
@@ -159,6 +270,23 @@ def main():
     dominant = max(kernels, key=lambda kk: kernels[kk]["ms"])
     dk = kernels[dominant]
     alg_total = sum(k["bytes"] for k in kernels.values())
+    # Launches of the dominant kernel in the timed region (one per action query;
+    # one walk and one gather launch per visit-buffer chunk of a diagonal query).
+    def launches_of(what, st):
+        if what == "action":
+            return 1
+        per_row = N * (K - 1) * 12
+        rows_per_chunk = max(1, (2 << 30) // per_row)
+        return -(-st["start_rows"] // rows_per_chunk)
+    launches = sum(launches_of(what, st) for what, _, st, _ in records
+                   if (what == "action") == (dominant == "action_walk"))
+    traffic = load_traffic(dominant)
+    if args.copy_probe_bytes:
+        src = torch.ones(args.copy_probe_bytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_probe_bytes} bytes done")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -202,7 +330,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": dk["gbs"] / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "bytes_per_launch": dk["bytes"] / launches,
+            "ms_per_launch": dk["ms"] / launches,
         },
         "cpu_baseline": cpu,
     }

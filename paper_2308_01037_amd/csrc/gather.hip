@@ -109,67 +109,71 @@ struct Table {
     }
 
     // Lookup of N keys stage by stage so that their LDS reads overlap: all
-    // filter words, then all home buckets, then all values, then the rare
-    // keys that need further buckets.  key < 0 means "no key" (result 0).
+    // filter words, then the home buckets and values in two halves (to bound
+    // register use), then the rare keys that need further buckets.
+    // key < 0 means "no key" (result 0).
     template <int N>
     __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
-        uint32_t fw[N], m[N], b[N];
+        static_assert(N % 2 == 0, "N must be even");
+        constexpr int H = N / 2;
+        uint32_t fw[N], m[N];
 #pragma unroll
         for (int u = 0; u < N; ++u) {
             const uint32_t h = fhash(key[u]);
             m[u] = filter_mask(h);
-            b[u] = bucket_of(key[u]);
             fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
         }
-        // Every lane issues its reads; lanes without a candidate read bucket 0,
-        // a single address the LDS serves as a broadcast.  Unconditional reads
-        // keep all N requests in flight together.
-        bool cand[N];
-        int4 lo[N], hi[N];
-#pragma unroll
-        for (int u = 0; u < N; ++u) {
-            cand[u] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
-            const uint32_t off = cand[u] ? kSlots * b[u] : 0u;
-            lo[u] = *reinterpret_cast<const int4 *>(keys + off);
-            hi[u] = *reinterpret_cast<const int4 *>(keys + off + 4);
-        }
-        int slot[N];
         uint32_t pending = 0;
 #pragma unroll
-        for (int u = 0; u < N; ++u) {
-            int j = -1;
-            if (cand[u]) {
-                const int32_t k = key[u];
-                j = (lo[u].x == k) ? 0 : j;
-                j = (lo[u].y == k) ? 1 : j;
-                j = (lo[u].z == k) ? 2 : j;
-                j = (lo[u].w == k) ? 3 : j;
-                j = (hi[u].x == k) ? 4 : j;
-                j = (hi[u].y == k) ? 5 : j;
-                j = (hi[u].z == k) ? 6 : j;
-                j = (hi[u].w == k) ? 7 : j;
-                // Slots fill in order, so a full bucket ends with a used last slot.
-                pending |= (j < 0 && hi[u].w != kEmpty) ? (1u << u) : 0u;
+        for (int half = 0; half < 2; ++half) {
+            // Every lane issues its reads; lanes without a candidate read bucket
+            // 0, one address the LDS serves as a broadcast.
+            bool cand[H];
+            uint32_t b[H];
+            int4 lo[H], hi[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v) {
+                const int u = half * H + v;
+                cand[v] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
+                b[v] = cand[v] ? bucket_of(key[u]) : 0u;
+                lo[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v]);
+                hi[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v] + 4);
             }
-            slot[u] = j;
+            int slot[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v) {
+                const int u = half * H + v;
+                const int32_t k = key[u];
+                int j = -1;
+                j = (lo[v].x == k) ? 0 : j;
+                j = (lo[v].y == k) ? 1 : j;
+                j = (lo[v].z == k) ? 2 : j;
+                j = (lo[v].w == k) ? 3 : j;
+                j = (hi[v].x == k) ? 4 : j;
+                j = (hi[v].y == k) ? 5 : j;
+                j = (hi[v].z == k) ? 6 : j;
+                j = (hi[v].w == k) ? 7 : j;
+                j = cand[v] ? j : -1;
+                // Slots fill in order, so a full bucket ends with a used last slot.
+                pending |= (cand[v] && j < 0 && hi[v].w != kEmpty) ? (1u << u) : 0u;
+                slot[v] = j;
+            }
+            double got[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v)
+                got[v] = vals[slot[v] >= 0 ? kSlots * b[v] + slot[v] : 0u];
+#pragma unroll
+            for (int v = 0; v < H; ++v)
+                out[half * H + v] = slot[v] >= 0 ? got[v] : 0.0;
         }
-        double got[N];
-#pragma unroll
-        for (int u = 0; u < N; ++u)
-            got[u] = vals[slot[u] >= 0 ? kSlots * b[u] + slot[u] : 0u];
-#pragma unroll
-        for (int u = 0; u < N; ++u)
-            out[u] = slot[u] >= 0 ? got[u] : 0.0;
         while (pending) {
             const int u = __ffs(pending) - 1;
             pending &= pending - 1;
             int32_t kx = key[0];
-            uint32_t bx = b[0];
 #pragma unroll
-            for (int v = 1; v < N; ++v) {
+            for (int v = 1; v < N; ++v)
                 kx = (v == u) ? key[v] : kx;
-                bx = (v == u) ? b[v] : bx;
-            }
+            uint32_t bx = bucket_of(kx);
             double r = 0.0;
             bool more = true;
             for (uint32_t tries = 1; more && tries < nb; ++tries) {
@@ -246,7 +250,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
             __syncthreads();
             const int64_t count = nw * (a.K - 1);
             if (nw == a.N) {
-                for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+                // Step 0 of every walk sits at k: insert the sum of those visits once
+                // instead of N colliding atomic updates of one slot.
+                double x0 = 0.0;
+                for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
+                    x0 += st[i] >= 0 ? xs[i] : 0.0;
+                x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
+                if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
+                    atomicAdd(a.overflow, 1ull);
+                for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
                     const int32_t s = st[i];
                     if (s >= 0 && !tab.insert(s, xs[i]))
                         atomicAdd(a.overflow, 1ull);
@@ -290,41 +302,71 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
                 if (threadIdx.x == 0)
                     bt.prefix[kBatch] = total;
                 __syncthreads();
-                // Chunks to groups of kGroup lanes.
+                // Group g takes the contiguous chunk range [g*per, (g+1)*per) and
+                // walks the neighbours forward, so the owner is searched once.
                 const int group = threadIdx.x / kGroup;
                 const int gl = threadIdx.x % kGroup;
-                for (uint32_t c = group; c < total; c += kGroups) {
-                    // Neighbour owning chunk c: last r with prefix[r] <= c (the
-                    // search is uniform across the group).
-                    int lo = 0, hi = kBatch;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (bt.prefix[mid] <= c)
-                            lo = mid;
+                const uint32_t per = (total + kGroups - 1) / kGroups;
+                const uint32_t c_begin = group * per;
+                const uint32_t c_end = (c_begin + per < total) ? c_begin + per : total;
+                if (c_begin < c_end) {
+                    int r = 0, hi = kBatch;
+                    while (hi - r > 1) {
+                        const int mid = (r + hi) >> 1;
+                        if (bt.prefix[mid] <= c_begin)
+                            r = mid;
                         else
                             hi = mid;
                     }
-                    const uint32_t first = (c - bt.prefix[lo]) * kChunk + gl;
-                    const uint32_t len = bt.len[lo];
-                    const int64_t base = int64_t(bt.start[lo]);
-                    int32_t key[kPerLane];
-                    double wv[kPerLane];
-#pragma unroll
-                    for (int u = 0; u < kPerLane; ++u) {
-                        const uint32_t off = first + u * kGroup;
-                        key[u] = off < len ? a.col[base + off] : -1;
-                        wv[u] = (WEIGHTED && off < len) ? a.val[base + off] : 1.0;
-                        probes += off < len ? 1 : 0;
-                    }
-                    double qv[kPerLane];
-                    tab.lookup_n<kPerLane>(key, qv);
+                    uint32_t next = bt.prefix[r + 1];
+                    uint32_t len = bt.len[r];
+                    int64_t base = int64_t(bt.start[r]);
+                    uint32_t first_chunk = bt.prefix[r];
                     double acc = 0.0;
+                    for (uint32_t c = c_begin; c < c_end; ++c) {
+                        if (c >= next) {
+                            // Row change: flush the finished neighbour's partial sum.
+                            const double g = dev::group_sum<kGroup>(acc);
+                            if (gl == 0 && g != 0.0)
+                                atomicAdd(&bt.sum[r], g);
+                            acc = 0.0;
+                            do {
+                                ++r;
+                                next = bt.prefix[r + 1];
+                            } while (c >= next);
+                            len = bt.len[r];
+                            base = int64_t(bt.start[r]);
+                            first_chunk = bt.prefix[r];
+                        }
+                        const uint32_t off0 = (c - first_chunk) * kChunk;
+                        const uint32_t first = off0 + gl;
+                        int32_t key[kPerLane];
+                        double wv[kPerLane];
+                        if (off0 + kChunk <= len) {
 #pragma unroll
-                    for (int u = 0; u < kPerLane; ++u)
-                        acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
-                    acc = dev::group_sum<kGroup>(acc);
-                    if (gl == 0 && acc != 0.0)
-                        atomicAdd(&bt.sum[lo], acc);
+                            for (int u = 0; u < kPerLane; ++u) {
+                                key[u] = a.col[base + first + u * kGroup];
+                                wv[u] = WEIGHTED ? a.val[base + first + u * kGroup] : 1.0;
+                            }
+                            probes += gl == 0 ? kChunk : 0;
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < kPerLane; ++u) {
+                                const uint32_t off = first + u * kGroup;
+                                key[u] = off < len ? a.col[base + off] : -1;
+                                wv[u] = (WEIGHTED && off < len) ? a.val[base + off] : 1.0;
+                            }
+                            probes += gl == 0 ? len - off0 : 0;
+                        }
+                        double qv[kPerLane];
+                        tab.lookup_n<kPerLane>(key, qv);
+#pragma unroll
+                        for (int u = 0; u < kPerLane; ++u)
+                            acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
+                    }
+                    const double g = dev::group_sum<kGroup>(acc);
+                    if (gl == 0 && g != 0.0)
+                        atomicAdd(&bt.sum[r], g);
                 }
                 __syncthreads();
                 if (threadIdx.x < m && bt.row[threadIdx.x] >= 0) {

@@ -94,7 +94,18 @@ typedef struct {
 #define MCMF_SYMMETRIC 1u /* caller states A = A^T; required by mcmf_diag */
 #define MCMF_VALIDATE 2u  /* check the CSR arrays (and, with MCMF_SYMMETRIC, symmetry) */
 
-/* Precision of the walk weights (the accumulators and final reduction are FP64). */
+/* Precision of the walk weights.  MCMF_PRECISION_FP32_WEIGHTS keeps W, the
+ * per-step factor s*sum|a| and each per-step contribution (c_{t+2} W r_l for
+ * the action, c_{t+2} W for the diagonal) in FP32; every sum over steps, walks
+ * and the gather stays FP64.  Walk paths are identical to the FP64 mode, so
+ * the difference from FP64 is rounding only.  Step t's weight carries at
+ * most 2t roundings (factor and product) and a term two or three more, so
+ *     |x_fp32 - x_fp64| <= 2 K * 2^-24 * sum |terms|
+ * per output (to first order, ignoring FP32 underflow of terms below 1e-38),
+ * where sum |terms| is the sum of the absolute values of the walk terms
+ * behind that output (the Monte Carlo part itself when A, v >= 0).
+ * FP32 weights must stay below 3.4e38 in magnitude: functions whose weights
+ * grow (s * sum|a| > 1 over many steps) overflow to inf in this mode. */
 #define MCMF_PRECISION_FP64 0
 #define MCMF_PRECISION_FP32_WEIGHTS 1
 

@@ -104,8 +104,6 @@ Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int3
                 return fail(MCMF_E_ARG, "reserved option words must be zero");
         if (o->precision != MCMF_PRECISION_FP64 && o->precision != MCMF_PRECISION_FP32_WEIGHTS)
             return fail(MCMF_E_ARG, "unknown precision %d", o->precision);
-        if (o->precision == MCMF_PRECISION_FP32_WEIGHTS)
-            return fail(MCMF_E_UNSUPPORTED, "FP32-weight walks are not built into this library");
         if (!(o->weight_cutoff >= 0.0) || !std::isfinite(o->weight_cutoff))
             return fail(MCMF_E_ARG, "weight_cutoff must be finite and >= 0");
     }
@@ -378,17 +376,19 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     EventList chunk_events;
     if (K >= 2 && n_start > 0) {
         const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
-        // Visit records of a chunk of start rows: 12 bytes per visit.
+        // Visit records of a chunk of start rows: 12 bytes per visit (8 with
+        // FP32 walk weights).
         const int64_t per_row = N * (K - 1);
+        const int64_t xbytes = p.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
         int64_t chunk_bytes = int64_t(2) << 30;
         if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
             chunk_bytes = std::max<int64_t>(1, strtoll(e, nullptr, 10));
-        int64_t rows_per_chunk = chunk_bytes / (per_row * 12);
+        int64_t rows_per_chunk = chunk_bytes / (per_row * (4 + xbytes));
         rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(rows_per_chunk, n_start));
         DevBuf<int32_t> vstate;
-        DevBuf<double> vx;
+        DevBuf<unsigned char> vx;
         MCMF_TRY(vstate.alloc(rows_per_chunk * per_row, s));
-        MCMF_TRY(vx.alloc(rows_per_chunk * per_row, s));
+        MCMF_TRY(vx.alloc(rows_per_chunk * per_row * xbytes, s));
         // Per-chunk events are read only after the call's final synchronisation,
         // so timing does not stall the stream between chunks.
         const int64_t n_chunks = (n_start + rows_per_chunk - 1) / rows_per_chunk;

@@ -197,7 +197,7 @@ struct GatherArgs {
     int K;
     int64_t walks_per_pass;
     const int32_t *vstate;
-    const double *vx;
+    const void *vx; // double[] or float[] (FP32 walk weights)
     const uint8_t *in_set; // null: every row requested
     double scale;
     uint32_t nb; // buckets
@@ -216,7 +216,7 @@ struct Batch {
     double sum[kBatch];          // <Q_k, C_i> partial sums
 };
 
-template <bool WEIGHTED>
+template <bool WEIGHTED, class VT>
 __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Batch bt;
@@ -236,7 +236,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
         const int32_t k = a.starts[kk];
         const uint2 rk = a.node[k];
         const int32_t *st = a.vstate + kk * span;
-        const double *xs = a.vx + kk * span;
+        const VT *xs = static_cast<const VT *>(a.vx) + kk * span;
         for (int64_t w0 = 0; w0 < a.N; w0 += a.walks_per_pass) {
             const int64_t nw = (a.N - w0 < a.walks_per_pass) ? (a.N - w0) : a.walks_per_pass;
             // (1) Q_k from walks [w0, w0 + nw).
@@ -254,13 +254,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
                 // instead of N colliding atomic updates of one slot.
                 double x0 = 0.0;
                 for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
-                    x0 += st[i] >= 0 ? xs[i] : 0.0;
+                    x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
                 x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
                 if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
                     atomicAdd(a.overflow, 1ull);
                 for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
                     const int32_t s = st[i];
-                    if (s >= 0 && !tab.insert(s, xs[i]))
+                    if (s >= 0 && !tab.insert(s, static_cast<double>(xs[i])))
                         atomicAdd(a.overflow, 1ull);
                 }
             } else {
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
                     const int64_t t = i / nw;
                     const int64_t slot = t * a.N + w0 + (i - t * nw);
                     const int32_t s = st[slot];
-                    if (s >= 0 && !tab.insert(s, xs[slot]))
+                    if (s >= 0 && !tab.insert(s, static_cast<double>(xs[slot])))
                         atomicAdd(a.overflow, 1ull);
                 }
             }
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
 } // namespace
 
 Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                   const int32_t *state, const double *x, const uint8_t *in_set, double *dacc,
+                   const int32_t *state, const void *x, const uint8_t *in_set, double *dacc,
                    unsigned long long *probes, unsigned long long *overflow, hipStream_t s) {
     if (n_start <= 0 || p.K < 2)
         return {};
@@ -417,15 +417,17 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
     const size_t lds = plan.lds_bytes;
     const int64_t cap_blocks = int64_t(1) << 20;
     const dim3 grid(static_cast<uint32_t>(n_start < cap_blocks ? n_start : cap_blocks));
-    if (g->weighted) {
-        MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_diag_gather<true>),
+    const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
+    auto launch = [&](auto kernel) -> Status {
+        MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        hipLaunchKernelGGL(k_diag_gather<true>, grid, dim3(kGatherThreads), lds, s, a);
-    } else {
-        MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_diag_gather<false>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        hipLaunchKernelGGL(k_diag_gather<false>, grid, dim3(kGatherThreads), lds, s, a);
-    }
+        hipLaunchKernelGGL(kernel, grid, dim3(kGatherThreads), lds, s, a);
+        return {};
+    };
+    if (g->weighted)
+        MCMF_TRY(fp32 ? launch(&k_diag_gather<true, float>) : launch(&k_diag_gather<true, double>));
+    else
+        MCMF_TRY(fp32 ? launch(&k_diag_gather<false, float>) : launch(&k_diag_gather<false, double>));
     MCMF_HIP(hipGetLastError());
     return {};
 }

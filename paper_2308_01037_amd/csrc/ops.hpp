@@ -41,15 +41,16 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
 
 // Diag walks for starts[0..n_start): visit records, t-major per start row:
 // state[(kk*(K-1) + t)*N + w], x = c_{t+2} W_t; finished walks store -1.
+// x is double[] (FP64) or float[] (FP32 walk weights).
 Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                  int32_t *state, double *x, uint64_t *digest, unsigned long long *steps,
+                  int32_t *state, void *x, uint64_t *digest, unsigned long long *steps,
                   hipStream_t s);
 
 // Diag gather for starts[0..n_start) with their visit records: for each
 // requested neighbour i of k, dacc[i] += s^2 a_ki <Q_k, C_i> / N.
 // in_set == null means every row is requested.
 Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                   const int32_t *state, const double *x, const uint8_t *in_set, double *dacc,
+                   const int32_t *state, const void *x, const uint8_t *in_set, double *dacc,
                    unsigned long long *probes, unsigned long long *overflow, hipStream_t s);
 
 } // namespace mcmf

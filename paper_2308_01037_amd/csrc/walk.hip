@@ -15,6 +15,14 @@
 // step.  The transition of step t is issued before step t is recorded, so
 // the record's load overlaps the bookkeeping; the action's r_l load sits off
 // that dependency chain.  Weighted rows search the running sums of |a|.
+//
+// Weight type WT: double (FP64 path) or float (FP32 walk weights).  With
+// float, W, the per-step factor s * sum|a| and each row contribution
+// c_{t+2} W r_l (action) or visit value c_{t+2} W (diagonal) are FP32; the
+// sums over steps, walks and the gather stay FP64.  Paths are identical in
+// both modes (sampling is integer), so the difference is rounding only.
+#include <type_traits>
+
 #include "device.hpp"
 #include "ops.hpp"
 
@@ -85,13 +93,13 @@ struct Pos {
 
 // One transition out of row p (deg > 0) with the block of random words x.
 // Updates W (times s * sum |a|, sign of the entry) and returns the new row.
-template <bool WEIGHTED>
+template <bool WEIGHTED, class WT>
 __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
-                                    double &W) {
+                                    WT &W) {
     Pos n;
     if constexpr (!WEIGHTED) {
         const uint32_t j = dev::uniform_index(x.x, x.y, p.deg);
-        W = W * (scale * static_cast<double>(p.deg));
+        W = W * static_cast<WT>(scale * static_cast<double>(p.deg));
         const uint4 e = g.edge[int64_t(p.start) + j];
         n.l = e.x;
         n.start = e.y;
@@ -99,7 +107,7 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
     } else {
         const double ra = g.rowabs[p.l];
         const uint32_t j = cdf_search(g.cum + p.start, p.deg, dev::unit53(x.x, x.y) * ra);
-        W = W * (scale * ra);
+        W = W * static_cast<WT>(scale * ra);
         if (g.val[int64_t(p.start) + j] < 0.0)
             W = -W;
         n.l = static_cast<uint32_t>(g.col[int64_t(p.start) + j]);
@@ -111,7 +119,7 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
 }
 
 // Action: q[k] = (1/N) sum_w sum_t c_{t+2} W_t r_{l_t}.
-template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
 __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *__restrict__ r,
                                                      const int32_t *__restrict__ starts,
                                                      int64_t n_start, WalkArgs a,
@@ -132,21 +140,21 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
             const uint32_t w = static_cast<uint32_t>(w64);
             Pos p{k, rk.x, rk.y};
             double rl = r_k;
-            double W = 1.0;
+            WT W = WT(1);
             double wacc = 0.0;
             uint64_t h = dev::kFnvBasis;
             for (int t = 0; t <= last; ++t) {
-                if (CUTOFF && !(fabs(W) > a.cutoff))
+                if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
                     break;
                 const bool more = t < last && p.deg > 0;
                 Pos nxt = p;
-                double Wn = W;
+                WT Wn = W;
                 if (more) {
                     const uint4 x = dev::philox4x32_10(
                         make_uint4(k, w, static_cast<uint32_t>(t), a.request), a.key0, a.key1);
-                    nxt = step<WEIGHTED>(g, p, x, a.scale, Wn);
+                    nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
                 }
-                wacc += a.coef[t] * W * rl;
+                wacc += static_cast<double>(static_cast<WT>(a.coef[t]) * W * static_cast<WT>(rl));
                 if (DIGEST)
                     h = dev::fnv_step(h, p.l);
                 ++nsteps;
@@ -177,11 +185,11 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
 
 // Diagonal: visit records of start row kk, t-major: slot (kk*(K-1) + t)*N + w
 // holds (l_t, c_{t+2} W_t); after a walk ends early its slots hold state -1.
-template <bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
 __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *__restrict__ starts,
                                                    int64_t n_start, WalkArgs a,
                                                    int32_t *__restrict__ vstate,
-                                                   double *__restrict__ vx,
+                                                   WT *__restrict__ vx,
                                                    uint64_t *__restrict__ digest,
                                                    unsigned long long *steps) {
     __shared__ unsigned long long redu[4];
@@ -195,23 +203,23 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
         for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
             const uint32_t w = static_cast<uint32_t>(w64);
             Pos p{k, rk.x, rk.y};
-            double W = 1.0;
+            WT W = WT(1);
             uint64_t h = dev::kFnvBasis;
             int t = 0;
             for (; t <= last; ++t) {
-                if (CUTOFF && !(fabs(W) > a.cutoff))
+                if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
                     break;
                 const bool more = t < last && p.deg > 0;
                 Pos nxt = p;
-                double Wn = W;
+                WT Wn = W;
                 if (more) {
                     const uint4 x = dev::philox4x32_10(
                         make_uint4(k, w, static_cast<uint32_t>(t), a.request), a.key0, a.key1);
-                    nxt = step<WEIGHTED>(g, p, x, a.scale, Wn);
+                    nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
                 }
                 const int64_t slot = row_base + int64_t(t) * a.N + w64;
                 vstate[slot] = static_cast<int32_t>(p.l);
-                vx[slot] = a.coef[t] * W;
+                vx[slot] = static_cast<WT>(a.coef[t]) * W;
                 if (DIGEST)
                     h = dev::fnv_step(h, p.l);
                 ++nsteps;
@@ -251,6 +259,33 @@ dim3 walk_grid(int64_t n_start) {
     return dim3(static_cast<uint32_t>(n_start < cap ? n_start : cap));
 }
 
+// Runtime flags to template arguments.
+template <class F>
+void dispatch4(bool fp32, bool weighted, bool digest, bool cutoff, F &&f) {
+    auto with_c = [&](auto wt, auto w, auto d) {
+        if (cutoff)
+            f(wt, w, d, std::true_type{});
+        else
+            f(wt, w, d, std::false_type{});
+    };
+    auto with_d = [&](auto wt, auto w) {
+        if (digest)
+            with_c(wt, w, std::true_type{});
+        else
+            with_c(wt, w, std::false_type{});
+    };
+    auto with_w = [&](auto wt) {
+        if (weighted)
+            with_d(wt, std::true_type{});
+        else
+            with_d(wt, std::false_type{});
+    };
+    if (fp32)
+        with_w(float{});
+    else
+        with_w(double{});
+}
+
 } // namespace
 
 Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
@@ -261,44 +296,33 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     const WalkArgs a = to_args(p);
     const GraphView gv = view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
-    const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
-#define MCMF_LAUNCH_ACTION(W_, D_, C_)                                                             \
-    hipLaunchKernelGGL((k_action_walk<W_, D_, C_>), grid, block, 0, s, gv, r, starts, n_start, a,   \
-                       q, digest, steps)
-    if (!w && !d && !c) MCMF_LAUNCH_ACTION(false, false, false);
-    else if (!w && !d && c) MCMF_LAUNCH_ACTION(false, false, true);
-    else if (!w && d && !c) MCMF_LAUNCH_ACTION(false, true, false);
-    else if (!w && d && c) MCMF_LAUNCH_ACTION(false, true, true);
-    else if (w && !d && !c) MCMF_LAUNCH_ACTION(true, false, false);
-    else if (w && !d && c) MCMF_LAUNCH_ACTION(true, false, true);
-    else if (w && d && !c) MCMF_LAUNCH_ACTION(true, true, false);
-    else MCMF_LAUNCH_ACTION(true, true, true);
-#undef MCMF_LAUNCH_ACTION
+    dispatch4(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
+              p.cutoff > 0.0, [&](auto wt, auto w, auto d, auto c) {
+                  using WT = decltype(wt);
+                  hipLaunchKernelGGL((k_action_walk<WT, decltype(w)::value, decltype(d)::value,
+                                                    decltype(c)::value>),
+                                     grid, block, 0, s, gv, r, starts, n_start, a, q, digest, steps);
+              });
     MCMF_HIP(hipGetLastError());
     return {};
 }
 
 Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                  int32_t *state, double *x, uint64_t *digest, unsigned long long *steps,
+                  int32_t *state, void *x, uint64_t *digest, unsigned long long *steps,
                   hipStream_t s) {
     if (n_start <= 0 || p.K < 2)
         return {};
     const WalkArgs a = to_args(p);
     const GraphView gv = view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
-    const bool w = g->weighted, d = digest != nullptr, c = p.cutoff > 0.0;
-#define MCMF_LAUNCH_DIAG(W_, D_, C_)                                                               \
-    hipLaunchKernelGGL((k_diag_walk<W_, D_, C_>), grid, block, 0, s, gv, starts, n_start, a, state, \
-                       x, digest, steps)
-    if (!w && !d && !c) MCMF_LAUNCH_DIAG(false, false, false);
-    else if (!w && !d && c) MCMF_LAUNCH_DIAG(false, false, true);
-    else if (!w && d && !c) MCMF_LAUNCH_DIAG(false, true, false);
-    else if (!w && d && c) MCMF_LAUNCH_DIAG(false, true, true);
-    else if (w && !d && !c) MCMF_LAUNCH_DIAG(true, false, false);
-    else if (w && !d && c) MCMF_LAUNCH_DIAG(true, false, true);
-    else if (w && d && !c) MCMF_LAUNCH_DIAG(true, true, false);
-    else MCMF_LAUNCH_DIAG(true, true, true);
-#undef MCMF_LAUNCH_DIAG
+    dispatch4(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
+              p.cutoff > 0.0, [&](auto wt, auto w, auto d, auto c) {
+                  using WT = decltype(wt);
+                  hipLaunchKernelGGL((k_diag_walk<WT, decltype(w)::value, decltype(d)::value,
+                                                  decltype(c)::value>),
+                                     grid, block, 0, s, gv, starts, n_start, a, state,
+                                     static_cast<WT *>(x), digest, steps);
+              });
     MCMF_HIP(hipGetLastError());
     return {};
 }

@@ -1,0 +1,88 @@
+"""FP32 walk weights with FP64 accumulation: the paths are the FP64 paths
+(bit-identical digests) and every output stays within the stated rounding
+bound |x32 - x64| <= 2 K 2^-24 sum|terms| of the FP64 result (step t's
+weight carries at most 2t roundings, a term at most four more).  On the
+non-negative graphs used here every term is non-negative, so sum|terms| is
+the Monte Carlo part x64 - h itself."""
+import numpy as np
+import pytest
+
+import graphgen as G
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from _gpu import graph  # noqa: E402
+from paper_2308_01037_amd import mcmf as M  # noqa: E402
+
+
+def run(g, what, precision, n, N, K, scale, rows=None, seed=5):
+    dig = torch.zeros(n, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    opts = M.make_opts(seed=seed, precision=precision, stream=stream, path_digest=dig)
+    f = M.make_fn(M.MCMF_FN_EXP, scale)
+    if what == "action":
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+        M.mcmf_action(g.handle, f, torch.ones(n, dtype=torch.float64, device="cuda"), N, K, opts, out)
+    else:
+        count = n if rows is None else len(rows)
+        out = torch.empty(count, dtype=torch.float64, device="cuda")
+        rt = None if rows is None else torch.as_tensor(rows, dtype=torch.int32, device="cuda")
+        M.mcmf_diag(g.handle, f, rt, 0 if rows is None else len(rows), N, K, opts, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), dig.cpu().numpy()
+
+
+def check_bound(x32, x64, h, K, what):
+    mc = x64 - h
+    assert np.all(mc >= -1e-15 * np.abs(x64)), what
+    bound = 2 * K * 2.0 ** -24 * np.abs(mc) + 4 * np.finfo(np.float64).eps * np.abs(x64) + 1e-30
+    err = np.abs(x32 - x64)
+    assert np.all(err <= bound), (what, float(np.max(err / np.maximum(bound, 1e-300))))
+    return float(np.max(err[mc > 0] / mc[mc > 0])) if np.any(mc > 0) else 0.0
+
+
+@pytest.mark.parametrize("maker", [lambda: G.erdos_renyi_dense(600, 0.02, seed=3),
+                                   lambda: G.rmat(12, seed=4),
+                                   lambda: G.barabasi_albert(5000, 8, seed=2)])
+def test_fp32_weights_within_bound(maker):
+    csr = maker()
+    K, N = 40, 64
+    s = 1.0 / csr.d_max
+    c = oracle.coeffs(oracle.FN_EXP, K)
+    with graph(csr) as g:
+        ya, da = run(g, "action", M.MCMF_PRECISION_FP64, csr.n, N, K, s)
+        yb, db = run(g, "action", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s)
+        xa, ea = run(g, "diag", M.MCMF_PRECISION_FP64, csr.n, N, K, s)
+        xb, eb = run(g, "diag", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s)
+    assert np.array_equal(da, db) and np.array_equal(ea, eb), "FP32 mode changed the walks"
+    rel_a = check_bound(yb, ya, c[0] + c[1] * s * csr.deg, K, "action")
+    rel_d = check_bound(xb, xa, np.full(csr.n, c[0]), K, "diag")
+    # The FP32 path is really taken: results differ from FP64 by rounding.
+    assert not np.array_equal(ya, yb) and not np.array_equal(xa, xb)
+    assert rel_a < 2 * K * 2.0 ** -24 and rel_d < 2 * K * 2.0 ** -24
+
+
+def test_fp32_against_oracle_on_sampled_rows():
+    # Barabasi-Albert graph, exp(A/d_max), full action and the diagonal on 1% of
+    # the rows; the FP64 oracle recomputes 200 sampled outputs of each.
+    csr = G.barabasi_albert(200_000, 8, seed=0)
+    K, N = 40, 256
+    s = 1.0 / csr.d_max
+    rows = G.random_rows(csr.n, csr.n // 100, seed=0)
+    with graph(csr) as g:
+        y32, _ = run(g, "action", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s, seed=1)
+        d32, _ = run(g, "diag", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s, rows=rows, seed=1)
+    pick = np.random.default_rng(3).choice(len(rows), 200, replace=False)
+    sample = np.sort(rows[pick]).astype(np.int32)
+    oa = oracle.action(csr, oracle.FN_EXP, np.ones(csr.n), N=N, K=K, scale=s, seed=1, rows=sample)
+    od = oracle.diag(csr, oracle.FN_EXP, N=N, K=K, scale=s, seed=1, rows=sample, assume_symmetric=True)
+    c = oracle.coeffs(oracle.FN_EXP, K)
+    check_bound(y32[sample], oa["y"], c[0] + c[1] * s * csr.deg[sample], K, "action vs oracle")
+    pos = {int(r): i for i, r in enumerate(rows)}
+    d_s = np.array([d32[pos[int(r)]] for r in sample])
+    check_bound(d_s, od["d"], np.full(sample.size, c[0]), K, "diag vs oracle")

@@ -221,6 +221,70 @@ mcmf_status mcmf_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows
 mcmf_status mcmf_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_t n_walks,
                         int32_t K, const mcmf_opts *opts, double *out, mcmf_stats *stats);
 
+/* ------------------------------------------------------------------ */
+/* Batched execution                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef enum { MCMF_REQ_DIAG = 0, MCMF_REQ_ACTION = 1 } mcmf_request_kind;
+
+/* One request of a batch: the arguments of one mcmf_diag / mcmf_action call.
+ * Arrays follow the conventions above (host or device memory). */
+typedef struct {
+    int32_t kind;               /* mcmf_request_kind */
+    int32_t K;                  /* highest power kept, 0 <= K <= 4096 */
+    const mcmf_graph *graph;    /* diag: created with MCMF_SYMMETRIC */
+    mcmf_fn fn;
+    const int32_t *rows;        /* diag: requested rows (NULL: every row) */
+    int64_t n_rows;             /* diag: number of requested rows */
+    const double *v;            /* action: double[n] */
+    int64_t n_walks;            /* walks per start row, >= 1 when K >= 2 */
+    uint64_t seed;
+    uint32_t request_id;
+    int32_t precision;          /* MCMF_PRECISION_* */
+    double weight_cutoff;       /* as in mcmf_opts */
+    double *out;                /* diag: double[n_rows] (or [n]); action: double[n] */
+    uint64_t *path_digest;      /* optional, as in mcmf_opts */
+    mcmf_status status;         /* out: this request's status */
+    uint64_t walk_steps;        /* out: recorded walk states of this request */
+} mcmf_request;
+
+typedef struct {
+    void *stream;               /* hipStream_t the batch is ordered on, or NULL for the
+                                   stream of the first request's graph */
+    int32_t use_graph;          /* 1: record the batch's launches in a hipGraph, then
+                                   launch that graph (one submission for the batch) */
+    int32_t reserved0;          /* must be zero */
+    uint32_t reserved[6];       /* must be zero */
+} mcmf_batch_opts;
+
+/*
+ * mcmf_batch -- run several diag / action requests (any mix of graphs,
+ * functions, walk counts, K and precisions on one device) as one unit of
+ * GPU work.  All walks of all requests run in one persistent walk kernel
+ * (work items: 64 walks of one start row of one request, taken by
+ * wavefronts in turn), the diagonal gathers in persistent gather kernels
+ * (one per visit-buffer chunk and kernel variant: FP64 / FP32 weights,
+ * unweighted / weighted graph).  Every request's walks are the ones its own
+ * mcmf_diag / mcmf_action call would draw (same keyed counters), so its
+ * result equals that call's result up to the order of floating-point
+ * additions.  The call returns once the whole batch is complete and its
+ * outputs are written.
+ *
+ *   reqs    array of n_reqs requests; status and walk_steps are written
+ *   opts    may be NULL
+ *   stats   optional: totals over the batch (start_rows, walks, walk_steps,
+ *           gather_probes, ms_total)
+ *
+ * Calls that overlap on one stream are ordered; on different streams they
+ * are independent (each call owns its scratch buffers).
+ *
+ * Errors: a request with invalid arguments gets its own status and fails the
+ * whole batch with that status before any work starts (no output written);
+ * MCMF_E_NOMEM, MCMF_E_DEVICE as for the single calls.
+ */
+mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *opts,
+                       mcmf_stats *stats);
+
 /* Static name of a status code. */
 const char *mcmf_status_string(mcmf_status s);
 

@@ -84,7 +84,58 @@ int64_t grid_for(int64_t n, int per_block) {
     return b < 1 ? 1 : (b < cap ? b : cap);
 }
 
+} // namespace
+
+Status mark_rows(const int32_t *rows, int64_t count, int64_t n, uint8_t *in_set, int *bad,
+                 hipStream_t s) {
+    if (count <= 0)
+        return {};
+    hipLaunchKernelGGL(k_mark_rows, dim3(grid_for(count, 256)), dim3(256), 0, s, rows, count, n,
+                       in_set, bad);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+Status mark_starts(const mcmf_graph *g, const int32_t *rows, int64_t count, uint8_t *start_flags,
+                   hipStream_t s) {
+    if (count <= 0)
+        return {};
+    hipLaunchKernelGGL(k_mark_starts, dim3(grid_for(count, 4)), dim3(256), 0, s, rows, count,
+                       g->node, g->col, start_flags);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+Status diag_finish(const mcmf_graph *g, const int32_t *rows, int64_t count, int K, double c0,
+                   double c1, double scale, const double *dacc, double *out, hipStream_t s) {
+    if (count <= 0)
+        return {};
+    hipLaunchKernelGGL(k_diag_finish, dim3(grid_for(count, 4)), dim3(256), 0, s, rows, count,
+                       g->node, g->col, g->val, K, c0, c1, scale, dacc, out);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+namespace {
+
 // ---- argument handling ----
+
+} // namespace
+
+WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N) {
+    WalkParams p;
+    p.coef = coef;
+    p.K = K;
+    p.scale = scale;
+    p.n_walks = N;
+    const uint64_t seed = o ? o->seed : 0;
+    p.key0 = static_cast<uint32_t>(seed & 0xffffffffu);
+    p.key1 = static_cast<uint32_t>(seed >> 32);
+    p.request = o ? o->request_id : 0u;
+    p.cutoff = o ? o->weight_cutoff : 0.0;
+    p.precision = o ? o->precision : 0;
+    return p;
+}
 
 Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K,
                     const mcmf_opts *o) {
@@ -109,6 +160,8 @@ Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int3
     }
     return {};
 }
+
+namespace {
 
 // Events destroyed on scope exit.
 struct EventList : std::vector<hipEvent_t> {
@@ -154,55 +207,6 @@ struct Timer {
     }
 };
 
-WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N) {
-    WalkParams p;
-    p.coef = coef;
-    p.K = K;
-    p.scale = scale;
-    p.n_walks = N;
-    const uint64_t seed = o ? o->seed : 0;
-    p.key0 = static_cast<uint32_t>(seed & 0xffffffffu);
-    p.key1 = static_cast<uint32_t>(seed >> 32);
-    p.request = o ? o->request_id : 0u;
-    p.cutoff = o ? o->weight_cutoff : 0.0;
-    p.precision = o ? o->precision : 0;
-    return p;
-}
-
-// Device view of a caller array: the array itself or a staged copy.
-template <class T>
-struct View {
-    T *ptr = nullptr;
-    DevBuf<T> staged;
-    bool host = false;
-    Status in(const T *p, size_t count, hipStream_t s) {
-        host = classify(p) == Mem::Host;
-        if (!host) {
-            ptr = const_cast<T *>(p);
-            return {};
-        }
-        MCMF_TRY(staged.alloc(count, s));
-        ptr = staged.ptr;
-        if (count)
-            MCMF_HIP(hipMemcpyAsync(ptr, p, sizeof(T) * count, hipMemcpyHostToDevice, s));
-        return {};
-    }
-    Status out(T *p, size_t count, hipStream_t s) {
-        host = classify(p) == Mem::Host;
-        if (!host) {
-            ptr = p;
-            return {};
-        }
-        MCMF_TRY(staged.alloc(count, s));
-        ptr = staged.ptr;
-        return {};
-    }
-    Status copy_back(T *p, size_t count, hipStream_t s) {
-        if (host && count)
-            MCMF_HIP(hipMemcpyAsync(p, ptr, sizeof(T) * count, hipMemcpyDeviceToHost, s));
-        return {};
-    }
-};
 
 Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_t N, int32_t K,
                   const mcmf_opts *o, double *out, mcmf_stats *stats) {

@@ -1,0 +1,607 @@
+// Batched execution (mcmf_batch): many diag / action requests as one unit of
+// GPU work.
+//
+// Work items.  A walk task is 64 walks (one wavefront) of one start row of
+// one request; the persistent walk kernel's wavefronts take tasks from the
+// flattened task space of all requests, so requests with few walks per row
+// or few rows do not leave the GPU idle.  Action tasks add their wavefront
+// sum into q[k] (FP64 atomics); diagonal tasks write visit records.  The
+// persistent gather kernel then takes one start row of one diagonal request
+// per iteration (gather_core.hpp).  Diagonal visit records are produced and
+// consumed in chunks bounded by a byte budget; all action tasks ride along in
+// the first chunk's walk launch.
+//
+// Keyed walks: a task draws exactly the Philox counters its request's own
+// mcmf_diag / mcmf_action call would draw, so results agree with those calls
+// up to the order of floating-point additions.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+#include "gather_core.hpp"
+#include "walk_core.hpp"
+
+namespace mcmf {
+
+namespace {
+
+constexpr int kWalkThreads = 256;
+constexpr int kTaskWalks = 64;
+
+enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4 };
+
+// Device descriptor of one request.
+struct BReq {
+    walk::GraphView g;
+    walk::WalkArgs a;
+    int32_t kind; // MCMF_REQ_*
+    int32_t mode; // kMode* bits
+    const int32_t *starts;
+    const double *r;           // action: s A v
+    double *q;                 // action: q per start row
+    uint64_t *digest;          // optional
+    unsigned long long *steps; // this request's step counter
+    const uint8_t *in_set;     // diag subset (null: all rows)
+    double *dacc;              // diag sums
+    int64_t wpp;               // walks per gather pass
+};
+
+// A run of one request's start rows inside a walk launch.
+struct WSeg {
+    int32_t req;
+    uint32_t tasks_per_row;
+    int64_t kk0;        // first start-row index in the request's start list
+    int64_t task_base;  // first task of this run in the launch
+    int64_t slot_base;  // diag: first visit slot of row kk0 in the chunk
+    int64_t xoff;       // diag: byte offset of that slot's value
+};
+
+// A run of one request's start rows inside a gather launch.
+struct GSeg {
+    int32_t req;
+    int64_t kk0;
+    int64_t item_base;
+    int64_t slot_base;
+    int64_t xoff;
+};
+
+template <class WT, bool WEIGHTED, bool CUTOFF>
+__device__ void run_task(const BReq &R, int64_t kk, uint32_t b, int32_t *vstate, WT *vx, int lane) {
+    const uint32_t k = static_cast<uint32_t>(R.starts[kk]);
+    const uint2 rk = R.g.node[k];
+    const int64_t w64 = int64_t(b) * kTaskWalks + lane;
+    const bool active = w64 < R.a.N;
+    uint64_t h = dev::kFnvBasis;
+    unsigned long long ns = 0;
+    if (R.kind == MCMF_REQ_ACTION) {
+        double acc = 0.0;
+        if (active)
+            acc = walk::action_walk<WT, WEIGHTED, true, CUTOFF>(R.g, R.r, R.a, k, rk, R.r[k],
+                                                                 static_cast<uint32_t>(w64), &h, &ns);
+        acc = dev::wave_sum(acc);
+        if (lane == 0 && acc != 0.0)
+            atomicAdd(&R.q[k], acc / static_cast<double>(R.a.N));
+    } else if (active) {
+        walk::diag_walk<WT, WEIGHTED, true, CUTOFF>(R.g, R.a, k, rk, static_cast<uint32_t>(w64),
+                                                     vstate + w64, vx + w64, R.a.N, &h, &ns);
+    }
+    const unsigned long long hs = dev::wave_sum_u64(active ? h : 0ull);
+    const unsigned long long st = dev::wave_sum_u64(ns);
+    if (lane == 0) {
+        if (R.digest)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]), hs);
+        atomicAdd(R.steps, st);
+    }
+}
+
+__global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restrict__ reqs,
+                                                             const WSeg *__restrict__ segs,
+                                                             int n_segs, int64_t n_tasks,
+                                                             int32_t *vstate, unsigned char *vxb) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
+    for (int64_t task = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6); task < n_tasks;
+         task += waves) {
+        int lo = 0, hi = n_segs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].task_base <= task)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const WSeg sg = segs[lo];
+        const BReq &R = reqs[sg.req];
+        const int64_t local = task - sg.task_base;
+        const int64_t rel = local / sg.tasks_per_row;
+        const uint32_t b = static_cast<uint32_t>(local - rel * sg.tasks_per_row);
+        const int64_t span = int64_t(R.a.K - 1) * R.a.N;
+        int32_t *vs = vstate + sg.slot_base + rel * span;
+        switch (R.mode) {
+        case 0: run_task<double, false, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeFp32: run_task<float, false, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeWeighted: run_task<double, true, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeWeighted | kModeFp32: run_task<float, true, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeCutoff: run_task<double, false, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeCutoff | kModeFp32: run_task<float, false, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
+        case kModeCutoff | kModeWeighted: run_task<double, true, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
+        default: run_task<float, true, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
+        }
+    }
+}
+
+template <bool WEIGHTED, class VT>
+__global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
+    const BReq *__restrict__ reqs, const GSeg *__restrict__ segs, int n_segs, int64_t n_items,
+    const int32_t *vstate, const unsigned char *vxb, uint32_t nb, unsigned long long *probes_out) {
+    using namespace gather;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ Batch bt;
+    __shared__ uint32_t scan_scratch[kWaves];
+    __shared__ unsigned long long red[kWaves];
+    const Shared sh = shared_views(smem, nb, &bt, scan_scratch, red);
+    unsigned long long probes = 0;
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        int lo = 0, hi = n_segs;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (segs[mid].item_base <= item)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        const GSeg sg = segs[lo];
+        const BReq &R = reqs[sg.req];
+        const int64_t rel = item - sg.item_base;
+        const int64_t span = int64_t(R.a.K - 1) * R.a.N;
+        RowJob job;
+        job.k = R.starts[sg.kk0 + rel];
+        job.rk = R.g.node[job.k];
+        job.st = vstate + sg.slot_base + rel * span;
+        job.N = R.a.N;
+        job.K = R.a.K;
+        job.walks_per_pass = R.wpp;
+        job.node = R.g.node;
+        job.col = R.g.col;
+        job.val = R.g.val;
+        job.in_set = R.in_set;
+        job.scale = R.a.scale;
+        job.dacc = R.dacc;
+        job.overflow = probes_out + 1;
+        gather_row<WEIGHTED, VT>(sh, job, reinterpret_cast<const VT *>(vxb + sg.xoff) + rel * span,
+                                 probes);
+    }
+    const unsigned long long total = dev::block_sum(probes, red);
+    if (threadIdx.x == 0)
+        atomicAdd(probes_out, total);
+}
+
+// Gather kernel for variant v = (FP32 weights ? 1 : 0) | (weighted ? 2 : 0).
+using GatherKernel = void (*)(const BReq *, const GSeg *, int, int64_t, const int32_t *,
+                              const unsigned char *, uint32_t, unsigned long long *);
+constexpr int kGatherVariants = 4;
+GatherKernel gather_kernel(int v) {
+    switch (v) {
+    case 0: return &k_batch_gather<false, double>;
+    case 1: return &k_batch_gather<false, float>;
+    case 2: return &k_batch_gather<true, double>;
+    default: return &k_batch_gather<true, float>;
+    }
+}
+
+// Host-side state of one request.
+struct Prep {
+    mcmf_request *req = nullptr;
+    std::vector<double> c;
+    DevBuf<double> coef, r, q, dacc;
+    DevBuf<uint8_t> in_set, start_flags;
+    DevBuf<int32_t> start_list;
+    View<double> vin, out;
+    View<int32_t> rows;
+    View<uint64_t> dig;
+    const int32_t *starts = nullptr;
+    int64_t n_start = 0;
+    int64_t count = 0; // outputs
+    bool all = false;
+};
+
+Status check_request(mcmf_request &q) {
+    mcmf_opts o = {};
+    o.precision = q.precision;
+    o.weight_cutoff = q.weight_cutoff;
+    MCMF_TRY(check_common(q.graph, &q.fn, q.n_walks, q.K, &o));
+    if (!q.out)
+        return fail(MCMF_E_ARG, "request output is NULL");
+    if (q.kind == MCMF_REQ_ACTION) {
+        if (!q.v)
+            return fail(MCMF_E_ARG, "action request without v");
+        if (q.v == q.out)
+            return fail(MCMF_E_ARG, "out may not alias v");
+    } else if (q.kind == MCMF_REQ_DIAG) {
+        if (!q.graph->symmetric)
+            return fail(MCMF_E_NOT_SYMMETRIC, "diag request on a graph not created with MCMF_SYMMETRIC");
+        if (q.rows && q.n_rows < 0)
+            return fail(MCMF_E_ARG, "n_rows is negative");
+    } else {
+        return fail(MCMF_E_ARG, "unknown request kind %d", q.kind);
+    }
+    return {};
+}
+
+Status prepare(Prep &P, hipStream_t s) {
+    mcmf_request &q = *P.req;
+    const mcmf_graph *g = q.graph;
+    const int64_t n = g->n;
+    P.c.resize(q.K + 1);
+    MCMF_TRY(make_coeffs(&q.fn, q.K, P.c.data()));
+    if (q.K >= 2) {
+        MCMF_TRY(P.coef.alloc(q.K - 1, s));
+        MCMF_HIP(hipMemcpyAsync(P.coef.ptr, P.c.data() + 2, sizeof(double) * (q.K - 1),
+                                hipMemcpyHostToDevice, s));
+    }
+    if (q.path_digest) {
+        MCMF_TRY(P.dig.out(q.path_digest, n, s));
+    }
+    if (q.kind == MCMF_REQ_ACTION) {
+        P.count = n;
+        MCMF_TRY(P.vin.in(q.v, n, s));
+        MCMF_TRY(P.out.out(q.out, n, s));
+        MCMF_TRY(P.r.alloc(n > 0 ? n : 1, s));
+        MCMF_TRY(spmv_r(g, P.vin.ptr, q.fn.scale, P.r.ptr, s));
+        if (q.K >= 2) {
+            MCMF_TRY(P.q.alloc(n > 0 ? n : 1, s));
+            P.starts = g->active;
+            P.n_start = g->n_active;
+        }
+        return {};
+    }
+    P.all = q.rows == nullptr;
+    P.count = P.all ? n : q.n_rows;
+    MCMF_TRY(P.out.out(q.out, P.count, s));
+    if (!P.all) {
+        MCMF_TRY(P.rows.in(q.rows, P.count, s));
+        MCMF_TRY(P.in_set.alloc(n > 0 ? n : 1, s));
+        MCMF_TRY(fill_u8(P.in_set.ptr, 0, n, s));
+        DevBuf<int> bad;
+        MCMF_TRY(bad.alloc(1, s));
+        MCMF_TRY(fill_i32(bad.ptr, 0, 1, s));
+        MCMF_TRY(mark_rows(P.rows.ptr, P.count, n, P.in_set.ptr, bad.ptr, s));
+        int hbad = 0;
+        MCMF_HIP(hipMemcpyAsync(&hbad, bad.ptr, sizeof hbad, hipMemcpyDeviceToHost, s));
+        MCMF_HIP(hipStreamSynchronize(s));
+        if (hbad)
+            return fail(MCMF_E_ARG, "a requested row lies outside [0, %lld)", static_cast<long long>(n));
+    }
+    if (q.K >= 2) {
+        MCMF_TRY(P.dacc.alloc(n > 0 ? n : 1, s));
+        if (P.all) {
+            P.starts = g->active;
+            P.n_start = g->n_active;
+        } else if (P.count > 0) {
+            MCMF_TRY(P.start_flags.alloc(n > 0 ? n : 1, s));
+            MCMF_TRY(P.start_list.alloc(n > 0 ? n : 1, s));
+            MCMF_TRY(fill_u8(P.start_flags.ptr, 0, n, s));
+            MCMF_TRY(mark_starts(g, P.rows.ptr, P.count, P.start_flags.ptr, s));
+            MCMF_TRY(compact(P.start_flags.ptr, n, 1, P.start_list.ptr, &P.n_start, s));
+            P.starts = P.start_list.ptr;
+        }
+    }
+    return {};
+}
+
+Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, mcmf_stats *stats) {
+    if (n_reqs < 0 || (n_reqs > 0 && !reqs))
+        return fail(MCMF_E_ARG, "bad request array");
+    if (o) {
+        if (o->reserved0)
+            return fail(MCMF_E_ARG, "reserved option words must be zero");
+        for (uint32_t r : o->reserved)
+            if (r)
+                return fail(MCMF_E_ARG, "reserved option words must be zero");
+    }
+    for (int64_t i = 0; i < n_reqs; ++i)
+        reqs[i].status = MCMF_OK;
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        Status st = check_request(reqs[i]);
+        if (st) {
+            reqs[i].status = st.code;
+            return st;
+        }
+    }
+    if (n_reqs == 0)
+        return {};
+    const int device = reqs[0].graph->device;
+    for (int64_t i = 0; i < n_reqs; ++i)
+        if (reqs[i].graph->device != device)
+            return fail(MCMF_E_ARG, "all requests of a batch must use graphs on one device");
+    MCMF_HIP(hipSetDevice(device));
+    hipStream_t s = (o && o->stream) ? static_cast<hipStream_t>(o->stream) : reqs[0].graph->stream;
+    const bool use_graph = o && o->use_graph;
+
+    std::vector<std::unique_ptr<Prep>> preps(n_reqs);
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        preps[i].reset(new Prep());
+        preps[i]->req = &reqs[i];
+        Status st = prepare(*preps[i], s);
+        if (st) {
+            reqs[i].status = st.code;
+            return st;
+        }
+    }
+
+    // Descriptors.
+    std::vector<BReq> hreq(n_reqs);
+    int64_t max_visit_row = 0;
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        const mcmf_request &q = reqs[i];
+        Prep &P = *preps[i];
+        BReq &B = hreq[i];
+        memset(&B, 0, sizeof B);
+        B.g = walk::view(q.graph);
+        mcmf_opts oo = {};
+        oo.seed = q.seed;
+        oo.request_id = q.request_id;
+        oo.precision = q.precision;
+        oo.weight_cutoff = q.weight_cutoff;
+        B.a = walk::to_args(walk_params(&oo, P.coef.ptr, q.K, q.fn.scale, q.n_walks));
+        B.kind = q.kind;
+        B.mode = (q.precision == MCMF_PRECISION_FP32_WEIGHTS ? kModeFp32 : 0) |
+                 (q.graph->weighted ? kModeWeighted : 0) | (q.weight_cutoff > 0.0 ? kModeCutoff : 0);
+        B.starts = P.starts;
+        B.r = P.r.ptr;
+        B.q = P.q.ptr;
+        B.digest = P.dig.ptr;
+        B.in_set = P.all ? nullptr : P.in_set.ptr;
+        B.dacc = P.dacc.ptr;
+        if (q.kind == MCMF_REQ_DIAG && q.K >= 2)
+            max_visit_row = std::max<int64_t>(max_visit_row, q.n_walks * (q.K - 1));
+    }
+    DevBuf<unsigned long long> counters; // per request steps, then probes, overflow
+    MCMF_TRY(counters.alloc(n_reqs + 2, s));
+    for (int64_t i = 0; i < n_reqs; ++i)
+        hreq[i].steps = counters.ptr + i;
+
+    // Gather plan: one table size for the whole batch, walks per pass per request.
+    const size_t table_lds = 160 * 1024 - gather::kStaticLds;
+    uint32_t nb = 0;
+    size_t lds = 0;
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        const mcmf_request &q = reqs[i];
+        if (q.kind != MCMF_REQ_DIAG || q.K < 2 || preps[i]->n_start == 0)
+            continue;
+        GatherPlan plan = plan_gather(q.graph->n, q.n_walks, q.K, table_lds,
+                                      sizeof(uint32_t) * gather::kFilterWords, gather::kSlots);
+        if (!plan.ok)
+            return fail(MCMF_E_UNSUPPORTED, "no Q_k table layout fits LDS for N=%lld, K=%d",
+                        static_cast<long long>(q.n_walks), q.K);
+        hreq[i].wpp = plan.walks_per_pass;
+        if (plan.cap / gather::kSlots > nb) {
+            nb = static_cast<uint32_t>(plan.cap / gather::kSlots);
+            lds = plan.lds_bytes;
+        }
+    }
+    DevBuf<BReq> dreq;
+    MCMF_TRY(dreq.alloc(n_reqs, s));
+    MCMF_HIP(hipMemcpyAsync(dreq.ptr, hreq.data(), sizeof(BReq) * n_reqs, hipMemcpyHostToDevice, s));
+
+    // Launch plan: chunk 0 = every action task + the first diag rows; later
+    // chunks = diag rows only.  Each chunk holds at most `budget` bytes of
+    // visit records.
+    int64_t budget = int64_t(2) << 30;
+    if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
+        budget = std::max<int64_t>(1, strtoll(e, nullptr, 10));
+    // Gather runs are kept per kernel variant (one launch each).
+    struct Chunk {
+        std::vector<WSeg> w;
+        std::vector<GSeg> gs[kGatherVariants];
+        int64_t items[kGatherVariants] = {0, 0, 0, 0};
+        int64_t tasks = 0, rows = 0, slots = 0, xbytes = 0;
+    };
+    std::vector<Chunk> chunks(1);
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        const mcmf_request &q = reqs[i];
+        if (q.kind != MCMF_REQ_ACTION || q.K < 2 || preps[i]->n_start == 0)
+            continue;
+        const uint32_t tpr = static_cast<uint32_t>((q.n_walks + kTaskWalks - 1) / kTaskWalks);
+        Chunk &c = chunks[0];
+        c.w.push_back(WSeg{static_cast<int32_t>(i), tpr, 0, c.tasks, 0, 0});
+        c.tasks += preps[i]->n_start * tpr;
+    }
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        const mcmf_request &q = reqs[i];
+        if (q.kind != MCMF_REQ_DIAG || q.K < 2 || preps[i]->n_start == 0)
+            continue;
+        const int64_t span = q.n_walks * (q.K - 1);
+        const int64_t xb = q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
+        const int64_t row_bytes = span * (4 + xb);
+        const uint32_t tpr = static_cast<uint32_t>((q.n_walks + kTaskWalks - 1) / kTaskWalks);
+        const int var = (q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 1 : 0) | (q.graph->weighted ? 2 : 0);
+        int64_t kk = 0;
+        while (kk < preps[i]->n_start) {
+            Chunk &c = chunks.back();
+            const int64_t used = c.slots * 4 + c.xbytes + 8;
+            int64_t fit = (budget - used) / row_bytes;
+            if (fit < 1 && c.rows > 0) {
+                chunks.emplace_back();
+                continue;
+            }
+            fit = std::max<int64_t>(fit, 1);
+            const int64_t take = std::min(fit, preps[i]->n_start - kk);
+            // Value arrays are 8-byte aligned per run.
+            c.xbytes = (c.xbytes + 7) & ~int64_t(7);
+            c.w.push_back(WSeg{static_cast<int32_t>(i), tpr, kk, c.tasks, c.slots, c.xbytes});
+            c.gs[var].push_back(GSeg{static_cast<int32_t>(i), kk, c.items[var], c.slots, c.xbytes});
+            c.tasks += take * tpr;
+            c.items[var] += take;
+            c.rows += take;
+            c.slots += take * span;
+            c.xbytes += take * span * xb;
+            kk += take;
+        }
+    }
+    int64_t max_slots = 0, max_xbytes = 0;
+    for (const Chunk &c : chunks) {
+        max_slots = std::max(max_slots, c.slots);
+        max_xbytes = std::max(max_xbytes, c.xbytes);
+    }
+    DevBuf<int32_t> vstate;
+    DevBuf<unsigned char> vxb;
+    MCMF_TRY(vstate.alloc(max_slots > 0 ? max_slots : 1, s));
+    MCMF_TRY(vxb.alloc(max_xbytes > 0 ? max_xbytes : 8, s));
+    std::vector<std::unique_ptr<DevBuf<WSeg>>> dws;
+    std::vector<std::unique_ptr<DevBuf<GSeg>>> dgs;
+    for (const Chunk &c : chunks) {
+        dws.emplace_back(new DevBuf<WSeg>());
+        if (!c.w.empty()) {
+            MCMF_TRY(dws.back()->alloc(c.w.size(), s));
+            MCMF_HIP(hipMemcpyAsync(dws.back()->ptr, c.w.data(), sizeof(WSeg) * c.w.size(),
+                                    hipMemcpyHostToDevice, s));
+        }
+        for (int v = 0; v < kGatherVariants; ++v) {
+            dgs.emplace_back(new DevBuf<GSeg>());
+            if (c.gs[v].empty())
+                continue;
+            MCMF_TRY(dgs.back()->alloc(c.gs[v].size(), s));
+            MCMF_HIP(hipMemcpyAsync(dgs.back()->ptr, c.gs[v].data(), sizeof(GSeg) * c.gs[v].size(),
+                                    hipMemcpyHostToDevice, s));
+        }
+    }
+    if (nb > 0)
+        for (int v = 0; v < kGatherVariants; ++v)
+            MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gather_kernel(v)),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+
+    // The device work of the batch: fills, walks, gathers, assembly.
+    const int64_t walk_blocks_cap = int64_t(num_cus()) * 16;
+    auto enqueue = [&]() -> Status {
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, n_reqs + 2, s));
+        for (int64_t i = 0; i < n_reqs; ++i) {
+            Prep &P = *preps[i];
+            const int64_t n = reqs[i].graph->n;
+            if (P.q.ptr)
+                MCMF_TRY(fill_f64(P.q.ptr, 0.0, n, s));
+            if (P.dacc.ptr)
+                MCMF_TRY(fill_f64(P.dacc.ptr, 0.0, n, s));
+            if (P.dig.ptr)
+                MCMF_TRY(fill_u64(P.dig.ptr, 0, n, s));
+        }
+        for (size_t ci = 0; ci < chunks.size(); ++ci) {
+            const Chunk &c = chunks[ci];
+            if (c.tasks > 0) {
+                const int64_t blocks = std::min<int64_t>(walk_blocks_cap, (c.tasks + 3) / 4);
+                hipLaunchKernelGGL(k_batch_walk, dim3(static_cast<uint32_t>(blocks)), dim3(kWalkThreads), 0,
+                                   s, dreq.ptr, dws[ci]->ptr, static_cast<int>(c.w.size()), c.tasks,
+                                   vstate.ptr, vxb.ptr);
+                MCMF_HIP(hipGetLastError());
+            }
+            for (int v = 0; v < kGatherVariants; ++v) {
+                if (c.items[v] == 0)
+                    continue;
+                const int64_t blocks = std::min<int64_t>(int64_t(1) << 20, c.items[v]);
+                hipLaunchKernelGGL(gather_kernel(v), dim3(static_cast<uint32_t>(blocks)),
+                                   dim3(gather::kGatherThreads), lds, s, dreq.ptr,
+                                   dgs[ci * kGatherVariants + v]->ptr, static_cast<int>(c.gs[v].size()),
+                                   c.items[v], vstate.ptr, vxb.ptr, nb, counters.ptr + n_reqs);
+                MCMF_HIP(hipGetLastError());
+            }
+        }
+        for (int64_t i = 0; i < n_reqs; ++i) {
+            const mcmf_request &q = reqs[i];
+            Prep &P = *preps[i];
+            const double c1 = q.K >= 1 ? P.c[1] : 0.0;
+            if (q.kind == MCMF_REQ_ACTION)
+                MCMF_TRY(spmv_assemble(q.graph, P.vin.ptr, P.r.ptr, q.K >= 2 ? P.q.ptr : nullptr,
+                                       P.c[0], c1, q.fn.scale, P.out.ptr, s));
+            else
+                MCMF_TRY(diag_finish(q.graph, P.all ? nullptr : P.rows.ptr, P.count, q.K, P.c[0], c1,
+                                     q.fn.scale, P.dacc.ptr, P.out.ptr, s));
+        }
+        return {};
+    };
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+        MCMF_HIP(hipEventCreate(&e0));
+        MCMF_HIP(hipEventCreate(&e1));
+        MCMF_HIP(hipEventRecord(e0, s));
+    }
+    if (use_graph) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        MCMF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        Status st = enqueue();
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (st) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return st;
+        }
+        MCMF_HIP(ce);
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            MCMF_HIP(ie);
+        }
+        hipError_t le = hipGraphLaunch(exec, s);
+        hipError_t se = hipStreamSynchronize(s);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        MCMF_HIP(le);
+        MCMF_HIP(se);
+    } else {
+        MCMF_TRY(enqueue());
+    }
+    if (stats)
+        MCMF_HIP(hipEventRecord(e1, s));
+
+    // Results back to host buffers; counters.
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        Prep &P = *preps[i];
+        MCMF_TRY(P.out.copy_back(reqs[i].out, P.count, s));
+        if (reqs[i].path_digest)
+            MCMF_TRY(P.dig.copy_back(reqs[i].path_digest, reqs[i].graph->n, s));
+    }
+    std::vector<unsigned long long> hc(n_reqs + 2, 0);
+    MCMF_HIP(hipMemcpyAsync(hc.data(), counters.ptr, sizeof(unsigned long long) * (n_reqs + 2),
+                            hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    if (hc[n_reqs + 1] != 0)
+        return fail(MCMF_E_DEVICE, "internal error: a Q_k table overflowed (%llu inserts lost)",
+                    hc[n_reqs + 1]);
+    uint64_t steps = 0, walks = 0, starts = 0;
+    for (int64_t i = 0; i < n_reqs; ++i) {
+        reqs[i].walk_steps = hc[i];
+        steps += hc[i];
+        if (reqs[i].K >= 2) {
+            starts += preps[i]->n_start;
+            walks += preps[i]->n_start * reqs[i].n_walks;
+        }
+    }
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        stats->start_rows = starts;
+        stats->walks = walks;
+        stats->walk_steps = steps;
+        stats->gather_probes = hc[n_reqs];
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            (void)hipGetLastError();
+        stats->ms_total = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return {};
+}
+
+} // namespace
+
+} // namespace mcmf
+
+extern "C" mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *opts,
+                                  mcmf_stats *stats) {
+    mcmf::clear_error();
+    return mcmf::run_batch(reqs, n_reqs, opts, stats).code;
+}

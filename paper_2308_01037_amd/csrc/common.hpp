@@ -82,6 +82,41 @@ struct DevBuf {
     }
 };
 
+// Device view of a caller array: the array itself or a staged copy.
+template <class T>
+struct View {
+    T *ptr = nullptr;
+    DevBuf<T> staged;
+    bool host = false;
+    Status in(const T *p, size_t count, hipStream_t s) {
+        host = classify(p) == Mem::Host;
+        if (!host) {
+            ptr = const_cast<T *>(p);
+            return {};
+        }
+        MCMF_TRY(staged.alloc(count, s));
+        ptr = staged.ptr;
+        if (count)
+            MCMF_HIP(hipMemcpyAsync(ptr, p, sizeof(T) * count, hipMemcpyHostToDevice, s));
+        return {};
+    }
+    Status out(T *p, size_t count, hipStream_t s) {
+        host = classify(p) == Mem::Host;
+        if (!host) {
+            ptr = p;
+            return {};
+        }
+        MCMF_TRY(staged.alloc(count, s));
+        ptr = staged.ptr;
+        return {};
+    }
+    Status copy_back(T *p, size_t count, hipStream_t s) {
+        if (host && count)
+            MCMF_HIP(hipMemcpyAsync(p, ptr, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+        return {};
+    }
+};
+
 // Coefficients c_0..c_K of the function family (host, FP64, in sequence).
 Status make_coeffs(const mcmf_fn *f, int K, double *c);
 

@@ -1,191 +1,13 @@
-// RandFunmDiag gather (Section 3.3, Eq. rand_funm_formula_diag): one
-// 1024-thread workgroup per start row k.
-//
-//  1. Q_k is built in LDS from the row's visit records: open addressing over
-//     8-slot buckets (keys int32, values FP64, LDS atomics on insert) and a
-//     blocked three-bit filter that rejects most absent keys with one LDS
-//     read.  A lookup reads a whole bucket (two 16-byte reads) per step.
-//  2. The columns C_i (= row i, A is symmetric) of the requested neighbours i
-//     of k, 256 neighbours at a time, are cut into chunks of kChunk entries.
-//     A group of 16 lanes takes one chunk (8 entries per lane, coalesced, all
-//     loads in flight together), probes Q_k for each entry, sums over the
-//     group and adds the sum into the neighbour's LDS total; after the batch
-//     each neighbour's total goes out with one FP64 atomic:
-//         dacc[i] += s a_ki * s <Q_k, C_i> / N.
-//  When the row's visits cannot fit the table at once, the walks are taken
-//  in passes (Q_k is linear in the walks) and the gather repeats per pass.
-#include "device.hpp"
-#include "ops.hpp"
-#include "plan.hpp"
+// Diagonal gather kernel of the single-request path: one 1024-thread
+// workgroup per start row; the per-row work is gather::gather_row
+// (gather_core.hpp).
+#include "gather_core.hpp"
 
 namespace mcmf {
 
 namespace {
 
-constexpr int kGatherThreads = 1024;
-constexpr int kWaves = kGatherThreads / 64;
-constexpr uint32_t kFilterLog2Words = 11; // 2048 words = 8 KiB
-constexpr uint32_t kFilterWords = 1u << kFilterLog2Words;
-constexpr int kBatch = 256;                // neighbours per batch
-constexpr int kGroup = 16;                 // lanes per chunk
-constexpr int kPerLane = 8;                // entries per lane per chunk
-constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
-constexpr int kGroups = kGatherThreads / kGroup;
-constexpr int kSlots = 8;                  // slots per bucket
-constexpr int32_t kEmpty = -1;
-
-__device__ __forceinline__ uint32_t mix32(uint32_t x) {
-    // Multiply-xorshift integer hash (the finaliser of MurmurHash3).
-    x ^= x >> 16;
-    x *= 0x85EBCA6Bu;
-    x ^= x >> 13;
-    x *= 0xC2B2AE35u;
-    x ^= x >> 16;
-    return x;
-}
-
-struct Table {
-    int32_t *keys; // nb buckets x kSlots slots, 32-byte aligned
-    double *vals;
-    uint32_t *filter;
-    uint32_t nb;
-
-    // Multiplicative hashing: node ids of the graphs here carry no structure
-    // that a multiply-shift hash would keep.
-    __device__ __forceinline__ uint32_t bucket_of(int32_t key) const {
-        return __umulhi(static_cast<uint32_t>(key) * 0x85EBCA77u, nb);
-    }
-    __device__ __forceinline__ static uint32_t fhash(int32_t key) {
-        return static_cast<uint32_t>(key) * 0x9E3779B1u;
-    }
-    // Top bits pick the filter word, three 5-bit fields below them the bits.
-    __device__ __forceinline__ static uint32_t filter_word(uint32_t h) {
-        return h >> (32 - kFilterLog2Words);
-    }
-    __device__ __forceinline__ static uint32_t filter_mask(uint32_t h) {
-        return (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31)) | (1u << (h & 31));
-    }
-
-    // Returns false only if every bucket is full (the plan rules that out).
-    __device__ bool insert(int32_t key, double x) {
-        const uint32_t h = fhash(key);
-        atomicOr(&filter[filter_word(h)], filter_mask(h));
-        uint32_t b = bucket_of(key);
-        for (uint32_t tries = 0; tries < nb; ++tries) {
-#pragma unroll
-            for (int j = 0; j < kSlots; ++j) {
-                const uint32_t s = kSlots * b + j;
-                const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
-                if (prev == kEmpty || prev == key) {
-                    atomicAdd(&vals[s], x);
-                    return true;
-                }
-            }
-            b = (b + 1 == nb) ? 0 : b + 1;
-        }
-        return false;
-    }
-
-    // Value of key in bucket b, or: 0 with *more = false when the key is absent
-    // (an empty slot ends the probe sequence), *more = true when the bucket is
-    // full without it (continue with the next bucket).
-    __device__ __forceinline__ double probe_bucket(int32_t key, uint32_t b, bool *more) const {
-        const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
-        const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
-        int j = -1;
-        j = (lo.x == key) ? 0 : j;
-        j = (lo.y == key) ? 1 : j;
-        j = (lo.z == key) ? 2 : j;
-        j = (lo.w == key) ? 3 : j;
-        j = (hi.x == key) ? 4 : j;
-        j = (hi.y == key) ? 5 : j;
-        j = (hi.z == key) ? 6 : j;
-        j = (hi.w == key) ? 7 : j;
-        *more = false;
-        if (j >= 0)
-            return vals[kSlots * b + j];
-        *more = hi.w != kEmpty; // slots fill in order: the last one is the test
-        return 0.0;
-    }
-
-    // Lookup of N keys stage by stage so that their LDS reads overlap: all
-    // filter words, then the home buckets and values in two halves (to bound
-    // register use), then the rare keys that need further buckets.
-    // key < 0 means "no key" (result 0).
-    template <int N>
-    __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
-        static_assert(N % 2 == 0, "N must be even");
-        constexpr int H = N / 2;
-        uint32_t fw[N], m[N];
-#pragma unroll
-        for (int u = 0; u < N; ++u) {
-            const uint32_t h = fhash(key[u]);
-            m[u] = filter_mask(h);
-            fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
-        }
-        uint32_t pending = 0;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            // Every lane issues its reads; lanes without a candidate read bucket
-            // 0, one address the LDS serves as a broadcast.
-            bool cand[H];
-            uint32_t b[H];
-            int4 lo[H], hi[H];
-#pragma unroll
-            for (int v = 0; v < H; ++v) {
-                const int u = half * H + v;
-                cand[v] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
-                b[v] = cand[v] ? bucket_of(key[u]) : 0u;
-                lo[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v]);
-                hi[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v] + 4);
-            }
-            int slot[H];
-#pragma unroll
-            for (int v = 0; v < H; ++v) {
-                const int u = half * H + v;
-                const int32_t k = key[u];
-                int j = -1;
-                j = (lo[v].x == k) ? 0 : j;
-                j = (lo[v].y == k) ? 1 : j;
-                j = (lo[v].z == k) ? 2 : j;
-                j = (lo[v].w == k) ? 3 : j;
-                j = (hi[v].x == k) ? 4 : j;
-                j = (hi[v].y == k) ? 5 : j;
-                j = (hi[v].z == k) ? 6 : j;
-                j = (hi[v].w == k) ? 7 : j;
-                j = cand[v] ? j : -1;
-                // Slots fill in order, so a full bucket ends with a used last slot.
-                pending |= (cand[v] && j < 0 && hi[v].w != kEmpty) ? (1u << u) : 0u;
-                slot[v] = j;
-            }
-            double got[H];
-#pragma unroll
-            for (int v = 0; v < H; ++v)
-                got[v] = vals[slot[v] >= 0 ? kSlots * b[v] + slot[v] : 0u];
-#pragma unroll
-            for (int v = 0; v < H; ++v)
-                out[half * H + v] = slot[v] >= 0 ? got[v] : 0.0;
-        }
-        while (pending) {
-            const int u = __ffs(pending) - 1;
-            pending &= pending - 1;
-            int32_t kx = key[0];
-#pragma unroll
-            for (int v = 1; v < N; ++v)
-                kx = (v == u) ? key[v] : kx;
-            uint32_t bx = bucket_of(kx);
-            double r = 0.0;
-            bool more = true;
-            for (uint32_t tries = 1; more && tries < nb; ++tries) {
-                bx = (bx + 1 == nb) ? 0 : bx + 1;
-                r = probe_bucket(kx, bx, &more);
-            }
-#pragma unroll
-            for (int v = 0; v < N; ++v)
-                out[v] = (v == u) ? r : out[v];
-        }
-    }
-};
+using namespace gather;
 
 struct GatherArgs {
     const uint2 *node;
@@ -206,175 +28,31 @@ struct GatherArgs {
     unsigned long long *overflow; // set if a table ever fills (a planning error)
 };
 
-// Per-batch neighbour metadata in LDS.
-struct Batch {
-    uint32_t prefix[kBatch + 1]; // first chunk of each neighbour's column
-    uint32_t start[kBatch];      // first entry of the column in col[]
-    uint32_t len[kBatch];        // column length
-    int32_t row[kBatch];         // neighbour i (-1: not requested)
-    double aki[kBatch];          // s * a_ki
-    double sum[kBatch];          // <Q_k, C_i> partial sums
-};
-
 template <bool WEIGHTED, class VT>
 __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Batch bt;
     __shared__ uint32_t scan_scratch[kWaves];
     __shared__ unsigned long long red[kWaves];
-    Table tab;
-    tab.nb = a.nb;
-    const uint32_t cap = kSlots * a.nb;
-    tab.vals = reinterpret_cast<double *>(smem);
-    tab.keys = reinterpret_cast<int32_t *>(smem + sizeof(double) * cap);
-    tab.filter = reinterpret_cast<uint32_t *>(smem + sizeof(double) * cap + sizeof(int32_t) * cap);
+    const Shared sh = shared_views(smem, a.nb, &bt, scan_scratch, red);
     const int64_t span = int64_t(a.K - 1) * a.N;
-    const double inv_n = 1.0 / static_cast<double>(a.N);
     unsigned long long probes = 0;
-
+    RowJob job;
+    job.N = a.N;
+    job.K = a.K;
+    job.walks_per_pass = a.walks_per_pass;
+    job.node = a.node;
+    job.col = a.col;
+    job.val = a.val;
+    job.in_set = a.in_set;
+    job.scale = a.scale;
+    job.dacc = a.dacc;
+    job.overflow = a.overflow;
     for (int64_t kk = blockIdx.x; kk < a.n_start; kk += gridDim.x) {
-        const int32_t k = a.starts[kk];
-        const uint2 rk = a.node[k];
-        const int32_t *st = a.vstate + kk * span;
-        const VT *xs = static_cast<const VT *>(a.vx) + kk * span;
-        for (int64_t w0 = 0; w0 < a.N; w0 += a.walks_per_pass) {
-            const int64_t nw = (a.N - w0 < a.walks_per_pass) ? (a.N - w0) : a.walks_per_pass;
-            // (1) Q_k from walks [w0, w0 + nw).
-            __syncthreads();
-            for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
-                tab.keys[i] = kEmpty;
-                tab.vals[i] = 0.0;
-            }
-            for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
-                tab.filter[i] = 0u;
-            __syncthreads();
-            const int64_t count = nw * (a.K - 1);
-            if (nw == a.N) {
-                // Step 0 of every walk sits at k: insert the sum of those visits once
-                // instead of N colliding atomic updates of one slot.
-                double x0 = 0.0;
-                for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
-                    x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
-                x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
-                if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
-                    atomicAdd(a.overflow, 1ull);
-                for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
-                    const int32_t s = st[i];
-                    if (s >= 0 && !tab.insert(s, static_cast<double>(xs[i])))
-                        atomicAdd(a.overflow, 1ull);
-                }
-            } else {
-                for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
-                    const int64_t t = i / nw;
-                    const int64_t slot = t * a.N + w0 + (i - t * nw);
-                    const int32_t s = st[slot];
-                    if (s >= 0 && !tab.insert(s, static_cast<double>(xs[slot])))
-                        atomicAdd(a.overflow, 1ull);
-                }
-            }
-            // (2) columns of the requested neighbours, kBatch neighbours at a time.
-            for (uint32_t p0 = 0; p0 < rk.y; p0 += kBatch) {
-                const uint32_t m = (rk.y - p0 < uint32_t(kBatch)) ? rk.y - p0 : uint32_t(kBatch);
-                __syncthreads(); // table complete / previous batch flushed
-                uint32_t nchunks = 0;
-                if (threadIdx.x < kBatch) {
-                    const int t = threadIdx.x;
-                    bt.sum[t] = 0.0;
-                    bt.row[t] = -1;
-                    bt.len[t] = 0;
-                    if (uint32_t(t) < m) {
-                        const int64_t e = int64_t(rk.x) + p0 + t;
-                        const int32_t i = a.col[e];
-                        if (!a.in_set || a.in_set[i]) {
-                            const uint2 ri = a.node[i];
-                            nchunks = (ri.y + kChunk - 1) / kChunk;
-                            bt.start[t] = ri.x;
-                            bt.len[t] = ri.y;
-                            bt.row[t] = i;
-                            bt.aki[t] = a.scale * (WEIGHTED ? a.val[e] : 1.0);
-                        }
-                    }
-                }
-                uint32_t total = 0;
-                const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
-                if (threadIdx.x < kBatch)
-                    bt.prefix[threadIdx.x] = before;
-                if (threadIdx.x == 0)
-                    bt.prefix[kBatch] = total;
-                __syncthreads();
-                // Group g takes the contiguous chunk range [g*per, (g+1)*per) and
-                // walks the neighbours forward, so the owner is searched once.
-                const int group = threadIdx.x / kGroup;
-                const int gl = threadIdx.x % kGroup;
-                const uint32_t per = (total + kGroups - 1) / kGroups;
-                const uint32_t c_begin = group * per;
-                const uint32_t c_end = (c_begin + per < total) ? c_begin + per : total;
-                if (c_begin < c_end) {
-                    int r = 0, hi = kBatch;
-                    while (hi - r > 1) {
-                        const int mid = (r + hi) >> 1;
-                        if (bt.prefix[mid] <= c_begin)
-                            r = mid;
-                        else
-                            hi = mid;
-                    }
-                    uint32_t next = bt.prefix[r + 1];
-                    uint32_t len = bt.len[r];
-                    int64_t base = int64_t(bt.start[r]);
-                    uint32_t first_chunk = bt.prefix[r];
-                    double acc = 0.0;
-                    for (uint32_t c = c_begin; c < c_end; ++c) {
-                        if (c >= next) {
-                            // Row change: flush the finished neighbour's partial sum.
-                            const double g = dev::group_sum<kGroup>(acc);
-                            if (gl == 0 && g != 0.0)
-                                atomicAdd(&bt.sum[r], g);
-                            acc = 0.0;
-                            do {
-                                ++r;
-                                next = bt.prefix[r + 1];
-                            } while (c >= next);
-                            len = bt.len[r];
-                            base = int64_t(bt.start[r]);
-                            first_chunk = bt.prefix[r];
-                        }
-                        const uint32_t off0 = (c - first_chunk) * kChunk;
-                        const uint32_t first = off0 + gl;
-                        int32_t key[kPerLane];
-                        double wv[kPerLane];
-                        if (off0 + kChunk <= len) {
-#pragma unroll
-                            for (int u = 0; u < kPerLane; ++u) {
-                                key[u] = a.col[base + first + u * kGroup];
-                                wv[u] = WEIGHTED ? a.val[base + first + u * kGroup] : 1.0;
-                            }
-                            probes += gl == 0 ? kChunk : 0;
-                        } else {
-#pragma unroll
-                            for (int u = 0; u < kPerLane; ++u) {
-                                const uint32_t off = first + u * kGroup;
-                                key[u] = off < len ? a.col[base + off] : -1;
-                                wv[u] = (WEIGHTED && off < len) ? a.val[base + off] : 1.0;
-                            }
-                            probes += gl == 0 ? len - off0 : 0;
-                        }
-                        double qv[kPerLane];
-                        tab.lookup_n<kPerLane>(key, qv);
-#pragma unroll
-                        for (int u = 0; u < kPerLane; ++u)
-                            acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
-                    }
-                    const double g = dev::group_sum<kGroup>(acc);
-                    if (gl == 0 && g != 0.0)
-                        atomicAdd(&bt.sum[r], g);
-                }
-                __syncthreads();
-                if (threadIdx.x < m && bt.row[threadIdx.x] >= 0) {
-                    const int t = threadIdx.x;
-                    atomicAdd(&a.dacc[bt.row[t]], bt.aki[t] * (a.scale * bt.sum[t]) * inv_n);
-                }
-            }
-        }
+        job.k = a.starts[kk];
+        job.rk = a.node[job.k];
+        job.st = a.vstate + kk * span;
+        gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + kk * span, probes);
     }
     if (a.probes) {
         const unsigned long long total = dev::block_sum(probes, red);
@@ -404,9 +82,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
     a.scale = p.scale;
     a.dacc = dacc;
     a.probes = probes;
-    const size_t static_lds = sizeof(Batch) + sizeof(uint32_t) * kWaves +
-                              sizeof(unsigned long long) * kWaves + 512;
-    const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - static_lds,
+    const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - kStaticLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);
     if (!plan.ok)
         return fail(MCMF_E_UNSUPPORTED, "no Q_k table layout fits LDS for N=%lld, K=%d",

@@ -1,0 +1,399 @@
+// Device-side core of the diagonal gather (Section 3.3, Eq.
+// rand_funm_formula_diag) for one start row k, shared by the single-request
+// and the batched gather kernels.
+//
+//  1. Q_k is built in LDS from the row's visit records: open addressing over
+//     8-slot buckets (keys int32, values FP64, LDS atomics on insert) and a
+//     blocked three-bit filter that rejects most absent keys with one LDS
+//     read.  A lookup reads a whole bucket (two 16-byte reads) per step.
+//  2. The columns C_i (= row i, A is symmetric) of the requested neighbours i
+//     of k, 256 neighbours at a time, are cut into chunks of kChunk entries.
+//     A group of 16 lanes takes a contiguous range of chunks (8 entries per
+//     lane, coalesced, all loads in flight together), probes Q_k for each
+//     entry, sums over the group and adds the sum into the neighbour's LDS
+//     total; after the batch each neighbour's total goes out with one FP64
+//     atomic:   dacc[i] += s a_ki * s <Q_k, C_i> / N.
+//  When the row's visits cannot fit the table at once, the walks are taken
+//  in passes (Q_k is linear in the walks) and the gather repeats per pass.
+#pragma once
+
+#include "device.hpp"
+#include "ops.hpp"
+#include "plan.hpp"
+
+namespace mcmf {
+namespace gather {
+
+constexpr int kGatherThreads = 1024;
+constexpr int kWaves = kGatherThreads / 64;
+constexpr uint32_t kFilterLog2Words = 11; // 2048 words = 8 KiB
+constexpr uint32_t kFilterWords = 1u << kFilterLog2Words;
+constexpr int kBatch = 256;                // neighbours per batch
+constexpr int kGroup = 16;                 // lanes per chunk
+constexpr int kPerLane = 8;                // entries per lane per chunk
+constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
+constexpr int kGroups = kGatherThreads / kGroup;
+constexpr int kSlots = 8;                  // slots per bucket
+constexpr int32_t kEmpty = -1;
+
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+    // Multiply-xorshift integer hash (the finaliser of MurmurHash3).
+    x ^= x >> 16;
+    x *= 0x85EBCA6Bu;
+    x ^= x >> 13;
+    x *= 0xC2B2AE35u;
+    x ^= x >> 16;
+    return x;
+}
+
+struct Table {
+    int32_t *keys; // nb buckets x kSlots slots, 32-byte aligned
+    double *vals;
+    uint32_t *filter;
+    uint32_t nb;
+
+    // Multiplicative hashing: node ids of the graphs here carry no structure
+    // that a multiply-shift hash would keep.
+    __device__ __forceinline__ uint32_t bucket_of(int32_t key) const {
+        return __umulhi(static_cast<uint32_t>(key) * 0x85EBCA77u, nb);
+    }
+    __device__ __forceinline__ static uint32_t fhash(int32_t key) {
+        return static_cast<uint32_t>(key) * 0x9E3779B1u;
+    }
+    // Top bits pick the filter word, three 5-bit fields below them the bits.
+    __device__ __forceinline__ static uint32_t filter_word(uint32_t h) {
+        return h >> (32 - kFilterLog2Words);
+    }
+    __device__ __forceinline__ static uint32_t filter_mask(uint32_t h) {
+        return (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31)) | (1u << (h & 31));
+    }
+
+    // Returns false only if every bucket is full (the plan rules that out).
+    __device__ bool insert(int32_t key, double x) const {
+        const uint32_t h = fhash(key);
+        atomicOr(&filter[filter_word(h)], filter_mask(h));
+        uint32_t b = bucket_of(key);
+        for (uint32_t tries = 0; tries < nb; ++tries) {
+#pragma unroll
+            for (int j = 0; j < kSlots; ++j) {
+                const uint32_t s = kSlots * b + j;
+                const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
+                if (prev == kEmpty || prev == key) {
+                    atomicAdd(&vals[s], x);
+                    return true;
+                }
+            }
+            b = (b + 1 == nb) ? 0 : b + 1;
+        }
+        return false;
+    }
+
+    // Value of key in bucket b, or: 0 with *more = false when the key is absent
+    // (an empty slot ends the probe sequence), *more = true when the bucket is
+    // full without it (continue with the next bucket).
+    __device__ __forceinline__ double probe_bucket(int32_t key, uint32_t b, bool *more) const {
+        const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
+        const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
+        int j = -1;
+        j = (lo.x == key) ? 0 : j;
+        j = (lo.y == key) ? 1 : j;
+        j = (lo.z == key) ? 2 : j;
+        j = (lo.w == key) ? 3 : j;
+        j = (hi.x == key) ? 4 : j;
+        j = (hi.y == key) ? 5 : j;
+        j = (hi.z == key) ? 6 : j;
+        j = (hi.w == key) ? 7 : j;
+        *more = false;
+        if (j >= 0)
+            return vals[kSlots * b + j];
+        *more = hi.w != kEmpty; // slots fill in order: the last one is the test
+        return 0.0;
+    }
+
+    // Lookup of N keys stage by stage so that their LDS reads overlap: all
+    // filter words, then the home buckets and values in two halves (to bound
+    // register use), then the rare keys that need further buckets.
+    // key < 0 means "no key" (result 0).
+    template <int N>
+    __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
+        static_assert(N % 2 == 0, "N must be even");
+        constexpr int H = N / 2;
+        uint32_t fw[N], m[N];
+#pragma unroll
+        for (int u = 0; u < N; ++u) {
+            const uint32_t h = fhash(key[u]);
+            m[u] = filter_mask(h);
+            fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
+        }
+        uint32_t pending = 0;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            // Every lane issues its reads; lanes without a candidate read bucket
+            // 0, one address the LDS serves as a broadcast.
+            bool cand[H];
+            uint32_t b[H];
+            int4 lo[H], hi[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v) {
+                const int u = half * H + v;
+                cand[v] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
+                b[v] = cand[v] ? bucket_of(key[u]) : 0u;
+                lo[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v]);
+                hi[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v] + 4);
+            }
+            int slot[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v) {
+                const int u = half * H + v;
+                const int32_t k = key[u];
+                int j = -1;
+                j = (lo[v].x == k) ? 0 : j;
+                j = (lo[v].y == k) ? 1 : j;
+                j = (lo[v].z == k) ? 2 : j;
+                j = (lo[v].w == k) ? 3 : j;
+                j = (hi[v].x == k) ? 4 : j;
+                j = (hi[v].y == k) ? 5 : j;
+                j = (hi[v].z == k) ? 6 : j;
+                j = (hi[v].w == k) ? 7 : j;
+                j = cand[v] ? j : -1;
+                // Slots fill in order, so a full bucket ends with a used last slot.
+                pending |= (cand[v] && j < 0 && hi[v].w != kEmpty) ? (1u << u) : 0u;
+                slot[v] = j;
+            }
+            double got[H];
+#pragma unroll
+            for (int v = 0; v < H; ++v)
+                got[v] = vals[slot[v] >= 0 ? kSlots * b[v] + slot[v] : 0u];
+#pragma unroll
+            for (int v = 0; v < H; ++v)
+                out[half * H + v] = slot[v] >= 0 ? got[v] : 0.0;
+        }
+        while (pending) {
+            const int u = __ffs(pending) - 1;
+            pending &= pending - 1;
+            int32_t kx = key[0];
+#pragma unroll
+            for (int v = 1; v < N; ++v)
+                kx = (v == u) ? key[v] : kx;
+            uint32_t bx = bucket_of(kx);
+            double r = 0.0;
+            bool more = true;
+            for (uint32_t tries = 1; more && tries < nb; ++tries) {
+                bx = (bx + 1 == nb) ? 0 : bx + 1;
+                r = probe_bucket(kx, bx, &more);
+            }
+#pragma unroll
+            for (int v = 0; v < N; ++v)
+                out[v] = (v == u) ? r : out[v];
+        }
+    }
+};
+
+// Per-batch neighbour metadata in LDS.
+struct Batch {
+    uint32_t prefix[kBatch + 1]; // first chunk of each neighbour's column
+    uint32_t start[kBatch];      // first entry of the column in col[]
+    uint32_t len[kBatch];        // column length
+    int32_t row[kBatch];         // neighbour i (-1: not requested)
+    double aki[kBatch];          // s * a_ki
+    double sum[kBatch];          // <Q_k, C_i> partial sums
+};
+
+// LDS views shared by every row a workgroup processes.
+struct Shared {
+    Table tab;
+    Batch *bt;
+    uint32_t *scan_scratch; // one word per wavefront
+    unsigned long long *red; // one word per wavefront
+};
+
+// One start row's gather job.
+struct RowJob {
+    int32_t k;
+    uint2 rk;               // record of row k
+    const int32_t *st;      // visit states of row k, t-major (t * N + w)
+    int64_t N;              // walks of row k
+    int K;
+    int64_t walks_per_pass;
+    const uint2 *node;
+    const int32_t *col;
+    const double *val;
+    const uint8_t *in_set;  // null: every row requested
+    double scale;
+    double *dacc;
+    unsigned long long *overflow;
+};
+
+// Runs the job with all threads of the workgroup (kGatherThreads).
+template <bool WEIGHTED, class VT>
+__device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restrict__ xs,
+                           unsigned long long &probes) {
+    const Table &tab = sh.tab;
+    Batch &bt = *sh.bt;
+    uint32_t *scan_scratch = sh.scan_scratch;
+    unsigned long long *red = sh.red;
+    const uint32_t cap = kSlots * tab.nb;
+    const double inv_n = 1.0 / static_cast<double>(j.N);
+    const int32_t k = j.k;
+    const uint2 rk = j.rk;
+    const int32_t *st = j.st;
+    for (int64_t w0 = 0; w0 < j.N; w0 += j.walks_per_pass) {
+        const int64_t nw = (j.N - w0 < j.walks_per_pass) ? (j.N - w0) : j.walks_per_pass;
+        // (1) Q_k from walks [w0, w0 + nw).
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
+            tab.keys[i] = kEmpty;
+            tab.vals[i] = 0.0;
+        }
+        for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
+            tab.filter[i] = 0u;
+        __syncthreads();
+        const int64_t count = nw * (j.K - 1);
+        if (nw == j.N) {
+            // Step 0 of every walk sits at k: insert the sum of those visits once
+            // instead of N colliding atomic updates of one slot.
+            double x0 = 0.0;
+            for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
+                x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
+            x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
+            if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
+                atomicAdd(j.overflow, 1ull);
+            for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
+                const int32_t s = st[i];
+                if (s >= 0 && !tab.insert(s, static_cast<double>(xs[i])))
+                    atomicAdd(j.overflow, 1ull);
+            }
+        } else {
+            for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+                const int64_t t = i / nw;
+                const int64_t slot = t * j.N + w0 + (i - t * nw);
+                const int32_t s = st[slot];
+                if (s >= 0 && !tab.insert(s, static_cast<double>(xs[slot])))
+                    atomicAdd(j.overflow, 1ull);
+            }
+        }
+        // (2) columns of the requested neighbours, kBatch neighbours at a time.
+        for (uint32_t p0 = 0; p0 < rk.y; p0 += kBatch) {
+            const uint32_t m = (rk.y - p0 < uint32_t(kBatch)) ? rk.y - p0 : uint32_t(kBatch);
+            __syncthreads(); // table complete / previous batch flushed
+            uint32_t nchunks = 0;
+            if (threadIdx.x < kBatch) {
+                const int t = threadIdx.x;
+                bt.sum[t] = 0.0;
+                bt.row[t] = -1;
+                bt.len[t] = 0;
+                if (uint32_t(t) < m) {
+                    const int64_t e = int64_t(rk.x) + p0 + t;
+                    const int32_t i = j.col[e];
+                    if (!j.in_set || j.in_set[i]) {
+                        const uint2 ri = j.node[i];
+                        nchunks = (ri.y + kChunk - 1) / kChunk;
+                        bt.start[t] = ri.x;
+                        bt.len[t] = ri.y;
+                        bt.row[t] = i;
+                        bt.aki[t] = j.scale * (WEIGHTED ? j.val[e] : 1.0);
+                    }
+                }
+            }
+            uint32_t total = 0;
+            const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
+            if (threadIdx.x < kBatch)
+                bt.prefix[threadIdx.x] = before;
+            if (threadIdx.x == 0)
+                bt.prefix[kBatch] = total;
+            __syncthreads();
+            // Group g takes the contiguous chunk range [g*per, (g+1)*per) and
+            // walks the neighbours forward, so the owner is searched once.
+            const int group = threadIdx.x / kGroup;
+            const int gl = threadIdx.x % kGroup;
+            const uint32_t per = (total + kGroups - 1) / kGroups;
+            const uint32_t c_begin = group * per;
+            const uint32_t c_end = (c_begin + per < total) ? c_begin + per : total;
+            if (c_begin < c_end) {
+                int r = 0, hi = kBatch;
+                while (hi - r > 1) {
+                    const int mid = (r + hi) >> 1;
+                    if (bt.prefix[mid] <= c_begin)
+                        r = mid;
+                    else
+                        hi = mid;
+                }
+                uint32_t next = bt.prefix[r + 1];
+                uint32_t len = bt.len[r];
+                int64_t base = int64_t(bt.start[r]);
+                uint32_t first_chunk = bt.prefix[r];
+                double acc = 0.0;
+                for (uint32_t c = c_begin; c < c_end; ++c) {
+                    if (c >= next) {
+                        // Row change: flush the finished neighbour's partial sum.
+                        const double g = dev::group_sum<kGroup>(acc);
+                        if (gl == 0 && g != 0.0)
+                            atomicAdd(&bt.sum[r], g);
+                        acc = 0.0;
+                        do {
+                            ++r;
+                            next = bt.prefix[r + 1];
+                        } while (c >= next);
+                        len = bt.len[r];
+                        base = int64_t(bt.start[r]);
+                        first_chunk = bt.prefix[r];
+                    }
+                    const uint32_t off0 = (c - first_chunk) * kChunk;
+                    const uint32_t first = off0 + gl;
+                    int32_t key[kPerLane];
+                    double wv[kPerLane];
+                    if (off0 + kChunk <= len) {
+#pragma unroll
+                        for (int u = 0; u < kPerLane; ++u) {
+                            key[u] = j.col[base + first + u * kGroup];
+                            wv[u] = WEIGHTED ? j.val[base + first + u * kGroup] : 1.0;
+                        }
+                        probes += gl == 0 ? kChunk : 0;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < kPerLane; ++u) {
+                            const uint32_t off = first + u * kGroup;
+                            key[u] = off < len ? j.col[base + off] : -1;
+                            wv[u] = (WEIGHTED && off < len) ? j.val[base + off] : 1.0;
+                        }
+                        probes += gl == 0 ? len - off0 : 0;
+                    }
+                    double qv[kPerLane];
+                    tab.lookup_n<kPerLane>(key, qv);
+#pragma unroll
+                    for (int u = 0; u < kPerLane; ++u)
+                        acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
+                }
+                const double g = dev::group_sum<kGroup>(acc);
+                if (gl == 0 && g != 0.0)
+                    atomicAdd(&bt.sum[r], g);
+            }
+            __syncthreads();
+            if (threadIdx.x < m && bt.row[threadIdx.x] >= 0) {
+                const int t = threadIdx.x;
+                atomicAdd(&j.dacc[bt.row[t]], bt.aki[t] * (j.scale * bt.sum[t]) * inv_n);
+            }
+        }
+    }
+}
+
+// LDS bytes of the table for a plan, and of the fixed per-workgroup arrays.
+constexpr size_t kStaticLds = sizeof(Batch) + sizeof(uint32_t) * kWaves +
+                              sizeof(unsigned long long) * kWaves + 512;
+
+__device__ __forceinline__ Shared shared_views(unsigned char *smem, uint32_t nb, Batch *bt,
+                                               uint32_t *scan, unsigned long long *red) {
+    Shared sh;
+    const uint32_t cap = kSlots * nb;
+    sh.tab.nb = nb;
+    sh.tab.vals = reinterpret_cast<double *>(smem);
+    sh.tab.keys = reinterpret_cast<int32_t *>(smem + sizeof(double) * cap);
+    sh.tab.filter = reinterpret_cast<uint32_t *>(smem + sizeof(double) * cap + sizeof(int32_t) * cap);
+    sh.bt = bt;
+    sh.scan_scratch = scan;
+    sh.red = red;
+    return sh;
+}
+
+} // namespace gather
+} // namespace mcmf

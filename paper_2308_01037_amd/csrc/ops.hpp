@@ -53,4 +53,15 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
                    const int32_t *state, const void *x, const uint8_t *in_set, double *dacc,
                    unsigned long long *probes, unsigned long long *overflow, hipStream_t s);
 
+// Diag setup and assembly (api.hip).
+Status mark_rows(const int32_t *rows, int64_t count, int64_t n, uint8_t *in_set, int *bad,
+                 hipStream_t s);
+Status mark_starts(const mcmf_graph *g, const int32_t *rows, int64_t count, uint8_t *start_flags,
+                   hipStream_t s);
+Status diag_finish(const mcmf_graph *g, const int32_t *rows, int64_t count, int K, double c0,
+                   double c1, double scale, const double *dacc, double *out, hipStream_t s);
+Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K,
+                    const mcmf_opts *o);
+WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N);
+
 } // namespace mcmf

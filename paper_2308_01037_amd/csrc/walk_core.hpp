@@ -1,0 +1,217 @@
+// Device-side core of one random walk, shared by the single-request and
+// the batched walk kernels.
+//
+// A walk keeps its state in registers: the current row l with its record
+// (first entry, length) and the weight W.  A transition draws Philox4x32-10
+// at counter (k, w, t, request), picks entry j of row l and moves to its
+// column, multiplying W by s * sum_j |a_lj| (negated for a negative entry).
+// Unweighted rows pick j = floor(u deg / 2^64) and read one 16-byte edge
+// record {next row, its first entry, its length}: one dependent load per
+// step.  The transition of step t is issued before step t is recorded, so
+// the record's load overlaps the bookkeeping.  Weighted rows search the
+// running sums of |a|.
+//
+// Weight type WT: double (FP64) or float (FP32 walk weights; W, the per-step
+// factor and each per-step contribution are FP32, every sum stays FP64).
+#pragma once
+
+#include <type_traits>
+
+#include "device.hpp"
+#include "ops.hpp"
+
+namespace mcmf {
+namespace walk {
+
+// First index j < deg with target < cum[j] (cum non-decreasing); deg-1 if none.
+__device__ __forceinline__ uint32_t cdf_search(const double *__restrict__ cum, uint32_t deg,
+                                               double target) {
+    uint32_t lo = 0, hi = deg;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (target < cum[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo < deg ? lo : deg - 1;
+}
+
+struct WalkArgs {
+    const double *coef; // c_{t+2} at index t
+    int K;
+    double scale;
+    int64_t N;
+    uint32_t key0, key1, request;
+    double cutoff;
+};
+
+inline WalkArgs to_args(const WalkParams &p) {
+    WalkArgs a;
+    a.coef = p.coef;
+    a.K = p.K;
+    a.scale = p.scale;
+    a.N = p.n_walks;
+    a.key0 = p.key0;
+    a.key1 = p.key1;
+    a.request = p.request;
+    a.cutoff = p.cutoff;
+    return a;
+}
+
+struct GraphView {
+    const uint2 *node;
+    const uint4 *edge;
+    const int32_t *col;
+    const double *val;
+    const double *rowabs;
+    const double *cum;
+};
+
+inline GraphView view(const mcmf_graph *g) {
+    GraphView v;
+    v.node = g->node;
+    v.edge = g->edge;
+    v.col = g->col;
+    v.val = g->val;
+    v.rowabs = g->rowabs;
+    v.cum = g->cum;
+    return v;
+}
+
+// Walk state of one walk: row, its record, weight.
+struct Pos {
+    uint32_t l, start, deg;
+};
+
+// One transition out of row p (deg > 0) with the block of random words x.
+// Updates W (times s * sum |a|, sign of the entry) and returns the new row.
+template <bool WEIGHTED, class WT>
+__device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
+                                    WT &W) {
+    Pos n;
+    if constexpr (!WEIGHTED) {
+        const uint32_t j = dev::uniform_index(x.x, x.y, p.deg);
+        W = W * static_cast<WT>(scale * static_cast<double>(p.deg));
+        const uint4 e = g.edge[int64_t(p.start) + j];
+        n.l = e.x;
+        n.start = e.y;
+        n.deg = e.z;
+    } else {
+        const double ra = g.rowabs[p.l];
+        const uint32_t j = cdf_search(g.cum + p.start, p.deg, dev::unit53(x.x, x.y) * ra);
+        W = W * static_cast<WT>(scale * ra);
+        if (g.val[int64_t(p.start) + j] < 0.0)
+            W = -W;
+        n.l = static_cast<uint32_t>(g.col[int64_t(p.start) + j]);
+        const uint2 r = g.node[n.l];
+        n.start = r.x;
+        n.deg = r.y;
+    }
+    return n;
+}
+
+
+// One action walk (walk index w from start row k): returns
+// sum_t c_{t+2} W_t r_{l_t}; adds the recorded states to *nsteps and folds
+// the path into *h.
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+__device__ __forceinline__ double action_walk(const GraphView &g, const double *__restrict__ r,
+                                              const WalkArgs &a, uint32_t k, uint2 rk, double r_k,
+                                              uint32_t w, uint64_t *h, unsigned long long *nsteps) {
+    const int last = a.K - 2;
+    Pos p{k, rk.x, rk.y};
+    double rl = r_k;
+    WT W = WT(1);
+    double wacc = 0.0;
+    for (int t = 0; t <= last; ++t) {
+        if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
+            break;
+        const bool more = t < last && p.deg > 0;
+        Pos nxt = p;
+        WT Wn = W;
+        if (more) {
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
+        }
+        wacc += static_cast<double>(static_cast<WT>(a.coef[t]) * W * static_cast<WT>(rl));
+        if (DIGEST)
+            *h = dev::fnv_step(*h, p.l);
+        ++*nsteps;
+        if (!more)
+            break;
+        p = nxt;
+        W = Wn;
+        rl = r[p.l];
+    }
+    return wacc;
+}
+
+// One diagonal walk: writes (l_t, c_{t+2} W_t) to vstate[t*stride],
+// vx[t*stride] for t = 0..K-2 (state -1 once the walk has ended).
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+__device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a, uint32_t k,
+                                          uint2 rk, uint32_t w, int32_t *__restrict__ vstate,
+                                          WT *__restrict__ vx, int64_t stride, uint64_t *h,
+                                          unsigned long long *nsteps) {
+    const int last = a.K - 2;
+    Pos p{k, rk.x, rk.y};
+    WT W = WT(1);
+    int t = 0;
+    for (; t <= last; ++t) {
+        if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
+            break;
+        const bool more = t < last && p.deg > 0;
+        Pos nxt = p;
+        WT Wn = W;
+        if (more) {
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
+        }
+        vstate[int64_t(t) * stride] = static_cast<int32_t>(p.l);
+        vx[int64_t(t) * stride] = static_cast<WT>(a.coef[t]) * W;
+        if (DIGEST)
+            *h = dev::fnv_step(*h, p.l);
+        ++*nsteps;
+        if (!more) {
+            ++t;
+            break;
+        }
+        p = nxt;
+        W = Wn;
+    }
+    for (; t <= last; ++t)
+        vstate[int64_t(t) * stride] = -1;
+}
+
+// Runtime flags to template arguments.
+template <class F>
+void dispatch4(bool fp32, bool weighted, bool digest, bool cutoff, F &&f) {
+    auto with_c = [&](auto wt, auto w, auto d) {
+        if (cutoff)
+            f(wt, w, d, std::true_type{});
+        else
+            f(wt, w, d, std::false_type{});
+    };
+    auto with_d = [&](auto wt, auto w) {
+        if (digest)
+            with_c(wt, w, std::true_type{});
+        else
+            with_c(wt, w, std::false_type{});
+    };
+    auto with_w = [&](auto wt) {
+        if (weighted)
+            with_d(wt, std::true_type{});
+        else
+            with_d(wt, std::false_type{});
+    };
+    if (fp32)
+        with_w(float{});
+    else
+        with_w(double{});
+}
+
+} // namespace walk
+} // namespace mcmf

@@ -76,6 +76,25 @@ class mcmf_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+MCMF_REQ_DIAG = 0
+MCMF_REQ_ACTION = 1
+
+
+class mcmf_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("K", ctypes.c_int32), ("graph", ctypes.c_void_p),
+                ("fn", mcmf_fn), ("rows", ctypes.c_void_p), ("n_rows", ctypes.c_int64),
+                ("v", ctypes.c_void_p), ("n_walks", ctypes.c_int64), ("seed", ctypes.c_uint64),
+                ("request_id", ctypes.c_uint32), ("precision", ctypes.c_int32),
+                ("weight_cutoff", ctypes.c_double), ("out", ctypes.c_void_p),
+                ("path_digest", ctypes.c_void_p), ("status", ctypes.c_int),
+                ("walk_steps", ctypes.c_uint64)]
+
+
+class mcmf_batch_opts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 6)]
+
+
 _P = ctypes.c_void_p
 _lib.mcmf_graph_create.argtypes = [ctypes.c_int64, _P, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P)]
 _lib.mcmf_graph_create.restype = ctypes.c_int
@@ -89,13 +108,16 @@ _lib.mcmf_diag.restype = ctypes.c_int
 _lib.mcmf_action.argtypes = [_P, ctypes.POINTER(mcmf_fn), _P, ctypes.c_int64, ctypes.c_int32,
                              ctypes.POINTER(mcmf_opts), _P, ctypes.POINTER(mcmf_stats)]
 _lib.mcmf_action.restype = ctypes.c_int
+_lib.mcmf_batch.argtypes = [ctypes.POINTER(mcmf_request), ctypes.c_int64,
+                            ctypes.POINTER(mcmf_batch_opts), ctypes.POINTER(mcmf_stats)]
+_lib.mcmf_batch.restype = ctypes.c_int
 _lib.mcmf_status_string.argtypes = [ctypes.c_int]
 _lib.mcmf_status_string.restype = ctypes.c_char_p
 _lib.mcmf_last_error.argtypes = []
 _lib.mcmf_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mcmf_graph_create", "mcmf_graph_destroy", "mcmf_graph_info", "mcmf_diag",
-            "mcmf_action", "mcmf_status_string", "mcmf_last_error"]
+            "mcmf_action", "mcmf_batch", "mcmf_status_string", "mcmf_last_error"]
 
 
 class MCMFError(RuntimeError):
@@ -223,6 +245,54 @@ def mcmf_action(g: int, f: mcmf_fn, v, n_walks: int, K: int, opts: Optional[mcmf
     _raise(_lib.mcmf_action(g, ctypes.byref(f), _addr(v), n_walks, K,
                             ctypes.byref(opts) if opts is not None else None, _addr(out),
                             ctypes.byref(stats) if stats is not None else None))
+
+
+def make_request(kind: int, graph: int, fn: mcmf_fn, K: int, n_walks: int, out, *, rows=None,
+                 v=None, seed: int = 0, request_id: int = 0,
+                 precision: int = MCMF_PRECISION_FP64, weight_cutoff: float = 0.0,
+                 path_digest=None) -> mcmf_request:
+    """An mcmf_request; the arrays it points to are kept alive on the struct."""
+    _check_dtype(rows, np.int32, "rows")
+    _check_dtype(v, np.float64, "v")
+    _check_dtype(out, np.float64, "out")
+    _check_dtype(path_digest, np.uint64, "path_digest")
+    r = mcmf_request()
+    r.kind = kind
+    r.K = K
+    r.graph = graph
+    r.fn = fn
+    rows_addr = _addr(rows)
+    if rows is not None and not rows_addr:
+        rows_addr = ctypes.addressof(_EMPTY_ROWS)
+    r.rows = rows_addr
+    r.n_rows = 0 if rows is None else len(rows)
+    r.v = _addr(v)
+    r.n_walks = n_walks
+    r.seed = seed
+    r.request_id = request_id
+    r.precision = precision
+    r.weight_cutoff = weight_cutoff
+    r.out = _addr(out)
+    r.path_digest = _addr(path_digest)
+    r._keep = (fn, rows, v, out, path_digest)
+    return r
+
+
+def mcmf_batch(reqs, opts: Optional[mcmf_batch_opts] = None,
+               stats: Optional[mcmf_stats] = None) -> None:
+    """Runs a list of mcmf_request; writes each request's status and
+    walk_steps back into the given structs."""
+    reqs = list(reqs)
+    arr = (mcmf_request * max(len(reqs), 1))()
+    for i, r in enumerate(reqs):
+        ctypes.memmove(ctypes.byref(arr, i * ctypes.sizeof(mcmf_request)), ctypes.byref(r),
+                       ctypes.sizeof(mcmf_request))
+    st = _lib.mcmf_batch(arr, len(reqs), ctypes.byref(opts) if opts is not None else None,
+                         ctypes.byref(stats) if stats is not None else None)
+    for i, r in enumerate(reqs):
+        r.status = arr[i].status
+        r.walk_steps = arr[i].walk_steps
+    _raise(st)
 
 
 # ---------------------------------------------------------------- convenience

@@ -83,3 +83,53 @@ def test_import_fails_loudly_without_library(tmp_path):
     code = f"import sys; sys.path.insert(0, {str(pkg)!r}); import mcmf"
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True)
     assert res.returncode != 0 and "libmcmf.so is missing" in res.stderr
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # The ctypes mirrors of the public structs must have the C layout.
+    from paper_2308_01037_amd import mcmf as M
+    structs = {"mcmf_fn": M.mcmf_fn, "mcmf_opts": M.mcmf_opts, "mcmf_stats": M.mcmf_stats,
+               "mcmf_request": M.mcmf_request, "mcmf_batch_opts": M.mcmf_batch_opts}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcmf.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        name, field, value = line.split()
+        got[(name, field)] = int(value)
+    import ctypes
+    for name, cls in structs.items():
+        assert got[(name, "size")] == ctypes.sizeof(cls), name
+        for field, _ in cls._fields_:
+            assert got[(name, field)] == getattr(cls, field).offset, (name, field)
+
+
+def test_batch_argument_errors_need_no_device():
+    from paper_2308_01037_amd import mcmf as M
+    f = M.make_fn()
+    y = np.zeros(5)
+    # An empty batch is a no-op.
+    M.mcmf_batch([])
+    bad = M.make_request(M.MCMF_REQ_ACTION, None, f, 5, 10, y, v=np.ones(5))
+    ok_shape = M.make_request(M.MCMF_REQ_DIAG, None, f, 5, 10, y)
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_batch([bad, ok_shape])
+    assert e.value.status == M.MCMF_E_ARG and bad.status == M.MCMF_E_ARG
+    assert "graph" in M.mcmf_last_error()
+    o = M.mcmf_batch_opts()
+    o.reserved[2] = 1
+    with pytest.raises(M.MCMFError) as e:
+        M.mcmf_batch([bad], o)
+    assert e.value.status == M.MCMF_E_ARG and "reserved" in M.mcmf_last_error()
+    kind = M.make_request(7, None, f, 5, 10, y)
+    with pytest.raises(M.MCMFError):
+        M.mcmf_batch([kind])
+    assert np.all(y == 0)

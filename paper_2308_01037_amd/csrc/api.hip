@@ -368,6 +368,14 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         }
         starts = start_list.ptr;
     }
+    // Work items of the gather over the start list.
+    DevBuf<int64_t> item_buf;
+    const int64_t *item_off = g->active_items;
+    if (!all && K >= 2 && n_start > 0) {
+        MCMF_TRY(item_buf.alloc(n_start + 1, s));
+        MCMF_TRY(gather_items(g, starts, n_start, item_buf.ptr, s));
+        item_off = item_buf.ptr;
+    }
     if (K >= 2) {
         MCMF_TRY(dacc.alloc(n > 0 ? n : 1, s));
         MCMF_TRY(fill_f64(dacc.ptr, 0.0, n, s));
@@ -396,6 +404,9 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         // Per-chunk events are read only after the call's final synchronisation,
         // so timing does not stall the stream between chunks.
         const int64_t n_chunks = (n_start + rows_per_chunk - 1) / rows_per_chunk;
+        DevBuf<unsigned long long> queues; // one work counter per gather launch
+        MCMF_TRY(queues.alloc(n_chunks, s));
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_chunks, s));
         if (stats) {
             chunk_events.assign(static_cast<size_t>(2 * n_chunks + 1), nullptr);
             for (auto &e : chunk_events)
@@ -410,9 +421,9 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
                                 counters.ptr, s));
             if (stats)
                 MCMF_HIP(hipEventRecord(chunk_events[2 * ci + 1], s));
-            MCMF_TRY(diag_gather(g, starts + c0, rows_here, p, vstate.ptr, vx.ptr,
+            MCMF_TRY(diag_gather(g, starts, item_off, c0, c0 + rows_here, p, vstate.ptr, vx.ptr,
                                  all ? nullptr : in_set.ptr, dacc.ptr, counters.ptr + 1,
-                                 counters.ptr + 2, s));
+                                 counters.ptr + 2, queues.ptr + ci, s));
         }
         if (stats)
             MCMF_HIP(hipEventRecord(chunk_events.back(), s));

@@ -6,8 +6,9 @@
 // flattened task space of all requests, so requests with few walks per row
 // or few rows do not leave the GPU idle.  Action tasks add their wavefront
 // sum into q[k] (FP64 atomics); diagonal tasks write visit records.  The
-// persistent gather kernel then takes one start row of one diagonal request
-// per iteration (gather_core.hpp).  Diagonal visit records are produced and
+// persistent gather workgroups then take items (up to 256 neighbours of one
+// start row of one diagonal request) from a queue counter and run
+// gather_core.hpp on each.  Diagonal visit records are produced and
 // consumed in chunks bounded by a byte budget; all action tasks ride along in
 // the first chunk's walk launch.
 //
@@ -46,6 +47,7 @@ struct BReq {
     unsigned long long *steps; // this request's step counter
     const uint8_t *in_set;     // diag subset (null: all rows)
     double *dacc;              // diag sums
+    const int64_t *item_off;   // diag: gather work items of the start list
     int64_t wpp;               // walks per gather pass
 };
 
@@ -59,10 +61,13 @@ struct WSeg {
     int64_t xoff;       // diag: byte offset of that slot's value
 };
 
-// A run of one request's start rows inside a gather launch.
+// A run of one request's start rows inside a gather launch.  item_base (the
+// run's first work item in the launch) is filled in on the device; an extra
+// entry after the last run holds the launch's item count.
 struct GSeg {
     int32_t req;
     int64_t kk0;
+    int64_t rows;
     int64_t item_base;
     int64_t slot_base;
     int64_t xoff;
@@ -133,18 +138,37 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
     }
 }
 
+// Item bases of the runs of one gather launch (one thread; runs are few).
+__global__ void k_seg_items(const BReq *__restrict__ reqs, GSeg *segs, int n_segs) {
+    if (blockIdx.x != 0 || threadIdx.x != 0)
+        return;
+    int64_t base = 0;
+    for (int i = 0; i < n_segs; ++i) {
+        const int64_t *off = reqs[segs[i].req].item_off;
+        segs[i].item_base = base;
+        base += off[segs[i].kk0 + segs[i].rows] - off[segs[i].kk0];
+    }
+    segs[n_segs].item_base = base;
+}
+
 template <bool WEIGHTED, class VT>
 __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
-    const BReq *__restrict__ reqs, const GSeg *__restrict__ segs, int n_segs, int64_t n_items,
-    const int32_t *vstate, const unsigned char *vxb, uint32_t nb, unsigned long long *probes_out) {
+    const BReq *__restrict__ reqs, const GSeg *__restrict__ segs, int n_segs,
+    const int32_t *vstate, const unsigned char *vxb, uint32_t nb, unsigned long long *probes_out,
+    unsigned long long *queue) {
     using namespace gather;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Batch bt;
     __shared__ uint32_t scan_scratch[kWaves];
     __shared__ unsigned long long red[kWaves];
+    __shared__ int64_t item_slot;
     const Shared sh = shared_views(smem, nb, &bt, scan_scratch, red);
+    const int64_t n_items = segs[n_segs].item_base;
     unsigned long long probes = 0;
-    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    for (;;) {
+        const int64_t item = next_item(queue, &item_slot);
+        if (item >= n_items)
+            break;
         int lo = 0, hi = n_segs;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -155,11 +179,16 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         }
         const GSeg sg = segs[lo];
         const BReq &R = reqs[sg.req];
-        const int64_t rel = item - sg.item_base;
+        const int64_t ri = R.item_off[sg.kk0] + (item - sg.item_base);
+        const int64_t kk = row_of_item(R.item_off, sg.kk0, sg.kk0 + sg.rows, ri);
+        const uint32_t part = static_cast<uint32_t>(ri - R.item_off[kk]);
+        const int64_t rel = kk - sg.kk0;
         const int64_t span = int64_t(R.a.K - 1) * R.a.N;
         RowJob job;
-        job.k = R.starts[sg.kk0 + rel];
+        job.k = R.starts[kk];
         job.rk = R.g.node[job.k];
+        job.p_begin = part * kBatch;
+        job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
         job.st = vstate + sg.slot_base + rel * span;
         job.N = R.a.N;
         job.K = R.a.K;
@@ -180,8 +209,9 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
 }
 
 // Gather kernel for variant v = (FP32 weights ? 1 : 0) | (weighted ? 2 : 0).
-using GatherKernel = void (*)(const BReq *, const GSeg *, int, int64_t, const int32_t *,
-                              const unsigned char *, uint32_t, unsigned long long *);
+using GatherKernel = void (*)(const BReq *, const GSeg *, int, const int32_t *,
+                              const unsigned char *, uint32_t, unsigned long long *,
+                              unsigned long long *);
 constexpr int kGatherVariants = 4;
 GatherKernel gather_kernel(int v) {
     switch (v) {
@@ -199,6 +229,8 @@ struct Prep {
     DevBuf<double> coef, r, q, dacc;
     DevBuf<uint8_t> in_set, start_flags;
     DevBuf<int32_t> start_list;
+    DevBuf<int64_t> items;
+    const int64_t *item_off = nullptr;
     View<double> vin, out;
     View<int32_t> rows;
     View<uint64_t> dig;
@@ -280,6 +312,7 @@ Status prepare(Prep &P, hipStream_t s) {
         if (P.all) {
             P.starts = g->active;
             P.n_start = g->n_active;
+            P.item_off = g->active_items;
         } else if (P.count > 0) {
             MCMF_TRY(P.start_flags.alloc(n > 0 ? n : 1, s));
             MCMF_TRY(P.start_list.alloc(n > 0 ? n : 1, s));
@@ -287,6 +320,9 @@ Status prepare(Prep &P, hipStream_t s) {
             MCMF_TRY(mark_starts(g, P.rows.ptr, P.count, P.start_flags.ptr, s));
             MCMF_TRY(compact(P.start_flags.ptr, n, 1, P.start_list.ptr, &P.n_start, s));
             P.starts = P.start_list.ptr;
+            MCMF_TRY(P.items.alloc(P.n_start + 1, s));
+            MCMF_TRY(gather_items(g, P.starts, P.n_start, P.items.ptr, s));
+            P.item_off = P.items.ptr;
         }
     }
     return {};
@@ -356,6 +392,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.digest = P.dig.ptr;
         B.in_set = P.all ? nullptr : P.in_set.ptr;
         B.dacc = P.dacc.ptr;
+        B.item_off = P.item_off;
         if (q.kind == MCMF_REQ_DIAG && q.K >= 2)
             max_visit_row = std::max<int64_t>(max_visit_row, q.n_walks * (q.K - 1));
     }
@@ -397,7 +434,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     struct Chunk {
         std::vector<WSeg> w;
         std::vector<GSeg> gs[kGatherVariants];
-        int64_t items[kGatherVariants] = {0, 0, 0, 0};
+        int64_t items[kGatherVariants] = {0, 0, 0, 0}; // start rows per variant
         int64_t tasks = 0, rows = 0, slots = 0, xbytes = 0;
     };
     std::vector<Chunk> chunks(1);
@@ -433,7 +470,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             // Value arrays are 8-byte aligned per run.
             c.xbytes = (c.xbytes + 7) & ~int64_t(7);
             c.w.push_back(WSeg{static_cast<int32_t>(i), tpr, kk, c.tasks, c.slots, c.xbytes});
-            c.gs[var].push_back(GSeg{static_cast<int32_t>(i), kk, c.items[var], c.slots, c.xbytes});
+            c.gs[var].push_back(GSeg{static_cast<int32_t>(i), kk, take, 0, c.slots, c.xbytes});
             c.tasks += take * tpr;
             c.items[var] += take;
             c.rows += take;
@@ -464,20 +501,31 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             dgs.emplace_back(new DevBuf<GSeg>());
             if (c.gs[v].empty())
                 continue;
-            MCMF_TRY(dgs.back()->alloc(c.gs[v].size(), s));
+            MCMF_TRY(dgs.back()->alloc(c.gs[v].size() + 1, s));
             MCMF_HIP(hipMemcpyAsync(dgs.back()->ptr, c.gs[v].data(), sizeof(GSeg) * c.gs[v].size(),
                                     hipMemcpyHostToDevice, s));
         }
     }
+    // Persistent gather workgroups: as many as fit on the device at once.
+    int64_t gather_blocks[kGatherVariants] = {0, 0, 0, 0};
     if (nb > 0)
-        for (int v = 0; v < kGatherVariants; ++v)
-            MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gather_kernel(v)),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        for (int v = 0; v < kGatherVariants; ++v) {
+            const void *fn = reinterpret_cast<const void *>(gather_kernel(v));
+            MCMF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+            int per_cu = 0;
+            MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, gather::kGatherThreads, lds));
+            gather_blocks[v] = int64_t(per_cu > 0 ? per_cu : 1) * num_cus();
+        }
+    // One work counter per gather launch.
+    const int64_t n_queues = static_cast<int64_t>(chunks.size()) * kGatherVariants;
+    DevBuf<unsigned long long> queues;
+    MCMF_TRY(queues.alloc(n_queues, s));
 
     // The device work of the batch: fills, walks, gathers, assembly.
     const int64_t walk_blocks_cap = int64_t(num_cus()) * 16;
     auto enqueue = [&]() -> Status {
         MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, n_reqs + 2, s));
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_queues, s));
         for (int64_t i = 0; i < n_reqs; ++i) {
             Prep &P = *preps[i];
             const int64_t n = reqs[i].graph->n;
@@ -500,11 +548,14 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             for (int v = 0; v < kGatherVariants; ++v) {
                 if (c.items[v] == 0)
                     continue;
-                const int64_t blocks = std::min<int64_t>(int64_t(1) << 20, c.items[v]);
-                hipLaunchKernelGGL(gather_kernel(v), dim3(static_cast<uint32_t>(blocks)),
-                                   dim3(gather::kGatherThreads), lds, s, dreq.ptr,
-                                   dgs[ci * kGatherVariants + v]->ptr, static_cast<int>(c.gs[v].size()),
-                                   c.items[v], vstate.ptr, vxb.ptr, nb, counters.ptr + n_reqs);
+                GSeg *segs = dgs[ci * kGatherVariants + v]->ptr;
+                const int n_segs = static_cast<int>(c.gs[v].size());
+                hipLaunchKernelGGL(k_seg_items, dim3(1), dim3(64), 0, s, dreq.ptr, segs, n_segs);
+                MCMF_HIP(hipGetLastError());
+                hipLaunchKernelGGL(gather_kernel(v), dim3(static_cast<uint32_t>(gather_blocks[v])),
+                                   dim3(gather::kGatherThreads), lds, s, dreq.ptr, segs, n_segs,
+                                   vstate.ptr, vxb.ptr, nb, counters.ptr + n_reqs,
+                                   queues.ptr + ci * kGatherVariants + v);
                 MCMF_HIP(hipGetLastError());
             }
         }

@@ -149,6 +149,9 @@ struct mcmf_graph {
     // carries the record of the row it moves to.
     uint4 *edge = nullptr;
     int32_t *active = nullptr;  // [n_active] rows with entries, ascending
+    // [n_active + 1] first diagonal-gather work item of each active row
+    // (exclusive prefix sums of ceil(row length / 256)).
+    int64_t *active_items = nullptr;
     // Rows grouped by length for the sparse products: short (<= 64 entries,
     // including empty rows), medium (<= 4096), long.
     int32_t *bin_rows = nullptr; // [n] concatenated bins

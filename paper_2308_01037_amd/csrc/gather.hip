@@ -1,6 +1,9 @@
-// Diagonal gather kernel of the single-request path: one 1024-thread
-// workgroup per start row; the per-row work is gather::gather_row
-// (gather_core.hpp).
+// Diagonal gather kernel of the single-request path.  Work items are
+// neighbour ranges of start rows (at most 256 neighbours each, so a hub row
+// is spread over many workgroups); persistent workgroups take items from a
+// queue counter and run gather::gather_row (gather_core.hpp) on each.
+#include <hip/hip_runtime.h>
+
 #include "gather_core.hpp"
 
 namespace mcmf {
@@ -9,23 +12,66 @@ namespace {
 
 using namespace gather;
 
+__global__ void k_item_counts(const int32_t *__restrict__ starts, int64_t n,
+                              const uint2 *__restrict__ node, uint32_t *__restrict__ cnt) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n)
+        cnt[i] = items_of(node[starts[i]].y);
+}
+
+// Exclusive prefix sums of cnt[0..n) into off[0..n], one workgroup of 1024
+// threads, 8 counts per thread per tile.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+__global__ __launch_bounds__(kScanThreads) void k_item_scan(const uint32_t *__restrict__ cnt,
+                                                            int64_t n, int64_t *__restrict__ off) {
+    __shared__ uint32_t scratch[kScanThreads / 64];
+    int64_t carry = 0;
+    const int64_t tile = int64_t(kScanThreads) * kScanPer;
+    for (int64_t t0 = 0; t0 < n; t0 += tile) {
+        const int64_t base = t0 + int64_t(threadIdx.x) * kScanPer;
+        uint32_t v[kScanPer];
+        uint32_t local = 0;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            v[u] = base + u < n ? cnt[base + u] : 0u;
+            local += v[u];
+        }
+        uint32_t total = 0;
+        const uint32_t before = dev::block_exclusive_scan(local, scratch, &total);
+        int64_t run = carry + before;
+#pragma unroll
+        for (int u = 0; u < kScanPer; ++u) {
+            if (base + u < n)
+                off[base + u] = run;
+            run += v[u];
+        }
+        carry += total;
+        __syncthreads(); // scratch is reused by the next tile
+    }
+    if (threadIdx.x == 0)
+        off[n] = carry;
+}
+
 struct GatherArgs {
     const uint2 *node;
     const int32_t *col;
     const double *val;
     const int32_t *starts;
-    int64_t n_start;
+    const int64_t *item_off;
+    int64_t row_begin, row_end;
     int64_t N;
     int K;
     int64_t walks_per_pass;
-    const int32_t *vstate;
-    const void *vx; // double[] or float[] (FP32 walk weights)
+    const int32_t *vstate; // records of start row row_begin onwards
+    const void *vx;        // double[] or float[] (FP32 walk weights)
     const uint8_t *in_set; // null: every row requested
     double scale;
     uint32_t nb; // buckets
     double *dacc;
     unsigned long long *probes;
     unsigned long long *overflow; // set if a table ever fills (a planning error)
+    unsigned long long *queue;
 };
 
 template <bool WEIGHTED, class VT>
@@ -34,8 +80,11 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     __shared__ Batch bt;
     __shared__ uint32_t scan_scratch[kWaves];
     __shared__ unsigned long long red[kWaves];
+    __shared__ int64_t item_slot;
     const Shared sh = shared_views(smem, a.nb, &bt, scan_scratch, red);
     const int64_t span = int64_t(a.K - 1) * a.N;
+    const int64_t first = a.item_off[a.row_begin];
+    const int64_t last = a.item_off[a.row_end];
     unsigned long long probes = 0;
     RowJob job;
     job.N = a.N;
@@ -48,11 +97,19 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.scale = a.scale;
     job.dacc = a.dacc;
     job.overflow = a.overflow;
-    for (int64_t kk = blockIdx.x; kk < a.n_start; kk += gridDim.x) {
+    for (;;) {
+        const int64_t item = first + next_item(a.queue, &item_slot);
+        if (item >= last)
+            break;
+        const int64_t kk = row_of_item(a.item_off, a.row_begin, a.row_end, item);
+        const uint32_t part = static_cast<uint32_t>(item - a.item_off[kk]);
         job.k = a.starts[kk];
         job.rk = a.node[job.k];
-        job.st = a.vstate + kk * span;
-        gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + kk * span, probes);
+        job.p_begin = part * kBatch;
+        job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
+        job.st = a.vstate + (kk - a.row_begin) * span;
+        gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + (kk - a.row_begin) * span,
+                                 probes);
     }
     if (a.probes) {
         const unsigned long long total = dev::block_sum(probes, red);
@@ -63,17 +120,37 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
 
 } // namespace
 
-Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                   const int32_t *state, const void *x, const uint8_t *in_set, double *dacc,
-                   unsigned long long *probes, unsigned long long *overflow, hipStream_t s) {
-    if (n_start <= 0 || p.K < 2)
+Status gather_items(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t *off,
+                    hipStream_t s) {
+    if (n_start < 0)
+        return fail(MCMF_E_ARG, "negative start-row count");
+    DevBuf<uint32_t> cnt;
+    MCMF_TRY(cnt.alloc(n_start > 0 ? n_start : 1, s));
+    if (n_start > 0) {
+        const int64_t blocks = (n_start + 255) / 256;
+        hipLaunchKernelGGL(k_item_counts, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, starts,
+                           n_start, g->node, cnt.ptr);
+        MCMF_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(kScanThreads), 0, s, cnt.ptr, n_start, off);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
+Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *item_off,
+                   int64_t row_begin, int64_t row_end, const WalkParams &p, const int32_t *state,
+                   const void *x, const uint8_t *in_set, double *dacc, unsigned long long *probes,
+                   unsigned long long *overflow, unsigned long long *queue, hipStream_t s) {
+    if (row_end <= row_begin || p.K < 2)
         return {};
     GatherArgs a = {};
     a.node = g->node;
     a.col = g->col;
     a.val = g->val;
     a.starts = starts;
-    a.n_start = n_start;
+    a.item_off = item_off;
+    a.row_begin = row_begin;
+    a.row_end = row_end;
     a.N = p.n_walks;
     a.K = p.K;
     a.vstate = state;
@@ -82,6 +159,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
     a.scale = p.scale;
     a.dacc = dacc;
     a.probes = probes;
+    a.queue = queue;
     const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - kStaticLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);
     if (!plan.ok)
@@ -91,13 +169,15 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, 
     a.walks_per_pass = plan.walks_per_pass;
     a.overflow = overflow;
     const size_t lds = plan.lds_bytes;
-    const int64_t cap_blocks = int64_t(1) << 20;
-    const dim3 grid(static_cast<uint32_t>(n_start < cap_blocks ? n_start : cap_blocks));
     const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
     auto launch = [&](auto kernel) -> Status {
-        MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
-        hipLaunchKernelGGL(kernel, grid, dim3(kGatherThreads), lds, s, a);
+        const void *fn = reinterpret_cast<const void *>(kernel);
+        MCMF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        // Persistent workgroups: as many as fit on the device at once.
+        int per_cu = 0;
+        MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kGatherThreads, lds));
+        const int64_t blocks = int64_t(per_cu > 0 ? per_cu : 1) * num_cus();
+        hipLaunchKernelGGL(kernel, dim3(static_cast<uint32_t>(blocks)), dim3(kGatherThreads), lds, s, a);
         return {};
     };
     if (g->weighted)

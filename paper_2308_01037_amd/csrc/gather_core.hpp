@@ -68,22 +68,53 @@ struct Table {
         return (1u << ((h >> 6) & 31)) | (1u << ((h >> 11) & 31)) | (1u << (h & 31));
     }
 
-    // Returns false only if every bucket is full (the plan rules that out).
+    // Slot of key in a bucket read as (lo, hi), or -1.
+    __device__ __forceinline__ static int slot_in(const int4 &lo, const int4 &hi, int32_t key) {
+        int j = -1;
+        j = (lo.x == key) ? 0 : j;
+        j = (lo.y == key) ? 1 : j;
+        j = (lo.z == key) ? 2 : j;
+        j = (lo.w == key) ? 3 : j;
+        j = (hi.x == key) ? 4 : j;
+        j = (hi.y == key) ? 5 : j;
+        j = (hi.z == key) ? 6 : j;
+        j = (hi.w == key) ? 7 : j;
+        return j;
+    }
+
+    // Adds x to key's value, claiming a slot for a new key.  Each pass reads
+    // the bucket once: a present key gets the add; otherwise the first empty
+    // slot is claimed with one compare-and-swap (slots fill in order, so no
+    // key sits behind an empty slot).  A lost claim means another key took
+    // that slot, so the bucket is read again; a full bucket passes the probe
+    // on.  Every lost claim fills a slot, which bounds the passes.  Returns
+    // false only if every bucket is full (the plan rules that out).
     __device__ bool insert(int32_t key, double x) const {
         const uint32_t h = fhash(key);
         atomicOr(&filter[filter_word(h)], filter_mask(h));
         uint32_t b = bucket_of(key);
-        for (uint32_t tries = 0; tries < nb; ++tries) {
-#pragma unroll
-            for (int j = 0; j < kSlots; ++j) {
-                const uint32_t s = kSlots * b + j;
-                const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
-                if (prev == kEmpty || prev == key) {
-                    atomicAdd(&vals[s], x);
-                    return true;
-                }
+        const uint32_t max_passes = (kSlots + 1) * nb;
+        for (uint32_t pass = 0; pass < max_passes; ++pass) {
+            const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
+            const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
+            const int j = slot_in(lo, hi, key);
+            if (j >= 0) {
+                atomicAdd(&vals[kSlots * b + j], x);
+                return true;
             }
-            b = (b + 1 == nb) ? 0 : b + 1;
+            const int used = (lo.x != kEmpty) + (lo.y != kEmpty) + (lo.z != kEmpty) +
+                             (lo.w != kEmpty) + (hi.x != kEmpty) + (hi.y != kEmpty) +
+                             (hi.z != kEmpty) + (hi.w != kEmpty);
+            if (used == kSlots) {
+                b = (b + 1 == nb) ? 0 : b + 1;
+                continue;
+            }
+            const uint32_t s = kSlots * b + used;
+            const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
+            if (prev == kEmpty || prev == key) {
+                atomicAdd(&vals[s], x);
+                return true;
+            }
         }
         return false;
     }
@@ -94,15 +125,7 @@ struct Table {
     __device__ __forceinline__ double probe_bucket(int32_t key, uint32_t b, bool *more) const {
         const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
         const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
-        int j = -1;
-        j = (lo.x == key) ? 0 : j;
-        j = (lo.y == key) ? 1 : j;
-        j = (lo.z == key) ? 2 : j;
-        j = (lo.w == key) ? 3 : j;
-        j = (hi.x == key) ? 4 : j;
-        j = (hi.y == key) ? 5 : j;
-        j = (hi.z == key) ? 6 : j;
-        j = (hi.w == key) ? 7 : j;
+        const int j = slot_in(lo, hi, key);
         *more = false;
         if (j >= 0)
             return vals[kSlots * b + j];
@@ -121,9 +144,10 @@ struct Table {
         uint32_t fw[N], m[N];
 #pragma unroll
         for (int u = 0; u < N; ++u) {
+            // Every lane reads a filter word (any word serves for "no key").
             const uint32_t h = fhash(key[u]);
             m[u] = filter_mask(h);
-            fw[u] = key[u] >= 0 ? filter[filter_word(h)] : 0u;
+            fw[u] = filter[filter_word(h)];
         }
         uint32_t pending = 0;
 #pragma unroll
@@ -137,7 +161,8 @@ struct Table {
             for (int v = 0; v < H; ++v) {
                 const int u = half * H + v;
                 cand[v] = key[u] >= 0 && (fw[u] & m[u]) == m[u];
-                b[v] = cand[v] ? bucket_of(key[u]) : 0u;
+                const uint32_t home = bucket_of(key[u]);
+                b[v] = cand[v] ? home : 0u;
                 lo[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v]);
                 hi[v] = *reinterpret_cast<const int4 *>(keys + kSlots * b[v] + 4);
             }
@@ -145,16 +170,7 @@ struct Table {
 #pragma unroll
             for (int v = 0; v < H; ++v) {
                 const int u = half * H + v;
-                const int32_t k = key[u];
-                int j = -1;
-                j = (lo[v].x == k) ? 0 : j;
-                j = (lo[v].y == k) ? 1 : j;
-                j = (lo[v].z == k) ? 2 : j;
-                j = (lo[v].w == k) ? 3 : j;
-                j = (hi[v].x == k) ? 4 : j;
-                j = (hi[v].y == k) ? 5 : j;
-                j = (hi[v].z == k) ? 6 : j;
-                j = (hi[v].w == k) ? 7 : j;
+                int j = slot_in(lo[v], hi[v], key[u]);
                 j = cand[v] ? j : -1;
                 // Slots fill in order, so a full bucket ends with a used last slot.
                 pending |= (cand[v] && j < 0 && hi[v].w != kEmpty) ? (1u << u) : 0u;
@@ -211,6 +227,7 @@ struct Shared {
 struct RowJob {
     int32_t k;
     uint2 rk;               // record of row k
+    uint32_t p_begin, p_end; // neighbours [p_begin, p_end) of row k (positions in its row)
     const int32_t *st;      // visit states of row k, t-major (t * N + w)
     int64_t N;              // walks of row k
     int K;
@@ -273,8 +290,8 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             }
         }
         // (2) columns of the requested neighbours, kBatch neighbours at a time.
-        for (uint32_t p0 = 0; p0 < rk.y; p0 += kBatch) {
-            const uint32_t m = (rk.y - p0 < uint32_t(kBatch)) ? rk.y - p0 : uint32_t(kBatch);
+        for (uint32_t p0 = j.p_begin; p0 < j.p_end; p0 += kBatch) {
+            const uint32_t m = (j.p_end - p0 < uint32_t(kBatch)) ? j.p_end - p0 : uint32_t(kBatch);
             __syncthreads(); // table complete / previous batch flushed
             uint32_t nchunks = 0;
             if (threadIdx.x < kBatch) {
@@ -375,6 +392,37 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             }
         }
     }
+}
+
+// Work items.  A start row with d neighbours is cut into ceil(d / kBatch)
+// items of at most kBatch neighbours each; every item builds Q_k itself, so
+// the items of a high-degree row run on many workgroups at once.
+// item_off[kk] = first item of start row kk (exclusive prefix sums).
+__device__ __forceinline__ uint32_t items_of(uint32_t deg) {
+    return (deg + kBatch - 1) / kBatch;
+}
+
+// Start row kk in [lo, hi) with off[kk] <= item < off[kk + 1].
+__device__ __forceinline__ int64_t row_of_item(const int64_t *__restrict__ off, int64_t lo,
+                                               int64_t hi, int64_t item) {
+    while (hi - lo > 1) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (off[mid] <= item)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Next work item of the workgroup from a queue counter (one atomic per item,
+// broadcast through LDS).
+__device__ __forceinline__ int64_t next_item(unsigned long long *counter, int64_t *slot) {
+    __syncthreads(); // every thread has read the previous item
+    if (threadIdx.x == 0)
+        *slot = static_cast<int64_t>(atomicAdd(counter, 1ull));
+    __syncthreads();
+    return *slot;
 }
 
 // LDS bytes of the table for a plan, and of the fixed per-workgroup arrays.

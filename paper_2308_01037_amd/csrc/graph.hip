@@ -246,6 +246,7 @@ void free_graph(mcmf_graph *g) {
     dev_free_sync(g->node, sizeof(uint2) * g->n);
     dev_free_sync(g->edge, sizeof(uint4) * g->nnz);
     dev_free_sync(g->active, sizeof(int32_t) * g->n_active);
+    dev_free_sync(g->active_items, sizeof(int64_t) * (g->n_active + 1));
     dev_free_sync(g->bin_rows, sizeof(int32_t) * g->n);
     if (g->stream)
         (void)hipStreamDestroy(g->stream);
@@ -361,6 +362,9 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     if (g->n_active > 0)
         MCMF_HIP(hipMemcpyAsync(g->active, tmp_active.ptr, sizeof(int32_t) * g->n_active,
                                 hipMemcpyDeviceToDevice, s));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->active_items),
+                            sizeof(int64_t) * (g->n_active + 1)));
+    MCMF_TRY(gather_items(g, g->active, g->n_active, g->active_items, s));
     int64_t off = 0;
     for (int b = 0; b < 3; ++b) {
         g->bin_offset[b] = off;
@@ -369,6 +373,7 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     }
     MCMF_HIP(hipStreamSynchronize(s));
     g->bytes = (sizeof(int32_t) + sizeof(uint4)) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
+               sizeof(int64_t) * (g->n_active + 1) +
                (g->weighted ? sizeof(double) * (2 * nnz + n) : 0);
     return {};
 }

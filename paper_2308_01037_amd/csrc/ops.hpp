@@ -46,12 +46,21 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
                   int32_t *state, void *x, uint64_t *digest, unsigned long long *steps,
                   hipStream_t s);
 
-// Diag gather for starts[0..n_start) with their visit records: for each
-// requested neighbour i of k, dacc[i] += s^2 a_ki <Q_k, C_i> / N.
-// in_set == null means every row is requested.
-Status diag_gather(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
-                   const int32_t *state, const void *x, const uint8_t *in_set, double *dacc,
-                   unsigned long long *probes, unsigned long long *overflow, hipStream_t s);
+// Work items of the diag gather: off[kk] = first item of start row kk
+// (ceil(row length / 256) items per row), off[n_start] = total.  off has
+// n_start + 1 entries.
+Status gather_items(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t *off,
+                    hipStream_t s);
+
+// Diag gather for start rows starts[row_begin..row_end) of a start list with
+// item offsets item_off (gather_items), whose visit records begin at
+// state / x: for each requested neighbour i of a start row k,
+// dacc[i] += s^2 a_ki <Q_k, C_i> / N.  in_set == null means every row is
+// requested.  queue is a zeroed work counter used by this launch only.
+Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *item_off,
+                   int64_t row_begin, int64_t row_end, const WalkParams &p, const int32_t *state,
+                   const void *x, const uint8_t *in_set, double *dacc, unsigned long long *probes,
+                   unsigned long long *overflow, unsigned long long *queue, hipStream_t s);
 
 // Diag setup and assembly (api.hip).
 Status mark_rows(const int32_t *rows, int64_t count, int64_t n, uint8_t *in_set, int *bad,

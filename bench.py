@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--walks", type=int, default=256)
     ap.add_argument("--K", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=40,
+    ap.add_argument("--cpu-rows", type=int, default=12,
                     help="output rows per query in the oracle's timed sample")
     ap.add_argument("--only", choices=["all", "action", "diag"], default="all")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
@@ -67,19 +67,22 @@ def algorithmic_bytes(kind, st, K):
 
 
 # Kernel name fragment -> (roofline name, source file whose hash tags counter data).
-KERNELS = {"k_diag_gather": ("diag_gather", "gather.hip"),
-           "k_diag_walk": ("diag_walk", "walk.hip"),
-           "k_action_walk": ("action_walk", "walk.hip")}
+KERNELS = {"k_diag_gather": ("diag_gather", "gather.hip+gather_core.hpp"),
+           "k_diag_walk": ("diag_walk", "walk.hip+walk_core.hpp"),
+           "k_action_walk": ("action_walk", "walk.hip+walk_core.hpp")}
 # Calibration: an elementwise kernel that reads and writes a known byte count
 # (device-to-device memcpy may run on a DMA engine and show no kernel).
 COPY_KERNEL = "neg_kernel"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rmat20.md")
 
 
-def source_sha(fname):
+def source_sha(fnames):
+    """Hash of the '+'-separated source files a kernel is built from."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2308_01037_amd", "csrc", fname)
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for fname in fnames.split("+"):
+        h.update(open(os.path.join(ROOT, "paper_2308_01037_amd", "csrc", fname), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def kernel_label(name):
@@ -115,7 +118,8 @@ def summarize(directory, probe_bytes):
         agg = {}
         for path in counters:
             for r in csv.DictReader(open(path)):
-                name = kernel_label(r["Kernel_Name"])
+                full = r["Kernel_Name"]
+                name = COPY_KERNEL if COPY_KERNEL in full else kernel_label(full)
                 key = (name, r["Counter_Name"])
                 a = agg.setdefault(key, [0.0, set()])
                 a[0] += float(r["Counter_Value"])

@@ -130,7 +130,8 @@ typedef struct {
     uint64_t walk_steps;    /* recorded walk states (K-1 per full walk) */
     uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather */
     double ms_setup;        /* marks, start set, temporaries */
-    double ms_spmv;         /* r = sA v and the final assembly (action) */
+    double ms_spmv;         /* r = sA v and the final assembly (action);
+                               the final assembly of the diagonal (diag) */
     double ms_walk;         /* walk kernels */
     double ms_gather;       /* Q_k build + column gather + scatter (diag) */
     double ms_total;        /* whole call, device time */

@@ -464,7 +464,8 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         stats->gather_probes = hc[1];
         stats->ms_setup = tm.ms(0, 1);
         stats->ms_walk = ms_walk;
-        stats->ms_gather = ms_gather + tm.ms(2, 3);
+        stats->ms_gather = ms_gather;
+        stats->ms_spmv = tm.ms(2, 3);
         stats->ms_total = tm.ms(0, 3);
     }
     return {};

@@ -84,16 +84,32 @@ struct Pos {
     uint32_t l, start, deg;
 };
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Edge record load; STREAM marks it non-temporal.  The entry a step picks is
+// uniform over all stored entries (the walk's edge distribution), so records
+// are rarely reused from cache; keeping them out of the cache leaves it to
+// the vector the action walks read at every step.
+template <bool STREAM>
+__device__ __forceinline__ uint4 load_edge(const uint4 *e) {
+    if constexpr (STREAM) {
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(e));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *e;
+    }
+}
+
 // One transition out of row p (deg > 0) with the block of random words x.
 // Updates W (times s * sum |a|, sign of the entry) and returns the new row.
-template <bool WEIGHTED, class WT>
+template <bool WEIGHTED, class WT, bool STREAM = false>
 __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
                                     WT &W) {
     Pos n;
     if constexpr (!WEIGHTED) {
         const uint32_t j = dev::uniform_index(x.x, x.y, p.deg);
         W = W * static_cast<WT>(scale * static_cast<double>(p.deg));
-        const uint4 e = g.edge[int64_t(p.start) + j];
+        const uint4 e = load_edge<STREAM>(g.edge + (int64_t(p.start) + j));
         n.l = e.x;
         n.start = e.y;
         n.deg = e.z;
@@ -133,7 +149,7 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
         if (more) {
             const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
                                                a.key0, a.key1);
-            nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
+            nxt = step<WEIGHTED, WT, true>(g, p, x, a.scale, Wn);
         }
         wacc += static_cast<double>(static_cast<WT>(a.coef[t]) * W * static_cast<WT>(rl));
         if (DIGEST)

@@ -41,8 +41,10 @@ def parse():
     ap.add_argument("--only", choices=["all", "action", "diag"], default="all")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="after timing, run one device copy of this many bytes (counter calibration)")
-    ap.add_argument("--summarize", metavar="DIR",
-                    help="print a markdown summary of rocprofv3 CSV output in DIR and exit")
+    ap.add_argument("--summarize", metavar="DIR[,DIR...]",
+                    help="print a markdown summary of rocprofv3 CSV output in the directories and exit")
+    ap.add_argument("--record-sources", metavar="PATH",
+                    help="write the hashes of the timed kernels' sources to PATH (for --summarize)")
     ap.add_argument("--probe-bytes", type=int, default=0,
                     help="with --summarize: size of the calibration copy in that run")
     return ap.parse_args()
@@ -100,8 +102,10 @@ def summarize(directory, probe_bytes):
     import csv
     import glob
     lines = []
-    traces = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
-    counters = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    traces, counters = [], []
+    for d in directory.split(","):
+        traces += glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
+        counters += glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
     if traces:
         per = {}
         for path in traces:
@@ -130,6 +134,13 @@ def summarize(directory, probe_bytes):
         for (name, ctr), (tot, disp) in sorted(agg.items()):
             if any(f in name for f in list(KERNELS) + [COPY_KERNEL]):
                 lines.append(f"| `{name}` | {ctr} | {len(disp)} | {tot / len(disp):.1f} |")
+        # Source hashes recorded by the profiled run itself (--record-sources).
+        recorded = {}
+        for d in directory.split(","):
+            try:
+                recorded.update(json.load(open(os.path.join(d, "sources.json"))))
+            except OSError:
+                pass
         traffic = {}
         for ctr in ("FETCH_SIZE", "WRITE_SIZE"):
             copy = [(tot, disp) for (name, c), (tot, disp) in agg.items()
@@ -146,7 +157,9 @@ def summarize(directory, probe_bytes):
                 if hits:
                     tot2 = sum(h[0] for h in hits)
                     nd = sum(len(h[1]) for h in hits)
-                    t = traffic.setdefault(kname, {"source": src, "sha": source_sha(src)})
+                    if src not in recorded:
+                        continue  # no record of the sources this run was built from
+                    t = traffic.setdefault(kname, {"source": src, "sha": recorded[src]})
                     t[ctr.lower() + "_bytes_per_launch"] = tot2 / nd * 1024.0 * factor
         if traffic:
             lines.append("")
@@ -202,6 +215,11 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the estimator's "
               "multi-GPU sharding is a design note, not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.record_sources:
+        os.makedirs(os.path.dirname(os.path.abspath(args.record_sources)), exist_ok=True)
+        with open(args.record_sources, "w") as fh:
+            json.dump({src: source_sha(src) for _, src in KERNELS.values()}, fh)
 
     import torch
     import graphgen as G

@@ -255,7 +255,9 @@ typedef struct {
     int32_t use_graph;          /* 1: record the batch's launches in a hipGraph, then
                                    launch that graph (one submission for the batch) */
     int32_t reserved0;          /* must be zero */
-    uint32_t reserved[6];       /* must be zero */
+    uint64_t visit_chunk_bytes; /* diagonal visit-record buffer of the batch; 0: the
+                                   MCMF_DIAG_CHUNK_BYTES environment value or 2 GiB */
+    uint32_t reserved[4];       /* must be zero */
 } mcmf_batch_opts;
 
 /*
@@ -285,6 +287,83 @@ typedef struct {
  */
 mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *opts,
                        mcmf_stats *stats);
+
+/* ------------------------------------------------------------------ */
+/* Serving                                                             */
+/* ------------------------------------------------------------------ */
+
+/*
+ * A request server on one device: graphs stay resident (created beforehand
+ * with mcmf_graph_create), requests arrive from any host thread, and the
+ * server runs them with continuous batching.  A dispatcher admits queued
+ * requests in arrival order against a device-memory budget, groups them into
+ * a batch (mcmf_batch) whenever one of its n_streams stream slots is free,
+ * and hands the batch to that slot's worker; batches on different streams
+ * overlap on the device.  Requests that arrive while batches run join the
+ * next batch as slots and memory free up.  Results equal those of the
+ * request's own mcmf_diag / mcmf_action call up to the order of
+ * floating-point additions (keyed walks).
+ */
+typedef struct mcmf_server mcmf_server;
+
+typedef struct {
+    uint64_t hbm_budget_bytes;  /* admission budget: estimated device bytes of all
+                                   batches in flight; 0: no limit.  A request larger
+                                   than the budget runs alone once the device is idle. */
+    uint64_t visit_chunk_bytes; /* diagonal visit-record buffer per batch; 0: 256 MiB */
+    int32_t n_streams;          /* stream slots (batches in flight), 1..16; 0: 2 */
+    int32_t max_batch;          /* most requests per batch, >= 1; 0: 64 */
+    int32_t device;             /* HIP device of the server and its graphs */
+    int32_t use_graph;          /* 1: each batch is recorded into a hipGraph and launched */
+    uint32_t reserved[8];       /* must be zero */
+} mcmf_server_opts;
+
+typedef struct {
+    mcmf_status status;         /* the request's status */
+    int32_t batch_size;         /* requests in the batch it ran in */
+    double queue_ms;            /* submit -> start of its batch (host clock) */
+    double run_ms;              /* start -> end of its batch */
+    uint64_t est_bytes;         /* its admission estimate */
+} mcmf_ticket_info;
+
+typedef struct {
+    uint64_t submitted, completed, batches;
+    uint64_t bytes_in_flight;       /* current admission total */
+    uint64_t peak_bytes_in_flight;  /* largest admission total so far */
+    uint64_t peak_batches_in_flight;
+    uint64_t largest_batch;
+    uint32_t reserved[8];
+} mcmf_server_stats;
+
+/*
+ * mcmf_server_create -- start a server (its dispatcher and one worker thread
+ * per stream slot; streams at default priority).
+ * Errors: MCMF_E_ARG (null out, values out of range, non-zero reserved
+ * words), MCMF_E_DEVICE.
+ */
+mcmf_status mcmf_server_create(const mcmf_server_opts *opts, mcmf_server **out);
+
+/*
+ * mcmf_server_submit -- queue one request.  The request is checked here (an
+ * invalid one is refused with its status and never queued).  The request
+ * struct and every array it names must stay valid until mcmf_server_wait
+ * for its ticket returns; the outputs, status and walk_steps are written by
+ * then.  Thread-safe.
+ */
+mcmf_status mcmf_server_submit(mcmf_server *s, mcmf_request *req, uint64_t *ticket);
+
+/*
+ * mcmf_server_wait -- block until the ticket's request has run; returns its
+ * status (info optional).  Each ticket is waited for exactly once; an
+ * unknown or already-waited ticket gives MCMF_E_ARG.  Thread-safe.
+ */
+mcmf_status mcmf_server_wait(mcmf_server *s, uint64_t ticket, mcmf_ticket_info *info);
+
+/* Counters of the server (thread-safe snapshot). */
+mcmf_status mcmf_server_query(mcmf_server *s, mcmf_server_stats *stats);
+
+/* Run every queued request, stop the threads, free the server. */
+void mcmf_server_destroy(mcmf_server *s);
 
 /* Static name of a status code. */
 const char *mcmf_status_string(mcmf_status s);

@@ -240,6 +240,8 @@ struct Prep {
     bool all = false;
 };
 
+} // namespace
+
 Status check_request(mcmf_request &q) {
     mcmf_opts o = {};
     o.precision = q.precision;
@@ -262,6 +264,8 @@ Status check_request(mcmf_request &q) {
     }
     return {};
 }
+
+namespace {
 
 Status prepare(Prep &P, hipStream_t s) {
     mcmf_request &q = *P.req;
@@ -327,6 +331,8 @@ Status prepare(Prep &P, hipStream_t s) {
     }
     return {};
 }
+
+} // namespace
 
 Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, mcmf_stats *stats) {
     if (n_reqs < 0 || (n_reqs > 0 && !reqs))
@@ -430,6 +436,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     int64_t budget = int64_t(2) << 30;
     if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
         budget = std::max<int64_t>(1, strtoll(e, nullptr, 10));
+    if (o && o->visit_chunk_bytes)
+        budget = static_cast<int64_t>(std::min<uint64_t>(o->visit_chunk_bytes, uint64_t(1) << 62));
     // Gather runs are kept per kernel variant (one launch each).
     struct Chunk {
         std::vector<WSeg> w;
@@ -646,8 +654,6 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     }
     return {};
 }
-
-} // namespace
 
 } // namespace mcmf
 

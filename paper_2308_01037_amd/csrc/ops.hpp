@@ -73,4 +73,8 @@ Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int3
                     const mcmf_opts *o);
 WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N);
 
+// Batched execution (batch.hip): argument check of one request, and a batch.
+Status check_request(mcmf_request &q);
+Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, mcmf_stats *stats);
+
 } // namespace mcmf

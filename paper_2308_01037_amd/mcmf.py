@@ -92,7 +92,35 @@ class mcmf_request(ctypes.Structure):
 
 class mcmf_batch_opts(ctypes.Structure):
     _fields_ = [("stream", ctypes.c_void_p), ("use_graph", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 6)]
+                ("reserved0", ctypes.c_int32), ("visit_chunk_bytes", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint32 * 4)]
+
+
+class mcmf_server_opts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("visit_chunk_bytes", ctypes.c_uint64),
+                ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 8)]
+
+
+class mcmf_ticket_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("batch_size", ctypes.c_int32),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("est_bytes", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mcmf_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("bytes_in_flight", ctypes.c_uint64),
+                ("peak_bytes_in_flight", ctypes.c_uint64),
+                ("peak_batches_in_flight", ctypes.c_uint64), ("largest_batch", ctypes.c_uint64),
+                ("reserved", ctypes.c_uint32 * 8)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 _P = ctypes.c_void_p
@@ -111,13 +139,25 @@ _lib.mcmf_action.restype = ctypes.c_int
 _lib.mcmf_batch.argtypes = [ctypes.POINTER(mcmf_request), ctypes.c_int64,
                             ctypes.POINTER(mcmf_batch_opts), ctypes.POINTER(mcmf_stats)]
 _lib.mcmf_batch.restype = ctypes.c_int
+_lib.mcmf_server_create.argtypes = [ctypes.POINTER(mcmf_server_opts), ctypes.POINTER(_P)]
+_lib.mcmf_server_create.restype = ctypes.c_int
+_lib.mcmf_server_submit.argtypes = [_P, ctypes.POINTER(mcmf_request), ctypes.POINTER(ctypes.c_uint64)]
+_lib.mcmf_server_submit.restype = ctypes.c_int
+_lib.mcmf_server_wait.argtypes = [_P, ctypes.c_uint64, ctypes.POINTER(mcmf_ticket_info)]
+_lib.mcmf_server_wait.restype = ctypes.c_int
+_lib.mcmf_server_query.argtypes = [_P, ctypes.POINTER(mcmf_server_stats)]
+_lib.mcmf_server_query.restype = ctypes.c_int
+_lib.mcmf_server_destroy.argtypes = [_P]
+_lib.mcmf_server_destroy.restype = None
 _lib.mcmf_status_string.argtypes = [ctypes.c_int]
 _lib.mcmf_status_string.restype = ctypes.c_char_p
 _lib.mcmf_last_error.argtypes = []
 _lib.mcmf_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mcmf_graph_create", "mcmf_graph_destroy", "mcmf_graph_info", "mcmf_diag",
-            "mcmf_action", "mcmf_batch", "mcmf_status_string", "mcmf_last_error"]
+            "mcmf_action", "mcmf_batch", "mcmf_server_create", "mcmf_server_submit",
+            "mcmf_server_wait", "mcmf_server_query", "mcmf_server_destroy",
+            "mcmf_status_string", "mcmf_last_error"]
 
 
 class MCMFError(RuntimeError):
@@ -293,6 +333,38 @@ def mcmf_batch(reqs, opts: Optional[mcmf_batch_opts] = None,
         r.status = arr[i].status
         r.walk_steps = arr[i].walk_steps
     _raise(st)
+
+
+def mcmf_server_create(opts: Optional[mcmf_server_opts] = None) -> int:
+    out = _P()
+    _raise(_lib.mcmf_server_create(ctypes.byref(opts) if opts is not None else None,
+                                   ctypes.byref(out)))
+    return out.value
+
+
+def mcmf_server_submit(server: int, req: mcmf_request) -> int:
+    """Queues req (which must stay alive until its wait); returns the ticket."""
+    t = ctypes.c_uint64()
+    _raise(_lib.mcmf_server_submit(server, ctypes.byref(req), ctypes.byref(t)))
+    return t.value
+
+
+def mcmf_server_wait(server: int, ticket: int, raise_on_error: bool = True) -> mcmf_ticket_info:
+    info = mcmf_ticket_info()
+    st = _lib.mcmf_server_wait(server, ticket, ctypes.byref(info))
+    if raise_on_error:
+        _raise(st)
+    return info
+
+
+def mcmf_server_query(server: int) -> dict:
+    st = mcmf_server_stats()
+    _raise(_lib.mcmf_server_query(server, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def mcmf_server_destroy(server: int) -> None:
+    _lib.mcmf_server_destroy(server)
 
 
 # ---------------------------------------------------------------- convenience

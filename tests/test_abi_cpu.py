@@ -89,7 +89,9 @@ def test_struct_layouts_match_header(tmp_path):
     # The ctypes mirrors of the public structs must have the C layout.
     from paper_2308_01037_amd import mcmf as M
     structs = {"mcmf_fn": M.mcmf_fn, "mcmf_opts": M.mcmf_opts, "mcmf_stats": M.mcmf_stats,
-               "mcmf_request": M.mcmf_request, "mcmf_batch_opts": M.mcmf_batch_opts}
+               "mcmf_request": M.mcmf_request, "mcmf_batch_opts": M.mcmf_batch_opts,
+               "mcmf_server_opts": M.mcmf_server_opts, "mcmf_ticket_info": M.mcmf_ticket_info,
+               "mcmf_server_stats": M.mcmf_server_stats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcmf.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
@@ -133,3 +135,26 @@ def test_batch_argument_errors_need_no_device():
     with pytest.raises(M.MCMFError):
         M.mcmf_batch([kind])
     assert np.all(y == 0)
+
+
+def test_server_argument_errors_need_no_device():
+    import ctypes
+    from paper_2308_01037_amd import mcmf as M
+    lib = M._lib
+    out = ctypes.c_void_p()
+    assert lib.mcmf_server_create(None, None) == M.MCMF_E_ARG
+    o = M.mcmf_server_opts()
+    o.reserved[0] = 1
+    assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
+    o = M.mcmf_server_opts()
+    o.n_streams = 17
+    assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
+    assert "n_streams" in M.mcmf_last_error()
+    o = M.mcmf_server_opts()
+    o.max_batch = -1
+    assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
+    t = ctypes.c_uint64()
+    assert lib.mcmf_server_submit(None, None, ctypes.byref(t)) == M.MCMF_E_ARG
+    assert lib.mcmf_server_wait(None, 1, None) == M.MCMF_E_ARG
+    assert lib.mcmf_server_query(None, None) == M.MCMF_E_ARG
+    lib.mcmf_server_destroy(None)

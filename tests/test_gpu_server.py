@@ -1,0 +1,164 @@
+"""The request server (mcmf_server_*) on the GPU: continuous batching over
+several streams with admission by a device-memory budget.
+
+Every request's result in the mix equals its own single call's (path digests
+and step counts exact, estimates within 1e-10 relative), whatever batch it
+lands in; the admission estimate in flight never exceeds the budget unless a
+request runs alone; destroying the server runs what is still queued.
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import graphgen as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from _gpu import fn_struct, graph  # noqa: E402
+from _reqs import Req, check_same, close_graphs, make_graphs, mixed_requests  # noqa: E402
+from paper_2308_01037_amd import mcmf as M  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    gs = make_graphs()
+    yield gs
+    close_graphs(gs)
+
+
+def server(**kw):
+    o = M.mcmf_server_opts()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return M.mcmf_server_create(o)
+
+
+def serve(srv, reqs, threads=1, host=False):
+    """Submits reqs (from `threads` host threads), waits for all; returns the
+    results in request order and the ticket infos."""
+    made = [q.make(host) for q in reqs]
+    tickets = [None] * len(reqs)
+
+    def submit(idx):
+        for i in idx:
+            tickets[i] = M.mcmf_server_submit(srv, made[i][0])
+
+    parts = [list(range(t, len(reqs), threads)) for t in range(threads)]
+    ths = [threading.Thread(target=submit, args=(p,)) for p in parts]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    infos = [M.mcmf_server_wait(srv, t) for t in tickets]
+    torch.cuda.synchronize()
+    res = []
+    for q, (r, out, dig) in zip(reqs, made):
+        assert r.status == M.MCMF_OK
+        d = Req.fetch(out, dig, q.count)
+        d["steps"] = r.walk_steps
+        res.append(d)
+    return res, infos
+
+
+def test_served_mix_equals_single_calls(graphs):
+    reqs = mixed_requests(graphs) * 3
+    want = [q.single() for q in reqs]
+    srv = server(n_streams=3, max_batch=5)
+    try:
+        got, infos = serve(srv, reqs, threads=4)
+        st = M.mcmf_server_query(srv)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, g, w) in enumerate(zip(reqs, got, want)):
+        check_same(q, g, w, f"request {i}")
+    assert st["submitted"] == st["completed"] == len(reqs)
+    assert st["largest_batch"] <= 5
+    assert all(1 <= inf.batch_size <= 5 and inf.queue_ms >= 0 and inf.run_ms > 0 for inf in infos)
+
+
+def test_host_buffers_and_hipgraph_batches(graphs):
+    reqs = mixed_requests(graphs)[:8]
+    want = [q.single() for q in reqs]
+    srv = server(n_streams=2, max_batch=3, use_graph=1)
+    try:
+        got, _ = serve(srv, reqs, threads=2, host=True)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, g, w) in enumerate(zip(reqs, got, want)):
+        check_same(q, g, w, f"request {i}")
+
+
+def test_budget_admission(graphs):
+    # A budget that holds about two of these requests: the estimate in flight
+    # stays within it, and every request still completes.
+    g1, c1 = graphs["rmat11"]
+    reqs = [Req(g1, c1, M.MCMF_REQ_DIAG, "exp", 1.0 / c1.d_max, 32, 10, seed=3, request=i,
+                rows=np.arange(i, c1.n, 17)) for i in range(12)]
+    want = [q.single() for q in reqs]
+    probe = reqs[0].make()[0]
+    srv0 = server(n_streams=1)
+    try:
+        t = M.mcmf_server_submit(srv0, probe)
+        one = M.mcmf_server_wait(srv0, t).est_bytes
+    finally:
+        M.mcmf_server_destroy(srv0)
+    budget = int(2.5 * one)
+    srv = server(n_streams=4, max_batch=8, hbm_budget_bytes=budget, visit_chunk_bytes=1 << 20)
+    try:
+        got, infos = serve(srv, reqs, threads=3)
+        st = M.mcmf_server_query(srv)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, g, w) in enumerate(zip(reqs, got, want)):
+        check_same(q, g, w, f"request {i}")
+    assert st["peak_bytes_in_flight"] <= budget
+    assert st["completed"] == len(reqs)
+
+
+def test_request_larger_than_budget_runs_alone(graphs):
+    g1, c1 = graphs["rmat11"]
+    reqs = [Req(g1, c1, M.MCMF_REQ_ACTION, "exp", 1.0 / c1.d_max, 16, 8, seed=4, request=i)
+            for i in range(4)]
+    want = [q.single() for q in reqs]
+    srv = server(n_streams=3, hbm_budget_bytes=1024)
+    try:
+        got, infos = serve(srv, reqs, threads=2)
+        st = M.mcmf_server_query(srv)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, g, w) in enumerate(zip(reqs, got, want)):
+        check_same(q, g, w, f"request {i}")
+    assert st["peak_batches_in_flight"] == 1
+    assert all(inf.batch_size == 1 for inf in infos)
+
+
+def test_invalid_request_is_refused_and_destroy_drains(graphs):
+    g1, c1 = graphs["rmat11"]
+    csr = G.rmat(8, seed=1)
+    with graph(csr, flags=0) as gn:
+        bad = Req(gn, csr, M.MCMF_REQ_DIAG, "exp", 0.1, 8, 5).make()[0]
+        srv = server(n_streams=2)
+        try:
+            with pytest.raises(M.MCMFError) as e:
+                M.mcmf_server_submit(srv, bad)
+            assert e.value.status == M.MCMF_E_NOT_SYMMETRIC
+            with pytest.raises(M.MCMFError):
+                M.mcmf_server_wait(srv, 12345)
+            ok = Req(g1, c1, M.MCMF_REQ_ACTION, "resolvent", 0.05, 16, 6, seed=5)
+            made = [ok.make() for _ in range(6)]
+            for r, _, _ in made:
+                M.mcmf_server_submit(srv, r)
+        finally:
+            M.mcmf_server_destroy(srv)  # runs the queued requests first
+        torch.cuda.synchronize()
+        want = ok.single()
+        for r, out, dig in made:
+            assert r.status == M.MCMF_OK
+            got = Req.fetch(out, dig, ok.count)
+            got["steps"] = r.walk_steps
+            check_same(ok, got, want, "drained request")

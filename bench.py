@@ -47,6 +47,14 @@ def parse():
                     help="write the hashes of the timed kernels' sources to PATH (for --summarize)")
     ap.add_argument("--probe-bytes", type=int, default=0,
                     help="with --summarize: size of the calibration copy in that run")
+    ap.add_argument("--workload", choices=["hotpath", "batch", "serve"], default="hotpath",
+                    help="hotpath: the R-MAT workload above (default); batch: 64 uneven requests "
+                         "batched vs one at a time; serve: Poisson arrivals on resident graphs, "
+                         "served vs sequential")
+    ap.add_argument("--requests", type=int, default=0, help="batch/serve: number of requests")
+    ap.add_argument("--qps", type=float, default=0.0,
+                    help="serve: arrival rate (0: the sequential path's measured capacity)")
+    ap.add_argument("--seed", type=int, default=7, help="batch/serve: workload seed")
     return ap.parse_args()
 
 
@@ -206,6 +214,265 @@ def cpu_baseline(csr, queries, rows, K, N):
     return total_steps / total_s, total_steps, total_s, sample.size
 
 
+# ------------------------------------------------------------------ batch / serve
+
+TARGET_SE = 1e-3  # target standard error of every estimate, relative to its rms value
+
+
+class Query:
+    """One request of the batch / serve workloads and its device buffers."""
+
+    def __init__(self, M, torch, graph, csr, kind, fn, scale, K, rows=None, v=None, seed=1, rid=0):
+        self.M, self.torch = M, torch
+        self.graph, self.csr, self.kind, self.fn, self.scale, self.K = graph, csr, kind, fn, scale, K
+        self.rows = None if rows is None else torch.as_tensor(np.asarray(rows, np.int32), device="cuda")
+        self.v = None if v is None else torch.as_tensor(np.asarray(v, np.float64), device="cuda")
+        self.count = csr.n if (kind == M.MCMF_REQ_ACTION or rows is None) else len(rows)
+        self.seed, self.rid, self.N = seed, rid, 16
+        self.out = torch.empty(max(self.count, 1), dtype=torch.float64, device="cuda")
+
+    def request(self, rid=None, out=None):
+        M = self.M
+        return M.make_request(self.kind, self.graph.handle, M.make_fn(self.fn, self.scale), self.K,
+                              self.N, self.out if out is None else out, rows=self.rows, v=self.v,
+                              seed=self.seed, request_id=self.rid if rid is None else rid)
+
+    def single(self, stream):
+        M = self.M
+        opts = M.make_opts(seed=self.seed, request_id=self.rid, stream=stream)
+        f = M.make_fn(self.fn, self.scale)
+        if self.kind == M.MCMF_REQ_ACTION:
+            M.mcmf_action(self.graph.handle, f, self.v, self.N, self.K, opts, self.out)
+        else:
+            M.mcmf_diag(self.graph.handle, f, self.rows, 0 if self.rows is None else len(self.rows),
+                        self.N, self.K, opts, self.out)
+
+
+def pick_walks(M, torch, queries, n0=16, n_max=1024):
+    """Walks per start row from a pilot: two independent estimates with n0
+    walks give the estimator's spread se0 (relative to the estimate's rms);
+    N = n0 (se0 / target)^2, at most n_max."""
+    for q in queries:
+        q.N = n0
+    outs = [[torch.empty_like(q.out) for q in queries] for _ in range(2)]
+    for k in range(2):
+        M.mcmf_batch([q.request(rid=(1 << 30) + 2 * i + k, out=outs[k][i]) for i, q in enumerate(queries)])
+    torch.cuda.synchronize()
+    for i, q in enumerate(queries):
+        a = outs[0][i][:q.count].cpu().numpy()
+        b = outs[1][i][:q.count].cpu().numpy()
+        rms = float(np.sqrt(np.mean(a ** 2))) if q.count else 0.0
+        se0 = float(np.sqrt(np.mean((a - b) ** 2) / 2.0)) / rms if rms > 0 else 0.0
+        q.N = int(min(n_max, max(1, np.ceil(n0 * (se0 / TARGET_SE) ** 2))))
+
+
+def bench_batch(args):
+    """64 uneven requests over ER / R-MAT / grid graphs of 1e4..1e6 nodes:
+    one batched launch (eager and hipGraph) against one call per request."""
+    import torch
+    import graphgen as G
+    from paper_2308_01037_amd import mcmf as M
+    rng = np.random.default_rng(args.seed)
+    t0 = time.time()
+    specs = [("er1e4", lambda: G.erdos_renyi_gnm(10_000, 50_000, seed=1)),
+             ("er1e5", lambda: G.erdos_renyi_gnm(100_000, 500_000, seed=2)),
+             ("er1e6", lambda: G.erdos_renyi_gnm(1_000_000, 5_000_000, seed=3)),
+             ("rmat14", lambda: G.rmat(14, seed=4)),
+             ("rmat17", lambda: G.rmat(17, seed=5)),
+             ("rmat20", lambda: G.rmat(20, seed=6)),
+             ("grid1000", lambda: G.grid2d(1000, 1000))]
+    graphs = []
+    for name, make in specs:
+        csr = make()
+        graphs.append((name, csr, M.Graph.from_csr(csr), G.lambda_max(csr, 50)))
+    log(f"graphs ready ({time.time() - t0:.1f} s)")
+    n_req = args.requests or 64
+    queries = []
+    for i in range(n_req):
+        name, csr, g, lam = graphs[rng.integers(len(graphs))]
+        fn = M.MCMF_FN_EXP if rng.random() < 0.5 else M.MCMF_FN_RESOLVENT
+        scale = 1.0 / csr.d_max if fn == M.MCMF_FN_EXP else 0.85 / lam
+        if rng.random() < 0.5:
+            frac = rng.uniform(0.01, 0.05)
+            rows = np.sort(rng.choice(csr.n, max(1, int(frac * csr.n)), replace=False))
+            queries.append(Query(M, torch, g, csr, M.MCMF_REQ_DIAG, fn, scale, args.K, rows=rows,
+                                 seed=args.seed, rid=i))
+        else:
+            queries.append(Query(M, torch, g, csr, M.MCMF_REQ_ACTION, fn, scale, args.K,
+                                 v=rng.random(csr.n), seed=args.seed, rid=i))
+    pick_walks(M, torch, queries)
+    log("walks per row: " + " ".join(str(q.N) for q in queries))
+    stream = torch.cuda.current_stream().cuda_stream
+    reqs = [q.request() for q in queries]
+
+    def plain():
+        for q in queries:
+            q.single(stream)
+        torch.cuda.synchronize()
+
+    def batched(use_graph):
+        o = M.mcmf_batch_opts()
+        o.stream = stream
+        o.use_graph = 1 if use_graph else 0
+        M.mcmf_batch(reqs, o)
+        torch.cuda.synchronize()
+
+    times = {}
+    results = {}
+    for name, fn in (("plain", plain), ("batched", lambda: batched(False)),
+                     ("batched_graph", lambda: batched(True))):
+        fn()  # warm-up
+        ts = []
+        for _ in range(max(1, args.steps)):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        times[name] = float(np.median(ts))
+        results[name] = [q.out[:q.count].cpu().numpy().copy() for q in queries]
+        log(f"{name}: {times[name] * 1e3:.1f} ms for {n_req} requests")
+    worst = 0.0
+    for a, b in zip(results["plain"], results["batched_graph"]):
+        if a.size:
+            worst = max(worst, float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-300))))
+    steps = sum(r.walk_steps for r in reqs)
+    return {
+        "metric": "queries/s, batched vs plain one-request-at-a-time, equal walks per request",
+        "value": n_req / times["batched_graph"], "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "higher_is_better": True, "data": "synthetic", "dtype": "f64",
+        "config": {"workload": f"{n_req} requests: diag on 1-5% row subsets or f(A)v with v~U(0,1), "
+                               "exp(A/d_max) or (I-0.85A/lambda_max)^-1, over ER (avg degree 10) "
+                               "n=1e4/1e5/1e6, R-MAT 14/17/20 (ef 16), grid 1000x1000; "
+                               f"K={args.K}; N per request from a pilot for std error {TARGET_SE}",
+                   "walks_per_row": [q.N for q in queries]},
+        "queries_per_s": {k: n_req / v for k, v in times.items()},
+        "ms": {k: v * 1e3 for k, v in times.items()},
+        "speedup_vs_plain": times["plain"] / times["batched_graph"],
+        "walk_steps": steps,
+        "max_rel_diff_batched_vs_plain": worst,
+    }
+
+
+def bench_serve(args):
+    """Resident R-MAT graphs, Poisson arrivals of diag requests whose row
+    counts are log-uniform in [1, 1e5]: the server (continuous batching,
+    budget admission) against one request at a time in arrival order."""
+    import threading
+    import torch
+    import graphgen as G
+    from paper_2308_01037_amd import mcmf as M
+    rng = np.random.default_rng(args.seed)
+    t0 = time.time()
+    scales = [17, 18, 18, 19, 19, 20, 20, 21]
+    graphs = []
+    csr_bytes = 0
+    for i, sc in enumerate(scales):
+        csr = G.rmat(sc, seed=100 + i)
+        csr_bytes += csr.nnz * 4 + (csr.n + 1) * 8
+        graphs.append((f"rmat{sc}", csr, M.Graph.from_csr(csr), G.lambda_max(csr, 30)))
+    log(f"{len(graphs)} graphs resident ({csr_bytes / 2**30:.2f} GiB of CSR, {time.time() - t0:.1f} s)")
+    n_req = args.requests or 200
+    N = 64
+    queries = []
+    for i in range(n_req):
+        name, csr, g, lam = graphs[rng.integers(len(graphs))]
+        fn = M.MCMF_FN_EXP if rng.random() < 0.5 else M.MCMF_FN_RESOLVENT
+        scale = 1.0 / csr.d_max if fn == M.MCMF_FN_EXP else 0.85 / lam
+        count = int(min(csr.n, np.floor(np.exp(rng.uniform(0.0, np.log(1e5))))))
+        rows = np.sort(rng.choice(csr.n, max(1, count), replace=False))
+        q = Query(M, torch, g, csr, M.MCMF_REQ_DIAG, fn, scale, args.K, rows=rows, seed=args.seed, rid=i)
+        q.N = N
+        queries.append(q)
+    stream = torch.cuda.current_stream().cuda_stream
+    # Service times one at a time (also the warm-up), then the arrival rate.
+    svc = []
+    for q in queries[:20]:
+        t = time.perf_counter()
+        q.single(stream)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+    mean_svc = float(np.mean(svc))
+    qps = args.qps or 1.0 / mean_svc
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, n_req))
+    log(f"mean sequential service {mean_svc * 1e3:.1f} ms -> {qps:.1f} requests/s offered")
+
+    # Plain: one request at a time in arrival order.
+    lat_plain = []
+    start = time.perf_counter()
+    for q, a in zip(queries, arrivals):
+        now = time.perf_counter() - start
+        if now < a:
+            time.sleep(a - now)
+        q.single(stream)
+        torch.cuda.synchronize()
+        lat_plain.append(time.perf_counter() - start - a)
+    span_plain = time.perf_counter() - start
+    plain_out = [q.out[:q.count].cpu().numpy().copy() for q in queries]
+    log(f"plain: {n_req / span_plain:.1f} requests/s, p99 {np.percentile(lat_plain, 99) * 1e3:.0f} ms")
+
+    # Served: submissions at the arrival times, completions waited in order.
+    o = M.mcmf_server_opts()
+    o.n_streams = 4
+    o.max_batch = 32
+    o.hbm_budget_bytes = 64 << 30
+    o.visit_chunk_bytes = 1 << 30
+    srv = M.mcmf_server_create(o)
+    reqs = [q.request() for q in queries]
+    tickets = [None] * n_req
+    submitted = [0.0] * n_req
+    infos = [None] * n_req
+    start = time.perf_counter()
+
+    def waiter():
+        for i in range(n_req):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            infos[i] = M.mcmf_server_wait(srv, tickets[i])
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    for i, a in enumerate(arrivals):
+        now = time.perf_counter() - start
+        if now < a:
+            time.sleep(a - now)
+        submitted[i] = time.perf_counter() - start
+        tickets[i] = M.mcmf_server_submit(srv, reqs[i])
+    th.join()
+    span_srv = time.perf_counter() - start
+    st = M.mcmf_server_query(srv)
+    M.mcmf_server_destroy(srv)
+    torch.cuda.synchronize()
+    # Latency of each request: arrival -> end of its batch (the server's own
+    # clock from submission on), whatever order the completions are waited in.
+    lat_srv = [(sub - a) + (inf.queue_ms + inf.run_ms) * 1e-3
+               for sub, a, inf in zip(submitted, arrivals, infos)]
+    worst = 0.0
+    for q, p in zip(queries, plain_out):
+        x = q.out[:q.count].cpu().numpy()
+        if x.size:
+            worst = max(worst, float(np.max(np.abs(x - p) / np.maximum(np.abs(p), 1e-300))))
+    pct = lambda xs, p: float(np.percentile(xs, p) * 1e3)
+    return {
+        "metric": "served requests/s and p50/p99 latency vs plain sequential, equal walks per request",
+        "value": n_req / span_srv, "unit": "requests/s", "n_gpus": 1, "higher_is_better": True,
+        "data": "synthetic", "dtype": "f64",
+        "config": {"workload": f"{len(scales)} resident R-MAT graphs (scales {scales}, ef 16, "
+                               f"{csr_bytes / 2**30:.2f} GiB CSR); {n_req} diag requests, rows "
+                               "log-uniform in [1, 1e5], exp(A/d_max) or (I-0.85A/lambda_max)^-1, "
+                               f"K={args.K}, N={N}; Poisson arrivals at {qps:.1f}/s",
+                   "server": {"n_streams": o.n_streams, "max_batch": o.max_batch,
+                              "hbm_budget_bytes": o.hbm_budget_bytes,
+                              "visit_chunk_bytes": o.visit_chunk_bytes}},
+        "served": {"requests_per_s": n_req / span_srv, "p50_ms": pct(lat_srv, 50),
+                   "p99_ms": pct(lat_srv, 99), "batches": st["batches"],
+                   "largest_batch": st["largest_batch"],
+                   "peak_batches_in_flight": st["peak_batches_in_flight"],
+                   "peak_bytes_in_flight": st["peak_bytes_in_flight"]},
+        "plain": {"requests_per_s": n_req / span_plain, "p50_ms": pct(lat_plain, 50),
+                  "p99_ms": pct(lat_plain, 99)},
+        "max_rel_diff_served_vs_plain": worst,
+    }
+
+
 def main():
     args = parse()
     if args.summarize:
@@ -215,6 +482,12 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the estimator's "
               "multi-GPU sharding is a design note, not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
 
     if args.record_sources:
         os.makedirs(os.path.dirname(os.path.abspath(args.record_sources)), exist_ok=True)

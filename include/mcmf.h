@@ -299,7 +299,10 @@ mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts
  * requests in arrival order against a device-memory budget, groups them into
  * a batch (mcmf_batch) whenever one of its n_streams stream slots is free,
  * and hands the batch to that slot's worker; batches on different streams
- * overlap on the device.  Requests that arrive while batches run join the
+ * overlap on the device.  A batch completes as a unit, so requests join one
+ * only while its bound on walk steps stays within max_batch_steps: a large
+ * request runs on its own stream while small ones keep flowing on the
+ * others.  Requests that arrive while batches run join the
  * next batch as slots and memory free up.  Results equal those of the
  * request's own mcmf_diag / mcmf_action call up to the order of
  * floating-point additions (keyed walks).
@@ -315,7 +318,10 @@ typedef struct {
     int32_t max_batch;          /* most requests per batch, >= 1; 0: 64 */
     int32_t device;             /* HIP device of the server and its graphs */
     int32_t use_graph;          /* 1: each batch is recorded into a hipGraph and launched */
-    uint32_t reserved[8];       /* must be zero */
+    uint64_t max_batch_steps;   /* a batch takes further requests only while the bound on
+                                   its walk steps stays within this; a request above it
+                                   runs alone; 0: 2^28 */
+    uint32_t reserved[6];       /* must be zero */
 } mcmf_server_opts;
 
 typedef struct {
@@ -324,6 +330,7 @@ typedef struct {
     double queue_ms;            /* submit -> start of its batch (host clock) */
     double run_ms;              /* start -> end of its batch */
     uint64_t est_bytes;         /* its admission estimate */
+    uint64_t est_steps;         /* its bound on walk steps (batch forming) */
 } mcmf_ticket_info;
 
 typedef struct {

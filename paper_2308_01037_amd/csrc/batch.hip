@@ -17,6 +17,8 @@
 // up to the order of floating-point additions.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
+#include <utility>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -30,9 +32,11 @@ namespace mcmf {
 namespace {
 
 constexpr int kWalkThreads = 256;
-constexpr int kTaskWalks = 64;
 
-enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4 };
+// Walk kernel variant of a request: FP32 weights, weighted graph, weight
+// cutoff, path digest.
+enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4, kModeDigest = 8 };
+constexpr int kWalkModes = 16;
 
 // Device descriptor of one request.
 struct BReq {
@@ -51,14 +55,19 @@ struct BReq {
     int64_t wpp;               // walks per gather pass
 };
 
-// A run of one request's start rows inside a walk launch.
+// A run of one request's start rows inside a walk launch.  A task is one
+// workgroup (256 threads): with N >= 128 walks per row, all N walks of one
+// row (each thread loops over walks, as the single-request kernel does, so a
+// row's walks share one CU and its caches); with N < 128, all N walks of
+// rows_per_task = floor(256 / N) rows, one walk per thread.
 struct WSeg {
     int32_t req;
-    uint32_t tasks_per_row;
-    int64_t kk0;        // first start-row index in the request's start list
-    int64_t task_base;  // first task of this run in the launch
-    int64_t slot_base;  // diag: first visit slot of row kk0 in the chunk
-    int64_t xoff;       // diag: byte offset of that slot's value
+    uint32_t rows_per_task; // 0: one row per task (N >= 128)
+    int64_t kk0;            // first start-row index in the request's start list
+    int64_t rows;           // start rows in the run
+    int64_t task_base;      // first task of this run in the launch
+    int64_t slot_base;      // diag: first visit slot of row kk0 in the chunk
+    int64_t xoff;           // diag: byte offset of that slot's value
 };
 
 // A run of one request's start rows inside a gather launch.  item_base (the
@@ -73,43 +82,47 @@ struct GSeg {
     int64_t xoff;
 };
 
-template <class WT, bool WEIGHTED, bool CUTOFF>
-__device__ void run_task(const BReq &R, int64_t kk, uint32_t b, int32_t *vstate, WT *vx, int lane) {
-    const uint32_t k = static_cast<uint32_t>(R.starts[kk]);
-    const uint2 rk = R.g.node[k];
-    const int64_t w64 = int64_t(b) * kTaskWalks + lane;
-    const bool active = w64 < R.a.N;
-    uint64_t h = dev::kFnvBasis;
-    unsigned long long ns = 0;
+constexpr int64_t kRowTaskWalks = 128; // N at or above which a task is one row
+
+template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
+__device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t rel, uint32_t k, uint2 rk,
+                                         int64_t w, int32_t *vstate, unsigned char *vxb, double &acc,
+                                         uint64_t &h, unsigned long long &ns) {
+    const int64_t N = R.a.N;
     if (R.kind == MCMF_REQ_ACTION) {
-        double acc = 0.0;
-        if (active)
-            acc = walk::action_walk<WT, WEIGHTED, true, CUTOFF>(R.g, R.r, R.a, k, rk, R.r[k],
-                                                                 static_cast<uint32_t>(w64), &h, &ns);
-        acc = dev::wave_sum(acc);
-        if (lane == 0 && acc != 0.0)
-            atomicAdd(&R.q[k], acc / static_cast<double>(R.a.N));
-    } else if (active) {
-        walk::diag_walk<WT, WEIGHTED, true, CUTOFF>(R.g, R.a, k, rk, static_cast<uint32_t>(w64),
-                                                     vstate + w64, vx + w64, R.a.N, &h, &ns);
-    }
-    const unsigned long long hs = dev::wave_sum_u64(active ? h : 0ull);
-    const unsigned long long st = dev::wave_sum_u64(ns);
-    if (lane == 0) {
-        if (R.digest)
-            atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]), hs);
-        atomicAdd(R.steps, st);
+        acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF>(R.g, R.r, R.a, k, rk, R.r[k],
+                                                                static_cast<uint32_t>(w), &h, &ns);
+    } else {
+        const int64_t span = int64_t(R.a.K - 1) * N;
+        WT *vx = reinterpret_cast<WT *>(vxb + sg.xoff) + rel * span;
+        walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF>(R.g, R.a, k, rk, static_cast<uint32_t>(w),
+                                                       vstate + sg.slot_base + rel * span + w, vx + w, N,
+                                                       &h, &ns);
     }
 }
 
+template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
 __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restrict__ reqs,
                                                              const WSeg *__restrict__ segs,
                                                              int n_segs, int64_t n_tasks,
-                                                             int32_t *vstate, unsigned char *vxb) {
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
-    for (int64_t task = int64_t(blockIdx.x) * (blockDim.x / 64) + (threadIdx.x >> 6); task < n_tasks;
-         task += waves) {
+                                                             int32_t *vstate, unsigned char *vxb,
+                                                             unsigned long long *queue) {
+    __shared__ double red[kWalkThreads / 64];
+    __shared__ unsigned long long redu[kWalkThreads / 64];
+    __shared__ int64_t task_slot;
+    const int tid = threadIdx.x;
+    // Tasks come from a queue counter in order, so the rows in flight stay a
+    // narrow window of the task space (walks of neighbouring rows share cache
+    // lines on graphs with locality).  The next task is claimed while the
+    // current one runs.
+    if (tid == 0)
+        task_slot = static_cast<int64_t>(atomicAdd(queue, 1ull));
+    __syncthreads();
+    int64_t task = dev::uniform(task_slot);
+    while (task < n_tasks) {
+        unsigned long long next = 0;
+        if (tid == 0)
+            next = atomicAdd(queue, 1ull);
         int lo = 0, hi = n_segs;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -118,24 +131,77 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
             else
                 hi = mid;
         }
-        const WSeg sg = segs[lo];
+        const WSeg &sg = segs[lo];
         const BReq &R = reqs[sg.req];
+        const int64_t N = R.a.N;
         const int64_t local = task - sg.task_base;
-        const int64_t rel = local / sg.tasks_per_row;
-        const uint32_t b = static_cast<uint32_t>(local - rel * sg.tasks_per_row);
-        const int64_t span = int64_t(R.a.K - 1) * R.a.N;
-        int32_t *vs = vstate + sg.slot_base + rel * span;
-        switch (R.mode) {
-        case 0: run_task<double, false, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeFp32: run_task<float, false, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeWeighted: run_task<double, true, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeWeighted | kModeFp32: run_task<float, true, false>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeCutoff: run_task<double, false, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeCutoff | kModeFp32: run_task<float, false, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
-        case kModeCutoff | kModeWeighted: run_task<double, true, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<double *>(vxb + sg.xoff) + rel * span, lane); break;
-        default: run_task<float, true, true>(R, sg.kk0 + rel, b, vs, reinterpret_cast<float *>(vxb + sg.xoff) + rel * span, lane); break;
+        uint64_t h = dev::kFnvBasis;
+        unsigned long long ns = 0;
+        if (sg.rows_per_task == 0) {
+            // One row: every thread loops over its walks.
+            const int64_t rel = local;
+            const uint32_t k = static_cast<uint32_t>(dev::uniform(R.starts[sg.kk0 + rel]));
+            const uint2 rk = R.g.node[k];
+            double acc = 0.0;
+            uint64_t dig = 0;
+            for (int64_t w = tid; w < N; w += blockDim.x) {
+                h = dev::kFnvBasis;
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns);
+                dig += h;
+            }
+            if (R.kind == MCMF_REQ_ACTION) {
+                const double total = dev::block_sum(acc, red);
+                if (tid == 0 && total != 0.0)
+                    atomicAdd(&R.q[k], total / static_cast<double>(N));
+            }
+            if (DIGEST) {
+                const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+                if (tid == 0)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]), dg);
+            }
+        } else {
+            // Several rows, one walk per thread.
+            const int64_t rel = local * sg.rows_per_task + tid / N;
+            const int64_t w = tid % N;
+            if (tid < int64_t(sg.rows_per_task) * N && rel < sg.rows) {
+                const uint32_t k = static_cast<uint32_t>(R.starts[sg.kk0 + rel]);
+                const uint2 rk = R.g.node[k];
+                double acc = 0.0;
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns);
+                if (R.kind == MCMF_REQ_ACTION && acc != 0.0)
+                    atomicAdd(&R.q[k], acc / static_cast<double>(N));
+                if (DIGEST)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]),
+                              static_cast<unsigned long long>(h));
+            }
         }
+        const unsigned long long st = dev::block_sum(ns, redu);
+        if (tid == 0) {
+            atomicAdd(R.steps, st);
+            task_slot = static_cast<int64_t>(next);
+        }
+        __syncthreads();
+        task = dev::uniform(task_slot);
     }
+}
+
+using WalkKernel = void (*)(const BReq *, const WSeg *, int, int64_t, int32_t *, unsigned char *,
+                            unsigned long long *);
+
+template <int M>
+WalkKernel walk_kernel_of() {
+    using WT = typename std::conditional<(M & kModeFp32) != 0, float, double>::type;
+    return &k_batch_walk<WT, (M & kModeWeighted) != 0, (M & kModeCutoff) != 0, (M & kModeDigest) != 0>;
+}
+
+template <int... M>
+WalkKernel walk_kernel_in(int m, std::integer_sequence<int, M...>) {
+    WalkKernel table[] = {walk_kernel_of<M>()...};
+    return table[m];
+}
+
+WalkKernel walk_kernel(int mode) {
+    return walk_kernel_in(mode, std::make_integer_sequence<int, kWalkModes>{});
 }
 
 // Item bases of the runs of one gather launch (one thread; runs are few).
@@ -166,7 +232,7 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
     const int64_t n_items = segs[n_segs].item_base;
     unsigned long long probes = 0;
     for (;;) {
-        const int64_t item = next_item(queue, &item_slot);
+        const int64_t item = dev::uniform(next_item(queue, &item_slot));
         if (item >= n_items)
             break;
         int lo = 0, hi = n_segs;
@@ -179,14 +245,16 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         }
         const GSeg sg = segs[lo];
         const BReq &R = reqs[sg.req];
-        const int64_t ri = R.item_off[sg.kk0] + (item - sg.item_base);
-        const int64_t kk = row_of_item(R.item_off, sg.kk0, sg.kk0 + sg.rows, ri);
-        const uint32_t part = static_cast<uint32_t>(ri - R.item_off[kk]);
+        const int64_t ri = dev::uniform(R.item_off[sg.kk0]) + (item - sg.item_base);
+        const int64_t kk = dev::uniform(row_of_item(R.item_off, sg.kk0, sg.kk0 + sg.rows, ri));
+        const uint32_t part = static_cast<uint32_t>(ri - dev::uniform(R.item_off[kk]));
         const int64_t rel = kk - sg.kk0;
         const int64_t span = int64_t(R.a.K - 1) * R.a.N;
         RowJob job;
-        job.k = R.starts[kk];
-        job.rk = R.g.node[job.k];
+        job.k = dev::uniform(R.starts[kk]);
+        const uint2 rk = R.g.node[job.k];
+        job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
+                            static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
         job.p_begin = part * kBatch;
         job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
         job.st = vstate + sg.slot_base + rel * span;
@@ -376,7 +444,6 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
 
     // Descriptors.
     std::vector<BReq> hreq(n_reqs);
-    int64_t max_visit_row = 0;
     for (int64_t i = 0; i < n_reqs; ++i) {
         const mcmf_request &q = reqs[i];
         Prep &P = *preps[i];
@@ -391,7 +458,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.a = walk::to_args(walk_params(&oo, P.coef.ptr, q.K, q.fn.scale, q.n_walks));
         B.kind = q.kind;
         B.mode = (q.precision == MCMF_PRECISION_FP32_WEIGHTS ? kModeFp32 : 0) |
-                 (q.graph->weighted ? kModeWeighted : 0) | (q.weight_cutoff > 0.0 ? kModeCutoff : 0);
+                 (q.graph->weighted ? kModeWeighted : 0) | (q.weight_cutoff > 0.0 ? kModeCutoff : 0) |
+                 (P.dig.ptr ? kModeDigest : 0);
         B.starts = P.starts;
         B.r = P.r.ptr;
         B.q = P.q.ptr;
@@ -399,18 +467,18 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.in_set = P.all ? nullptr : P.in_set.ptr;
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
-        if (q.kind == MCMF_REQ_DIAG && q.K >= 2)
-            max_visit_row = std::max<int64_t>(max_visit_row, q.n_walks * (q.K - 1));
     }
     DevBuf<unsigned long long> counters; // per request steps, then probes, overflow
     MCMF_TRY(counters.alloc(n_reqs + 2, s));
     for (int64_t i = 0; i < n_reqs; ++i)
         hreq[i].steps = counters.ptr + i;
 
-    // Gather plan: one table size for the whole batch, walks per pass per request.
+    // Gather plan of each diagonal request: its own table size (so a request
+    // with few walks keeps a small table and many workgroups per CU) and
+    // walks per pass.
     const size_t table_lds = 160 * 1024 - gather::kStaticLds;
-    uint32_t nb = 0;
-    size_t lds = 0;
+    std::vector<uint32_t> req_nb(n_reqs, 0);
+    std::vector<size_t> req_lds(n_reqs, 0);
     for (int64_t i = 0; i < n_reqs; ++i) {
         const mcmf_request &q = reqs[i];
         if (q.kind != MCMF_REQ_DIAG || q.K < 2 || preps[i]->n_start == 0)
@@ -421,10 +489,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             return fail(MCMF_E_UNSUPPORTED, "no Q_k table layout fits LDS for N=%lld, K=%d",
                         static_cast<long long>(q.n_walks), q.K);
         hreq[i].wpp = plan.walks_per_pass;
-        if (plan.cap / gather::kSlots > nb) {
-            nb = static_cast<uint32_t>(plan.cap / gather::kSlots);
-            lds = plan.lds_bytes;
-        }
+        req_nb[i] = static_cast<uint32_t>(plan.cap / gather::kSlots);
+        req_lds[i] = plan.lds_bytes;
     }
     DevBuf<BReq> dreq;
     MCMF_TRY(dreq.alloc(n_reqs, s));
@@ -432,28 +498,52 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
 
     // Launch plan: chunk 0 = every action task + the first diag rows; later
     // chunks = diag rows only.  Each chunk holds at most `budget` bytes of
-    // visit records.
+    // visit records.  Walk runs are kept per walk-kernel variant, gather runs
+    // per (gather variant, table size): one launch each.
     int64_t budget = int64_t(2) << 30;
     if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
         budget = std::max<int64_t>(1, strtoll(e, nullptr, 10));
     if (o && o->visit_chunk_bytes)
         budget = static_cast<int64_t>(std::min<uint64_t>(o->visit_chunk_bytes, uint64_t(1) << 62));
-    // Gather runs are kept per kernel variant (one launch each).
+    struct GatherGroup {
+        int variant;
+        uint32_t nb;
+        size_t lds;
+        std::vector<GSeg> segs;
+    };
     struct Chunk {
-        std::vector<WSeg> w;
-        std::vector<GSeg> gs[kGatherVariants];
-        int64_t items[kGatherVariants] = {0, 0, 0, 0}; // start rows per variant
-        int64_t tasks = 0, rows = 0, slots = 0, xbytes = 0;
+        std::vector<WSeg> w[kWalkModes];
+        int64_t tasks[kWalkModes] = {};
+        std::vector<GatherGroup> g;
+        int64_t rows = 0, slots = 0, xbytes = 0;
+    };
+    auto add_walks = [&](Chunk &c, int64_t i, int64_t kk0, int64_t rows, int64_t slot_base, int64_t xoff) {
+        const int m = hreq[i].mode;
+        const int64_t N = reqs[i].n_walks;
+        WSeg w = {};
+        w.req = static_cast<int32_t>(i);
+        w.kk0 = kk0;
+        w.rows = rows;
+        w.task_base = c.tasks[m];
+        w.slot_base = slot_base;
+        w.xoff = xoff;
+        int64_t tasks;
+        if (N >= kRowTaskWalks) {
+            w.rows_per_task = 0;
+            tasks = rows;
+        } else {
+            w.rows_per_task = static_cast<uint32_t>(kWalkThreads / N);
+            tasks = (rows + w.rows_per_task - 1) / w.rows_per_task;
+        }
+        c.w[m].push_back(w);
+        c.tasks[m] += tasks;
     };
     std::vector<Chunk> chunks(1);
     for (int64_t i = 0; i < n_reqs; ++i) {
         const mcmf_request &q = reqs[i];
         if (q.kind != MCMF_REQ_ACTION || q.K < 2 || preps[i]->n_start == 0)
             continue;
-        const uint32_t tpr = static_cast<uint32_t>((q.n_walks + kTaskWalks - 1) / kTaskWalks);
-        Chunk &c = chunks[0];
-        c.w.push_back(WSeg{static_cast<int32_t>(i), tpr, 0, c.tasks, 0, 0});
-        c.tasks += preps[i]->n_start * tpr;
+        add_walks(chunks[0], i, 0, preps[i]->n_start, 0, 0);
     }
     for (int64_t i = 0; i < n_reqs; ++i) {
         const mcmf_request &q = reqs[i];
@@ -462,7 +552,6 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         const int64_t span = q.n_walks * (q.K - 1);
         const int64_t xb = q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
         const int64_t row_bytes = span * (4 + xb);
-        const uint32_t tpr = static_cast<uint32_t>((q.n_walks + kTaskWalks - 1) / kTaskWalks);
         const int var = (q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 1 : 0) | (q.graph->weighted ? 2 : 0);
         int64_t kk = 0;
         while (kk < preps[i]->n_start) {
@@ -477,10 +566,16 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             const int64_t take = std::min(fit, preps[i]->n_start - kk);
             // Value arrays are 8-byte aligned per run.
             c.xbytes = (c.xbytes + 7) & ~int64_t(7);
-            c.w.push_back(WSeg{static_cast<int32_t>(i), tpr, kk, c.tasks, c.slots, c.xbytes});
-            c.gs[var].push_back(GSeg{static_cast<int32_t>(i), kk, take, 0, c.slots, c.xbytes});
-            c.tasks += take * tpr;
-            c.items[var] += take;
+            add_walks(c, i, kk, take, c.slots, c.xbytes);
+            GatherGroup *grp = nullptr;
+            for (auto &gg : c.g)
+                if (gg.variant == var && gg.nb == req_nb[i])
+                    grp = &gg;
+            if (!grp) {
+                c.g.push_back(GatherGroup{var, req_nb[i], req_lds[i], {}});
+                grp = &c.g.back();
+            }
+            grp->segs.push_back(GSeg{static_cast<int32_t>(i), kk, take, 0, c.slots, c.xbytes});
             c.rows += take;
             c.slots += take * span;
             c.xbytes += take * span * xb;
@@ -496,41 +591,67 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     DevBuf<unsigned char> vxb;
     MCMF_TRY(vstate.alloc(max_slots > 0 ? max_slots : 1, s));
     MCMF_TRY(vxb.alloc(max_xbytes > 0 ? max_xbytes : 8, s));
+    // Device copies of the run tables; the gather table of a group carries a
+    // spare entry for its item count.
     std::vector<std::unique_ptr<DevBuf<WSeg>>> dws;
     std::vector<std::unique_ptr<DevBuf<GSeg>>> dgs;
+    size_t lds_max[kGatherVariants] = {0, 0, 0, 0};
+    int64_t n_groups = 0;
     for (const Chunk &c : chunks) {
-        dws.emplace_back(new DevBuf<WSeg>());
-        if (!c.w.empty()) {
-            MCMF_TRY(dws.back()->alloc(c.w.size(), s));
-            MCMF_HIP(hipMemcpyAsync(dws.back()->ptr, c.w.data(), sizeof(WSeg) * c.w.size(),
+        for (int m = 0; m < kWalkModes; ++m) {
+            dws.emplace_back(new DevBuf<WSeg>());
+            if (c.w[m].empty())
+                continue;
+            MCMF_TRY(dws.back()->alloc(c.w[m].size(), s));
+            MCMF_HIP(hipMemcpyAsync(dws.back()->ptr, c.w[m].data(), sizeof(WSeg) * c.w[m].size(),
                                     hipMemcpyHostToDevice, s));
         }
-        for (int v = 0; v < kGatherVariants; ++v) {
+        for (const GatherGroup &gg : c.g) {
             dgs.emplace_back(new DevBuf<GSeg>());
-            if (c.gs[v].empty())
-                continue;
-            MCMF_TRY(dgs.back()->alloc(c.gs[v].size() + 1, s));
-            MCMF_HIP(hipMemcpyAsync(dgs.back()->ptr, c.gs[v].data(), sizeof(GSeg) * c.gs[v].size(),
+            MCMF_TRY(dgs.back()->alloc(gg.segs.size() + 1, s));
+            MCMF_HIP(hipMemcpyAsync(dgs.back()->ptr, gg.segs.data(), sizeof(GSeg) * gg.segs.size(),
                                     hipMemcpyHostToDevice, s));
+            lds_max[gg.variant] = std::max(lds_max[gg.variant], gg.lds);
+            ++n_groups;
         }
     }
-    // Persistent gather workgroups: as many as fit on the device at once.
-    int64_t gather_blocks[kGatherVariants] = {0, 0, 0, 0};
-    if (nb > 0)
-        for (int v = 0; v < kGatherVariants; ++v) {
-            const void *fn = reinterpret_cast<const void *>(gather_kernel(v));
-            MCMF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+    for (int v = 0; v < kGatherVariants; ++v)
+        if (lds_max[v] > 0)
+            MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gather_kernel(v)),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds_max[v])));
+    // Persistent gather workgroups per group: as many as fit at once.
+    std::vector<int64_t> group_blocks;
+    for (const Chunk &c : chunks)
+        for (const GatherGroup &gg : c.g) {
             int per_cu = 0;
-            MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, gather::kGatherThreads, lds));
-            gather_blocks[v] = int64_t(per_cu > 0 ? per_cu : 1) * num_cus();
+            MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void *>(gather_kernel(gg.variant)), gather::kGatherThreads,
+                gg.lds));
+            group_blocks.push_back(int64_t(per_cu > 0 ? per_cu : 1) * num_cus());
         }
-    // One work counter per gather launch.
-    const int64_t n_queues = static_cast<int64_t>(chunks.size()) * kGatherVariants;
+    // One work counter per gather launch, then one per (chunk, walk mode).
+    const int64_t walk_queue0 = n_groups;
+    const int64_t n_queues = n_groups + static_cast<int64_t>(chunks.size()) * kWalkModes;
     DevBuf<unsigned long long> queues;
     MCMF_TRY(queues.alloc(n_queues, s));
 
+    // Walk workgroups: exactly as many as are resident at once.  The tasks
+    // are dealt out in order, so the device works through a narrow window of
+    // the task space (one or two requests, one graph's data in the caches);
+    // workgroups waiting for a slot would start at the front of the task
+    // space and spread the window over every request.
+    int64_t walk_blocks[kWalkModes] = {};
+    for (const Chunk &c : chunks)
+        for (int m = 0; m < kWalkModes; ++m)
+            if (c.tasks[m] > 0 && walk_blocks[m] == 0) {
+                int per_cu = 0;
+                MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void *>(walk_kernel(m)), kWalkThreads, 0));
+                walk_blocks[m] = int64_t(per_cu > 0 ? per_cu : 1) * num_cus();
+            }
+
     // The device work of the batch: fills, walks, gathers, assembly.
-    const int64_t walk_blocks_cap = int64_t(num_cus()) * 16;
     auto enqueue = [&]() -> Status {
         MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, n_reqs + 2, s));
         MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_queues, s));
@@ -544,27 +665,29 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             if (P.dig.ptr)
                 MCMF_TRY(fill_u64(P.dig.ptr, 0, n, s));
         }
+        int64_t gi = 0;
         for (size_t ci = 0; ci < chunks.size(); ++ci) {
             const Chunk &c = chunks[ci];
-            if (c.tasks > 0) {
-                const int64_t blocks = std::min<int64_t>(walk_blocks_cap, (c.tasks + 3) / 4);
-                hipLaunchKernelGGL(k_batch_walk, dim3(static_cast<uint32_t>(blocks)), dim3(kWalkThreads), 0,
-                                   s, dreq.ptr, dws[ci]->ptr, static_cast<int>(c.w.size()), c.tasks,
-                                   vstate.ptr, vxb.ptr);
+            for (int m = 0; m < kWalkModes; ++m) {
+                if (c.tasks[m] == 0)
+                    continue;
+                const int64_t blocks = std::min<int64_t>(walk_blocks[m], c.tasks[m]);
+                hipLaunchKernelGGL(walk_kernel(m), dim3(static_cast<uint32_t>(blocks)), dim3(kWalkThreads), 0,
+                                   s, dreq.ptr, dws[ci * kWalkModes + m]->ptr, static_cast<int>(c.w[m].size()),
+                                   c.tasks[m], vstate.ptr, vxb.ptr,
+                                   queues.ptr + walk_queue0 + static_cast<int64_t>(ci) * kWalkModes + m);
                 MCMF_HIP(hipGetLastError());
             }
-            for (int v = 0; v < kGatherVariants; ++v) {
-                if (c.items[v] == 0)
-                    continue;
-                GSeg *segs = dgs[ci * kGatherVariants + v]->ptr;
-                const int n_segs = static_cast<int>(c.gs[v].size());
+            for (const GatherGroup &gg : c.g) {
+                GSeg *segs = dgs[gi]->ptr;
+                const int n_segs = static_cast<int>(gg.segs.size());
                 hipLaunchKernelGGL(k_seg_items, dim3(1), dim3(64), 0, s, dreq.ptr, segs, n_segs);
                 MCMF_HIP(hipGetLastError());
-                hipLaunchKernelGGL(gather_kernel(v), dim3(static_cast<uint32_t>(gather_blocks[v])),
-                                   dim3(gather::kGatherThreads), lds, s, dreq.ptr, segs, n_segs,
-                                   vstate.ptr, vxb.ptr, nb, counters.ptr + n_reqs,
-                                   queues.ptr + ci * kGatherVariants + v);
+                hipLaunchKernelGGL(gather_kernel(gg.variant), dim3(static_cast<uint32_t>(group_blocks[gi])),
+                                   dim3(gather::kGatherThreads), gg.lds, s, dreq.ptr, segs, n_segs,
+                                   vstate.ptr, vxb.ptr, gg.nb, counters.ptr + n_reqs, queues.ptr + gi);
                 MCMF_HIP(hipGetLastError());
+                ++gi;
             }
         }
         for (int64_t i = 0; i < n_reqs; ++i) {

@@ -6,7 +6,9 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "mcmf.h"
 
@@ -158,4 +160,8 @@ struct mcmf_graph {
     int64_t bin_count[3] = {0, 0, 0};
     int64_t bin_offset[3] = {0, 0, 0};
     size_t bytes = 0;
+
+    // Host copy of the row lengths, made on first use (request sizing).
+    std::mutex host_mu;
+    std::vector<uint32_t> host_len;
 };

@@ -50,6 +50,16 @@ __device__ __forceinline__ uint64_t fnv_step(uint64_t h, uint32_t word) {
 
 // ---- reductions over a 64-wide wavefront ----
 
+// A value known to be equal on every lane of the wavefront, moved to a
+// scalar register so that what is computed from it stays scalar too.
+__device__ __forceinline__ int32_t uniform(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform(int64_t x) {
+    const uint64_t u = static_cast<uint64_t>(x);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((uint64_t(hi) << 32) | lo);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)

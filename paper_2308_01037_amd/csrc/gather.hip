@@ -98,13 +98,15 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.dacc = a.dacc;
     job.overflow = a.overflow;
     for (;;) {
-        const int64_t item = first + next_item(a.queue, &item_slot);
+        const int64_t item = dev::uniform(first + next_item(a.queue, &item_slot));
         if (item >= last)
             break;
-        const int64_t kk = row_of_item(a.item_off, a.row_begin, a.row_end, item);
-        const uint32_t part = static_cast<uint32_t>(item - a.item_off[kk]);
-        job.k = a.starts[kk];
-        job.rk = a.node[job.k];
+        const int64_t kk = dev::uniform(row_of_item(a.item_off, a.row_begin, a.row_end, item));
+        const uint32_t part = static_cast<uint32_t>(item - dev::uniform(a.item_off[kk]));
+        job.k = dev::uniform(a.starts[kk]);
+        const uint2 rk = a.node[job.k];
+        job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
+                            static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
         job.p_begin = part * kBatch;
         job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
         job.st = a.vstate + (kk - a.row_begin) * span;

@@ -40,39 +40,76 @@ struct Ticket {
     mcmf_request *req = nullptr;
     uint64_t fixed_bytes = 0;  // per-request arrays
     uint64_t visit_bytes = 0;  // upper bound of its visit records
+    uint64_t steps = 0;        // upper bound of its walk steps
     Clock::time_point submitted, started, finished;
     int32_t batch_size = 0;
     bool done = false;
 };
 
-// Device bytes one request holds while its batch runs, without the shared
-// visit-record buffer (host-side estimate from sizes only).
-void estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits) {
-    const uint64_t n = static_cast<uint64_t>(q.graph->n);
+// Row lengths of a graph on the host (copied once per graph).
+Status host_lengths(mcmf_graph *g, const std::vector<uint32_t> **out) {
+    std::lock_guard<std::mutex> lock(g->host_mu);
+    if (g->host_len.size() != static_cast<size_t>(g->n)) {
+        std::vector<uint2> node(static_cast<size_t>(g->n));
+        if (g->n > 0) {
+            MCMF_HIP(hipSetDevice(g->device));
+            MCMF_HIP(hipMemcpy(node.data(), g->node, sizeof(uint2) * node.size(), hipMemcpyDeviceToHost));
+        }
+        std::vector<uint32_t> len(node.size());
+        for (size_t i = 0; i < node.size(); ++i)
+            len[i] = node[i].y;
+        g->host_len.swap(len);
+    }
+    *out = &g->host_len;
+    return {};
+}
+
+// Host-side sizing of one request: device bytes it holds while its batch
+// runs (without the shared visit-record buffer), an upper bound of its
+// visit-record bytes and of its walk steps.  A diagonal request on a row
+// subset starts walks only from neighbours of its rows, so the sum of their
+// lengths bounds its start rows.
+Status estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64_t *steps) {
+    mcmf_graph *g = const_cast<mcmf_graph *>(q.graph);
+    const uint64_t n = static_cast<uint64_t>(g->n);
     const uint64_t kb = q.K >= 2 ? static_cast<uint64_t>(q.K) : 2;
     uint64_t f = 8 * kb + 64 * 1024; // coefficients, descriptors, rounding slack
-    uint64_t v = 0;
+    uint64_t starts = q.K >= 2 ? static_cast<uint64_t>(g->n_active) : 0;
     if (q.kind == MCMF_REQ_ACTION) {
         f += 8 * n * 4; // v and out staging, r, q
-        if (q.path_digest)
-            f += 8 * n;
     } else {
         const uint64_t count = q.rows ? static_cast<uint64_t>(q.n_rows) : n;
         f += 8 * n + 2 * n + 4 * n + 8 * (n + 1) + 12 * count; // dacc, marks, start list, items, rows/out
-        if (q.path_digest)
-            f += 8 * n;
-        if (q.K >= 2) {
-            uint64_t starts = static_cast<uint64_t>(q.graph->n_active);
-            if (q.rows) {
-                const uint64_t bound = count * static_cast<uint64_t>(std::max<int64_t>(q.graph->d_max, 1));
-                starts = std::min(starts, bound);
+        if (q.rows && starts > 0) {
+            const std::vector<uint32_t> *len = nullptr;
+            MCMF_TRY(host_lengths(g, &len));
+            std::vector<int32_t> hrows;
+            const int32_t *rows = q.rows;
+            if (classify(q.rows) == Mem::Device) {
+                hrows.resize(static_cast<size_t>(count));
+                if (count)
+                    MCMF_HIP(hipMemcpy(hrows.data(), q.rows, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
+                rows = hrows.data();
             }
-            const uint64_t per = q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 8 : 12;
-            v = starts * static_cast<uint64_t>(q.n_walks) * (kb - 1) * per;
+            uint64_t sum = 0;
+            for (uint64_t p = 0; p < count; ++p) {
+                const int32_t r = rows[p];
+                if (r < 0 || static_cast<uint64_t>(r) >= n)
+                    return fail(MCMF_E_ARG, "rows[%llu] = %d outside [0, %llu)",
+                                static_cast<unsigned long long>(p), r, static_cast<unsigned long long>(n));
+                sum += (*len)[static_cast<size_t>(r)];
+            }
+            starts = std::min(starts, sum);
         }
     }
+    if (q.path_digest)
+        f += 8 * n;
+    const uint64_t per = q.precision == MCMF_PRECISION_FP32_WEIGHTS ? 8 : 12;
+    const uint64_t st = q.K >= 2 ? starts * static_cast<uint64_t>(q.n_walks) * (kb - 1) : 0;
     *fixed = f;
-    *visits = v;
+    *visits = q.kind == MCMF_REQ_DIAG ? st * per : 0;
+    *steps = st;
+    return {};
 }
 
 } // namespace
@@ -88,6 +125,7 @@ struct mcmf_server {
     std::unordered_map<uint64_t, std::shared_ptr<mcmf::Ticket>> tickets;
     uint64_t next_id = 1;
     bool stopping = false;
+    bool dispatch_done = false; // the dispatcher has handed out the last batch
     uint64_t in_flight = 0;
     mcmf_server_stats stats = {};
     uint64_t batches_in_flight = 0;
@@ -108,6 +146,13 @@ namespace mcmf {
 
 namespace {
 
+uint64_t batch_steps(const std::vector<std::shared_ptr<Ticket>> &b) {
+    uint64_t steps = 0;
+    for (const auto &t : b)
+        steps += t->steps;
+    return steps;
+}
+
 uint64_t batch_estimate(const std::vector<std::shared_ptr<Ticket>> &b, uint64_t chunk) {
     uint64_t fixed = 0, visits = 0;
     for (const auto &t : b) {
@@ -123,7 +168,9 @@ void run_slot(mcmf_server *S, mcmf_server::Slot *slot) {
         std::vector<std::shared_ptr<Ticket>> batch;
         {
             std::unique_lock<std::mutex> lock(S->mu);
-            S->cv_slot.wait(lock, [&] { return !slot->batch.empty() || (S->stopping && !slot->busy); });
+            // Exit only once the dispatcher is done: until then a stopping
+            // server still hands queued requests to idle slots.
+            S->cv_slot.wait(lock, [&] { return !slot->batch.empty() || S->dispatch_done; });
             if (slot->batch.empty())
                 return;
             batch = slot->batch;
@@ -198,7 +245,10 @@ void run_dispatcher(mcmf_server *S) {
             const uint64_t e = batch_estimate(batch, chunk);
             const bool fits = budget == 0 || S->in_flight + e <= budget;
             const bool alone = batch.size() == 1 && S->in_flight == 0;
-            if (!fits && !alone) {
+            // A batch completes as a unit: later requests join only while the
+            // batch stays small, so small requests do not wait for a large one.
+            const bool small = batch.size() == 1 || batch_steps(batch) <= S->opts.max_batch_steps;
+            if ((!fits && !alone) || !small) {
                 batch.pop_back();
                 break;
             }
@@ -223,6 +273,8 @@ void run_dispatcher(mcmf_server *S) {
         S->cv_slot.notify_all();
     }
     // Wake the workers so that they see the stop.
+    S->dispatch_done = true;
+    lock.unlock();
     S->cv_slot.notify_all();
 }
 
@@ -259,6 +311,8 @@ Status create_server(const mcmf_server_opts *o, mcmf_server **out) {
         op.max_batch = 64;
     if (op.visit_chunk_bytes == 0)
         op.visit_chunk_bytes = uint64_t(256) << 20;
+    if (op.max_batch_steps == 0)
+        op.max_batch_steps = uint64_t(1) << 28;
     if (op.n_streams < 1 || op.n_streams > 16)
         return fail(MCMF_E_ARG, "n_streams = %d outside 1..16", op.n_streams);
     if (op.max_batch < 1)
@@ -305,7 +359,11 @@ Status submit(mcmf_server *S, mcmf_request *req, uint64_t *ticket) {
                     copy.graph->device, S->opts.device);
     auto t = std::make_shared<Ticket>();
     t->req = req;
-    estimate(copy, &t->fixed_bytes, &t->visit_bytes);
+    st = estimate(copy, &t->fixed_bytes, &t->visit_bytes, &t->steps);
+    if (st) {
+        req->status = st.code;
+        return st;
+    }
     t->submitted = Clock::now();
     {
         std::lock_guard<std::mutex> lock(S->mu);
@@ -342,6 +400,7 @@ Status wait_ticket(mcmf_server *S, uint64_t id, mcmf_ticket_info *info) {
         info->queue_ms = ms_between(t->submitted, t->started);
         info->run_ms = ms_between(t->started, t->finished);
         info->est_bytes = t->fixed_bytes + std::min(t->visit_bytes, S->opts.visit_chunk_bytes);
+        info->est_steps = t->steps;
     }
     if (code != MCMF_OK)
         return fail(code, "request failed: %s", mcmf_status_string(code));

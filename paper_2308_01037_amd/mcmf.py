@@ -100,13 +100,13 @@ class mcmf_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("visit_chunk_bytes", ctypes.c_uint64),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("reserved", ctypes.c_uint32 * 8)]
+                ("max_batch_steps", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 6)]
 
 
 class mcmf_ticket_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("batch_size", ctypes.c_int32),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
-                ("est_bytes", ctypes.c_uint64)]
+                ("est_bytes", ctypes.c_uint64), ("est_steps", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}

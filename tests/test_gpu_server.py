@@ -162,3 +162,25 @@ def test_invalid_request_is_refused_and_destroy_drains(graphs):
             got = Req.fetch(out, dig, ok.count)
             got["steps"] = r.walk_steps
             check_same(ok, got, want, "drained request")
+
+
+def test_batches_stay_small_and_step_bounds_hold(graphs):
+    # With a walk-step bound of one step per batch every request runs alone;
+    # each request's step bound holds for the steps it actually recorded.
+    reqs = mixed_requests(graphs)[:7]
+    want = [q.single() for q in reqs]
+    srv = server(n_streams=2, max_batch=8, max_batch_steps=1)
+    try:
+        made = [q.make() for q in reqs]
+        tickets = [M.mcmf_server_submit(srv, m[0]) for m in made]
+        infos = [M.mcmf_server_wait(srv, t) for t in tickets]
+    finally:
+        M.mcmf_server_destroy(srv)
+    torch.cuda.synchronize()
+    for i, (q, (r, out, dig), inf, w) in enumerate(zip(reqs, made, infos, want)):
+        got = Req.fetch(out, dig, q.count)
+        got["steps"] = r.walk_steps
+        check_same(q, got, w, f"request {i}")
+        assert inf.est_steps >= r.walk_steps, (i, inf.est_steps, r.walk_steps)
+        if inf.est_steps > 1:
+            assert inf.batch_size == 1

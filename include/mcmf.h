@@ -300,7 +300,7 @@ mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts
  * a batch (mcmf_batch) whenever one of its n_streams stream slots is free,
  * and hands the batch to that slot's worker; batches on different streams
  * overlap on the device.  A batch completes as a unit, so requests join one
- * only while its bound on walk steps stays within max_batch_steps: a large
+ * only while its estimated walk steps stay within max_batch_steps: a large
  * request runs on its own stream while small ones keep flowing on the
  * others.  Requests that arrive while batches run join the
  * next batch as slots and memory free up.  Results equal those of the
@@ -318,9 +318,9 @@ typedef struct {
     int32_t max_batch;          /* most requests per batch, >= 1; 0: 64 */
     int32_t device;             /* HIP device of the server and its graphs */
     int32_t use_graph;          /* 1: each batch is recorded into a hipGraph and launched */
-    uint64_t max_batch_steps;   /* a batch takes further requests only while the bound on
-                                   its walk steps stays within this; a request above it
-                                   runs alone; 0: 2^28 */
+    uint64_t max_batch_steps;   /* a batch takes further requests only while its estimated
+                                   walk steps stay within this; a request above it runs
+                                   alone; 0: 2^28 */
     uint32_t reserved[6];       /* must be zero */
 } mcmf_server_opts;
 
@@ -330,7 +330,8 @@ typedef struct {
     double queue_ms;            /* submit -> start of its batch (host clock) */
     double run_ms;              /* start -> end of its batch */
     uint64_t est_bytes;         /* its admission estimate */
-    uint64_t est_steps;         /* its bound on walk steps (batch forming) */
+    uint64_t est_steps;         /* its estimate of walk steps (batch forming); for actions
+                                   and full diagonals an upper bound */
 } mcmf_ticket_info;
 
 typedef struct {
@@ -352,10 +353,11 @@ mcmf_status mcmf_server_create(const mcmf_server_opts *opts, mcmf_server **out);
 
 /*
  * mcmf_server_submit -- queue one request.  The request is checked here (an
- * invalid one is refused with its status and never queued).  The request
- * struct and every array it names must stay valid until mcmf_server_wait
- * for its ticket returns; the outputs, status and walk_steps are written by
- * then.  Thread-safe.
+ * invalid one is refused with its status and never queued) and sized from
+ * its sizes alone (no device access: submitting never waits for the device).
+ * The request struct and every array it names must stay valid until
+ * mcmf_server_wait for its ticket returns; the outputs, status and
+ * walk_steps are written by then.  Thread-safe.
  */
 mcmf_status mcmf_server_submit(mcmf_server *s, mcmf_request *req, uint64_t *ticket);
 

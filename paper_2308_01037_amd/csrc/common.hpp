@@ -6,9 +6,7 @@
 
 #include <cstdint>
 #include <cstdio>
-#include <mutex>
 #include <string>
-#include <vector>
 
 #include "mcmf.h"
 
@@ -161,7 +159,4 @@ struct mcmf_graph {
     int64_t bin_offset[3] = {0, 0, 0};
     size_t bytes = 0;
 
-    // Host copy of the row lengths, made on first use (request sizing).
-    std::mutex host_mu;
-    std::vector<uint32_t> host_len;
 };

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -92,41 +93,118 @@ static Status reserve(size_t bytes) {
 
 static void unreserve(size_t bytes) { g_bytes_in_use.fetch_sub(static_cast<int64_t>(bytes)); }
 
-static Status ensure_pool(int device) {
-    // Keep freed stream-ordered memory in the pool so that repeated calls do
-    // not return it to the driver.
-    static std::mutex mu;
-    static bool done[64] = {};
-    std::lock_guard<std::mutex> lock(mu);
-    if (device < 0 || device >= 64 || done[device])
-        return {};
-    hipMemPool_t pool;
-    MCMF_HIP(hipDeviceGetDefaultMemPool(&pool, device));
-    uint64_t threshold = UINT64_MAX;
-    MCMF_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
-    done[device] = true;
-    return {};
+// Block cache for the per-call temporaries.  Freed blocks stay with the
+// library (grouped by size class, at most 1/8 over the request) and are
+// handed out again: to the same stream at once (stream order protects the
+// reuse), to another stream once an event recorded at the free has passed.
+// Device memory is only returned to the driver when the cache grows past
+// its limit or an allocation fails, so a steady stream of calls maps no new
+// memory.
+namespace {
+
+struct CachedBlock {
+    void *p;
+    size_t bytes;
+    int device;
+    hipStream_t stream;
+    hipEvent_t freed;
+};
+
+std::mutex g_cache_mu;
+std::vector<CachedBlock> g_cache;
+std::vector<hipEvent_t> g_spare_events;
+size_t g_cached_bytes = 0;
+
+size_t cache_limit() {
+    static size_t limit = [] {
+        const char *s = getenv("MCMF_CACHE_BYTES");
+        if (s)
+            return static_cast<size_t>(strtoull(s, nullptr, 10));
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            return size_t(8) << 30;
+        }
+        return total_b / 8;
+    }();
+    return limit;
 }
+
+// Size classes: 8 per power of two, at least 4 KiB.
+size_t size_class(size_t bytes) {
+    if (bytes <= 4096)
+        return 4096;
+    const int top = 63 - __builtin_clzll(static_cast<unsigned long long>(bytes - 1));
+    const size_t step = size_t(1) << (top >= 3 ? top - 3 : 0);
+    return (bytes + step - 1) / step * step;
+}
+
+// Frees cached blocks (oldest first) until at most `keep` bytes stay cached.
+// The caller holds g_cache_mu.
+void trim_locked(size_t keep) {
+    while (g_cached_bytes > keep && !g_cache.empty()) {
+        const CachedBlock b = g_cache.front();
+        g_cache.erase(g_cache.begin());
+        g_cached_bytes -= b.bytes;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(b.device);
+        (void)hipEventSynchronize(b.freed);
+        (void)hipFree(b.p);
+        (void)hipSetDevice(cur);
+        g_spare_events.push_back(b.freed);
+    }
+}
+
+} // namespace
 
 Status dev_alloc(void **p, size_t bytes, hipStream_t stream) {
     *p = nullptr;
     if (bytes == 0)
         return {};
-    MCMF_TRY(reserve(bytes));
+    const size_t cls = size_class(bytes);
+    MCMF_TRY(reserve(cls));
     int device = 0;
     hipError_t e = hipGetDevice(&device);
-    if (e == hipSuccess) {
-        Status s = ensure_pool(device);
-        if (s) {
-            unreserve(bytes);
-            return s;
+    if (e != hipSuccess) {
+        unreserve(cls);
+        return hip_fail(e, "hipGetDevice", __FILE__, __LINE__);
+    }
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        for (size_t i = 0; i < g_cache.size(); ++i) {
+            CachedBlock &b = g_cache[i];
+            if (b.device != device || b.bytes != cls)
+                continue;
+            bool ready = b.stream == stream;
+            if (!ready) {
+                const hipError_t q = hipEventQuery(b.freed);
+                ready = q == hipSuccess;
+                if (q != hipSuccess)
+                    (void)hipGetLastError();
+            }
+            if (!ready)
+                continue;
+            *p = b.p;
+            g_cached_bytes -= b.bytes;
+            g_spare_events.push_back(b.freed);
+            g_cache.erase(g_cache.begin() + static_cast<std::ptrdiff_t>(i));
+            return {};
         }
-        e = hipMallocAsync(p, bytes, stream);
+    }
+    e = hipMalloc(p, cls);
+    if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lock(g_cache_mu);
+            trim_locked(0);
+        }
+        e = hipMalloc(p, cls);
     }
     if (e != hipSuccess) {
-        unreserve(bytes);
+        unreserve(cls);
         *p = nullptr;
-        return hip_fail(e, "hipMallocAsync", __FILE__, __LINE__);
+        return hip_fail(e, "hipMalloc", __FILE__, __LINE__);
     }
     return {};
 }
@@ -134,8 +212,32 @@ Status dev_alloc(void **p, size_t bytes, hipStream_t stream) {
 void dev_free(void *p, size_t bytes, hipStream_t stream) {
     if (!p)
         return;
-    (void)hipFreeAsync(p, stream);
-    unreserve(bytes);
+    const size_t cls = size_class(bytes);
+    unreserve(cls);
+    int device = 0;
+    (void)hipGetDevice(&device);
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    hipEvent_t ev = nullptr;
+    if (!g_spare_events.empty()) {
+        ev = g_spare_events.back();
+        g_spare_events.pop_back();
+    } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        ev = nullptr;
+    }
+    if (!ev || hipEventRecord(ev, stream) != hipSuccess) {
+        // No event to order a reuse by: give the block back to the driver.
+        (void)hipGetLastError();
+        if (ev)
+            g_spare_events.push_back(ev);
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(p);
+        return;
+    }
+    g_cache.push_back(CachedBlock{p, cls, device, stream, ev});
+    g_cached_bytes += cls;
+    if (g_cached_bytes > cache_limit())
+        trim_locked(cache_limit());
 }
 
 Status dev_alloc_sync(void **p, size_t bytes) {

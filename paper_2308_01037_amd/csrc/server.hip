@@ -46,31 +46,15 @@ struct Ticket {
     bool done = false;
 };
 
-// Row lengths of a graph on the host (copied once per graph).
-Status host_lengths(mcmf_graph *g, const std::vector<uint32_t> **out) {
-    std::lock_guard<std::mutex> lock(g->host_mu);
-    if (g->host_len.size() != static_cast<size_t>(g->n)) {
-        std::vector<uint2> node(static_cast<size_t>(g->n));
-        if (g->n > 0) {
-            MCMF_HIP(hipSetDevice(g->device));
-            MCMF_HIP(hipMemcpy(node.data(), g->node, sizeof(uint2) * node.size(), hipMemcpyDeviceToHost));
-        }
-        std::vector<uint32_t> len(node.size());
-        for (size_t i = 0; i < node.size(); ++i)
-            len[i] = node[i].y;
-        g->host_len.swap(len);
-    }
-    *out = &g->host_len;
-    return {};
-}
-
-// Host-side sizing of one request: device bytes it holds while its batch
-// runs (without the shared visit-record buffer), an upper bound of its
-// visit-record bytes and of its walk steps.  A diagonal request on a row
-// subset starts walks only from neighbours of its rows, so the sum of their
-// lengths bounds its start rows.
-Status estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64_t *steps) {
-    mcmf_graph *g = const_cast<mcmf_graph *>(q.graph);
+// Host-side sizing of one request, from sizes alone (no device access, so
+// submitting never waits behind the batches in flight):
+//  * device bytes it holds while its batch runs, without the shared
+//    visit-record buffer (an upper bound);
+//  * its visit-record bytes and walk steps (estimates: a diagonal request on
+//    a row subset starts walks from the neighbours of its rows, taken as
+//    count * mean row length, at most every row with entries).
+void estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64_t *steps) {
+    const mcmf_graph *g = q.graph;
     const uint64_t n = static_cast<uint64_t>(g->n);
     const uint64_t kb = q.K >= 2 ? static_cast<uint64_t>(q.K) : 2;
     uint64_t f = 8 * kb + 64 * 1024; // coefficients, descriptors, rounding slack
@@ -80,26 +64,9 @@ Status estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64
     } else {
         const uint64_t count = q.rows ? static_cast<uint64_t>(q.n_rows) : n;
         f += 8 * n + 2 * n + 4 * n + 8 * (n + 1) + 12 * count; // dacc, marks, start list, items, rows/out
-        if (q.rows && starts > 0) {
-            const std::vector<uint32_t> *len = nullptr;
-            MCMF_TRY(host_lengths(g, &len));
-            std::vector<int32_t> hrows;
-            const int32_t *rows = q.rows;
-            if (classify(q.rows) == Mem::Device) {
-                hrows.resize(static_cast<size_t>(count));
-                if (count)
-                    MCMF_HIP(hipMemcpy(hrows.data(), q.rows, sizeof(int32_t) * count, hipMemcpyDeviceToHost));
-                rows = hrows.data();
-            }
-            uint64_t sum = 0;
-            for (uint64_t p = 0; p < count; ++p) {
-                const int32_t r = rows[p];
-                if (r < 0 || static_cast<uint64_t>(r) >= n)
-                    return fail(MCMF_E_ARG, "rows[%llu] = %d outside [0, %llu)",
-                                static_cast<unsigned long long>(p), r, static_cast<unsigned long long>(n));
-                sum += (*len)[static_cast<size_t>(r)];
-            }
-            starts = std::min(starts, sum);
+        if (q.rows && n > 0) {
+            const uint64_t mean_len = (static_cast<uint64_t>(g->nnz) + n - 1) / n;
+            starts = std::min(starts, count * std::max<uint64_t>(mean_len, 1));
         }
     }
     if (q.path_digest)
@@ -109,7 +76,6 @@ Status estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64
     *fixed = f;
     *visits = q.kind == MCMF_REQ_DIAG ? st * per : 0;
     *steps = st;
-    return {};
 }
 
 } // namespace
@@ -359,11 +325,7 @@ Status submit(mcmf_server *S, mcmf_request *req, uint64_t *ticket) {
                     copy.graph->device, S->opts.device);
     auto t = std::make_shared<Ticket>();
     t->req = req;
-    st = estimate(copy, &t->fixed_bytes, &t->visit_bytes, &t->steps);
-    if (st) {
-        req->status = st.code;
-        return st;
-    }
+    estimate(copy, &t->fixed_bytes, &t->visit_bytes, &t->steps);
     t->submitted = Clock::now();
     {
         std::lock_guard<std::mutex> lock(S->mu);

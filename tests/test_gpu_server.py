@@ -165,8 +165,9 @@ def test_invalid_request_is_refused_and_destroy_drains(graphs):
 
 
 def test_batches_stay_small_and_step_bounds_hold(graphs):
-    # With a walk-step bound of one step per batch every request runs alone;
-    # each request's step bound holds for the steps it actually recorded.
+    # With a walk-step limit of one step per batch every request runs alone;
+    # for actions and full diagonals the step estimate is an upper bound of
+    # the steps actually recorded.
     reqs = mixed_requests(graphs)[:7]
     want = [q.single() for q in reqs]
     srv = server(n_streams=2, max_batch=8, max_batch_steps=1)
@@ -181,6 +182,7 @@ def test_batches_stay_small_and_step_bounds_hold(graphs):
         got = Req.fetch(out, dig, q.count)
         got["steps"] = r.walk_steps
         check_same(q, got, w, f"request {i}")
-        assert inf.est_steps >= r.walk_steps, (i, inf.est_steps, r.walk_steps)
+        if q.kind == M.MCMF_REQ_ACTION or q.rows is None:
+            assert inf.est_steps >= r.walk_steps, (i, inf.est_steps, r.walk_steps)
         if inf.est_steps > 1:
             assert inf.batch_size == 1

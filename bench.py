@@ -36,8 +36,8 @@ def parse():
     ap.add_argument("--walks", type=int, default=256)
     ap.add_argument("--K", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=12,
-                    help="output rows per query in the oracle's timed sample")
+    ap.add_argument("--cpu-steps", type=float, default=3e7,
+                    help="walk steps per query in the oracle's timed sample")
     ap.add_argument("--only", choices=["all", "action", "diag"], default="all")
     ap.add_argument("--copy-probe-bytes", type=int, default=0,
                     help="after timing, run one device copy of this many bytes (counter calibration)")
@@ -191,14 +191,26 @@ def load_traffic(kernel):
     return None
 
 
-def cpu_baseline(csr, queries, rows, K, N):
+def cpu_baseline(csr, queries, target_steps, K, N):
     """The oracle, single-threaded, on a bounded sample: each query evaluated at
-    `rows` random non-isolated output rows (its walks start from their
-    neighbourhoods).  Returns walk steps per second."""
+    random non-isolated output rows (its walks start from their
+    neighbourhoods), rows added until one query's walks make about
+    `target_steps` steps.  Returns walk steps per second."""
     import oracle
     rng = np.random.default_rng(123)
-    cand = np.nonzero(csr.deg > 0)[0]
-    sample = np.sort(rng.choice(cand, size=min(rows, cand.size), replace=False)).astype(np.int32)
+    cand = rng.permutation(np.nonzero(csr.deg > 0)[0])
+    starts, picked = set(), []
+    per_start = N * (K - 1)
+    for r in cand:
+        nb = csr.col[csr.row_ptr[r]:csr.row_ptr[r + 1]]
+        grown = len(starts.union(nb.tolist()))
+        if grown * per_start > 1.5 * target_steps:
+            continue  # a hub neighbourhood alone would overshoot
+        starts.update(nb.tolist())
+        picked.append(r)
+        if len(starts) * per_start >= target_steps:
+            break
+    sample = np.sort(np.array(picked, dtype=np.int32))
     total_steps, total_s = 0, 0.0
     for kind, fn, scale in queries:
         t0 = time.perf_counter()
@@ -596,7 +608,7 @@ def main():
         import oracle
         oq = [(what, oracle.FN_EXP if fname == "exp" else oracle.FN_RESOLVENT,
                beta if fname == "exp" else gamma) for what, fname, _, _ in queries]
-        rate, steps_c, secs, nrows = cpu_baseline(csr, oq, args.cpu_rows, K, N)
+        rate, steps_c, secs, nrows = cpu_baseline(csr, oq, args.cpu_steps, K, N)
         cpu = {"value": rate, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
                "sample": f"each of the {len(oq)} queries evaluated at {nrows} random non-isolated "
                          f"rows (walks from their neighbourhoods): {steps_c} walk steps in "

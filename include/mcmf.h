@@ -93,6 +93,9 @@ typedef struct {
 /* Flags for mcmf_graph_create. */
 #define MCMF_SYMMETRIC 1u /* caller states A = A^T; required by mcmf_diag */
 #define MCMF_VALIDATE 2u  /* check the CSR arrays (and, with MCMF_SYMMETRIC, symmetry) */
+#define MCMF_DIGRAPH 4u   /* A is a directed graph: store B = [[0, A], [A^T, 0]] (Section 4,
+                             Eq. digraph_sym), 2n x 2n and symmetric; rows 0..n-1 of B
+                             are A's rows (out-edges), rows n..2n-1 its columns (in-edges) */
 
 /* Precision of the walk weights.  MCMF_PRECISION_FP32_WEIGHTS keeps W, the
  * per-step factor s*sum|a| and each per-step contribution (c_{t+2} W r_l for
@@ -148,8 +151,16 @@ typedef struct {
  *   col_idx  int32[nnz], 0 <= col < n (order within a row is kept: it is the
  *            order the sampler's cumulative sums run in)
  *   values   double[nnz], finite; NULL means every stored entry is 1
- *   flags    MCMF_SYMMETRIC | MCMF_VALIDATE
+ *   flags    MCMF_SYMMETRIC | MCMF_VALIDATE, or MCMF_DIGRAPH (| MCMF_VALIDATE)
  *   out      receives the handle; set only on MCMF_OK
+ *
+ * With MCMF_DIGRAPH the graph is B = [[0, A], [A^T, 0]]: n and nnz of the
+ * handle are 2n and 2 nnz, B is symmetric (mcmf_diag allowed).  Row i < n of
+ * B holds A's row i with columns shifted by n, in A's order; row n + j holds
+ * column j of A: the rows i with a_ij != 0, ascending, with the values a_ij.
+ * B is assembled on the host (A is read back first if it is in device
+ * memory); columns are always range-checked there (MCMF_E_CSR).  Requires
+ * n < 2^30 and 2 nnz < 2^32.
  *
  * Errors: MCMF_E_ARG (null out, n out of range, null arrays with nnz > 0),
  * MCMF_E_CSR (with MCMF_VALIDATE: row_ptr[0] != 0, decreasing row_ptr, a
@@ -160,6 +171,49 @@ typedef struct {
  */
 mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                               const double *values, uint32_t flags, mcmf_graph **out);
+
+/* ------------------------------------------------------------------ */
+/* Tuning                                                              */
+/* ------------------------------------------------------------------ */
+
+/* Sampler layouts of an unweighted walk step (Definition 1 (ii): both pick
+ * entry floor(u deg / 2^64) of the current row; results are identical). */
+#define MCMF_SAMPLER_EDGE 0 /* one 16-byte record per step: the picked entry carries
+                               the next row's record (one dependent load) */
+#define MCMF_SAMPLER_ROW 1  /* the picked column (4 bytes), then the next row's record
+                               (8 bytes): two dependent loads, less data per step */
+
+/* Per-graph choices of the walk kernels.  They change memory traffic only,
+ * never a result.  Defaults: action EDGE with non-temporal loads, diag EDGE
+ * with cached loads. */
+typedef struct {
+    int32_t action_sampler;  /* MCMF_SAMPLER_* of mcmf_action walks */
+    int32_t action_stream;   /* 1: the walk's record loads are non-temporal */
+    int32_t diag_sampler;    /* MCMF_SAMPLER_* of mcmf_diag walks */
+    int32_t diag_stream;     /* 1: non-temporal record loads */
+    double action_ms[4];     /* mcmf_tune only: ms of each action variant, index sampler*2+stream */
+    double diag_ms[4];       /* mcmf_tune only: ms of each diag-walk variant, same index */
+    int64_t sample_rows;     /* mcmf_tune only: start rows in the timed sample */
+    uint32_t reserved[6];    /* must be zero on input */
+} mcmf_tuning;
+
+/* Set / read a graph's tuning.  Not to be called while a request on the
+ * graph runs.  Errors: MCMF_E_ARG (null pointers, values out of range). */
+mcmf_status mcmf_graph_set_tuning(mcmf_graph *g, const mcmf_tuning *t);
+mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t);
+
+/*
+ * mcmf_tune -- the autotuner: times every sampler layout and load policy of
+ * the action and diagonal walk kernels on a sample of the graph's rows (rows
+ * with entries taken at an even stride, about 2^28 walk steps in all, with
+ * the function, n_walks and K of the intended requests), keeps the fastest of
+ * each and stores it in the graph (mcmf_graph_set_tuning).  out receives the
+ * choice and the measured times.  The caller may cache the result by a
+ * fingerprint of the graph and reapply it with mcmf_graph_set_tuning.
+ * Errors: as mcmf_action (K >= 2, n_walks >= 1 required), MCMF_E_NOMEM,
+ * MCMF_E_DEVICE.
+ */
+mcmf_status mcmf_tune(mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K, mcmf_tuning *out);
 
 /* Release the graph's device memory.  NULL is ignored. */
 void mcmf_graph_destroy(mcmf_graph *g);

@@ -158,5 +158,7 @@ struct mcmf_graph {
     int64_t bin_count[3] = {0, 0, 0};
     int64_t bin_offset[3] = {0, 0, 0};
     size_t bytes = 0;
+    // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
+    mcmf_tuning tuning = {MCMF_SAMPLER_EDGE, 1, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, {}};
 
 };

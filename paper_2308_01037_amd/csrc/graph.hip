@@ -409,6 +409,77 @@ Status compact(const uint8_t *flags, int64_t n, uint8_t match, int32_t *out, int
     return {};
 }
 
+// B = [[0, A], [A^T, 0]] of a directed graph A, on the host: rows i < n are
+// A's rows with columns shifted by n; row n + j lists the rows i with
+// a_ij != 0 in ascending order (a counting sort over A's rows taken in order
+// is stable, so no sort is needed).
+Status digraph_symmetrize(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                          std::vector<int64_t> &b_ptr, std::vector<int32_t> &b_col,
+                          std::vector<double> &b_val) {
+    if (n >= (int64_t(1) << 30))
+        return fail(MCMF_E_UNSUPPORTED, "MCMF_DIGRAPH needs n < 2^30 (got %lld)", static_cast<long long>(n));
+    std::vector<int64_t> hptr;
+    std::vector<int32_t> hcol;
+    std::vector<double> hval;
+    const int64_t *rp = row_ptr;
+    if (classify(row_ptr) == Mem::Device) {
+        hptr.resize(static_cast<size_t>(n + 1));
+        MCMF_HIP(hipMemcpy(hptr.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+        rp = hptr.data();
+    }
+    if (rp[0] != 0)
+        return fail(MCMF_E_CSR, "row_ptr[0] = %lld, expected 0", static_cast<long long>(rp[0]));
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i])
+            return fail(MCMF_E_CSR, "row_ptr decreases at row %lld", static_cast<long long>(i));
+    const int64_t nnz = rp[n];
+    if (2 * nnz >= (int64_t(1) << 32))
+        return fail(MCMF_E_UNSUPPORTED, "MCMF_DIGRAPH needs 2 nnz < 2^32 (nnz = %lld)",
+                    static_cast<long long>(nnz));
+    if (nnz > 0 && !col)
+        return fail(MCMF_E_ARG, "col_idx is NULL with nnz = %lld", static_cast<long long>(nnz));
+    const int32_t *cp = col;
+    if (nnz > 0 && classify(col) == Mem::Device) {
+        hcol.resize(static_cast<size_t>(nnz));
+        MCMF_HIP(hipMemcpy(hcol.data(), col, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost));
+        cp = hcol.data();
+    }
+    const double *vp = val;
+    if (val && nnz > 0 && classify(val) == Mem::Device) {
+        hval.resize(static_cast<size_t>(nnz));
+        MCMF_HIP(hipMemcpy(hval.data(), val, sizeof(double) * nnz, hipMemcpyDeviceToHost));
+        vp = hval.data();
+    }
+    for (int64_t e = 0; e < nnz; ++e)
+        if (cp[e] < 0 || cp[e] >= n)
+            return fail(MCMF_E_CSR, "col_idx[%lld] = %d outside [0, %lld)", static_cast<long long>(e), cp[e],
+                        static_cast<long long>(n));
+    b_ptr.assign(static_cast<size_t>(2 * n + 1), 0);
+    b_col.resize(static_cast<size_t>(2 * nnz));
+    if (vp)
+        b_val.resize(static_cast<size_t>(2 * nnz));
+    for (int64_t i = 0; i < n; ++i)
+        b_ptr[i + 1] = rp[i + 1];
+    for (int64_t e = 0; e < nnz; ++e)
+        ++b_ptr[n + cp[e] + 1];
+    for (int64_t j = n; j < 2 * n; ++j)
+        b_ptr[j + 1] += b_ptr[j];
+    for (int64_t e = 0; e < nnz; ++e) {
+        b_col[e] = static_cast<int32_t>(cp[e] + n);
+        if (vp)
+            b_val[e] = vp[e];
+    }
+    std::vector<int64_t> cursor(b_ptr.begin() + n, b_ptr.begin() + 2 * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+            const int64_t pos = cursor[cp[e]]++;
+            b_col[pos] = static_cast<int32_t>(i);
+            if (vp)
+                b_val[pos] = vp[e];
+        }
+    return {};
+}
+
 } // namespace mcmf
 
 using namespace mcmf;
@@ -428,9 +499,27 @@ extern "C" mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, cons
         fail(MCMF_E_ARG, "row_ptr is NULL");
         return MCMF_E_ARG;
     }
-    if (flags & ~(MCMF_SYMMETRIC | MCMF_VALIDATE)) {
-        fail(MCMF_E_ARG, "unknown flag bits 0x%x", flags & ~(MCMF_SYMMETRIC | MCMF_VALIDATE));
+    const uint32_t known = MCMF_SYMMETRIC | MCMF_VALIDATE | MCMF_DIGRAPH;
+    if (flags & ~known) {
+        fail(MCMF_E_ARG, "unknown flag bits 0x%x", flags & ~known);
         return MCMF_E_ARG;
+    }
+    if ((flags & MCMF_DIGRAPH) && (flags & MCMF_SYMMETRIC)) {
+        fail(MCMF_E_ARG, "MCMF_DIGRAPH and MCMF_SYMMETRIC exclude each other (B is symmetric by construction)");
+        return MCMF_E_ARG;
+    }
+    std::vector<int64_t> b_ptr;
+    std::vector<int32_t> b_col;
+    std::vector<double> b_val;
+    if (flags & MCMF_DIGRAPH) {
+        Status st = digraph_symmetrize(n, row_ptr, col_idx, values, b_ptr, b_col, b_val);
+        if (st)
+            return st.code;
+        n = 2 * n;
+        row_ptr = b_ptr.data();
+        col_idx = b_col.data();
+        values = values ? b_val.data() : nullptr;
+        flags = (flags & MCMF_VALIDATE) | MCMF_SYMMETRIC;
     }
     mcmf_graph *g = new (std::nothrow) mcmf_graph();
     if (!g) {

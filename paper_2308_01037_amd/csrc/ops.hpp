@@ -26,6 +26,9 @@ struct WalkParams {
     uint32_t request;
     double cutoff; // 0 = off
     int precision; // MCMF_PRECISION_*
+    // Sampler layout and load policy: -1 = the graph's tuning.
+    int sampler = -1;
+    int stream = -1;
 };
 
 // r = s A v.

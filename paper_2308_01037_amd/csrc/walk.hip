@@ -12,7 +12,7 @@ using walk::GraphView;
 using walk::WalkArgs;
 
 // Action: q[k] = (1/N) sum_w sum_t c_{t+2} W_t r_{l_t}.
-template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF, bool EDGE, bool STREAM>
 __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *__restrict__ r,
                                                      const int32_t *__restrict__ starts,
                                                      int64_t n_start, WalkArgs a,
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
         unsigned long long nsteps = 0;
         for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
             uint64_t h = dev::kFnvBasis;
-            acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF>(
+            acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF, EDGE, STREAM>(
                 g, r, a, k, rk, r_k, static_cast<uint32_t>(w64), &h, &nsteps);
             if (DIGEST)
                 dig += h;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
 
 // Diagonal: visit records of start row kk, t-major: slot (kk*(K-1) + t)*N + w
 // holds (l_t, c_{t+2} W_t); after a walk ends early its slots hold state -1.
-template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF, bool EDGE, bool STREAM>
 __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *__restrict__ starts,
                                                    int64_t n_start, WalkArgs a,
                                                    int32_t *__restrict__ vstate,
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
         unsigned long long nsteps = 0;
         for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
             uint64_t h = dev::kFnvBasis;
-            walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF>(g, a, k, rk, static_cast<uint32_t>(w64),
+            walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF, EDGE, STREAM>(g, a, k, rk, static_cast<uint32_t>(w64),
                                                            vstate + row_base + w64,
                                                            vx + row_base + w64, a.N, &h, &nsteps);
             if (DIGEST)
@@ -108,11 +108,14 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
-    walk::dispatch4(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
-                    p.cutoff > 0.0, [&](auto wt, auto w, auto d, auto c) {
+    const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.action_sampler) == MCMF_SAMPLER_EDGE;
+    const bool stream = (p.stream >= 0 ? p.stream : g->tuning.action_stream) != 0;
+    walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
+                    p.cutoff > 0.0, edge, stream, [&](auto wt, auto w, auto d, auto c, auto e, auto st) {
                         using WT = decltype(wt);
                         hipLaunchKernelGGL((k_action_walk<WT, decltype(w)::value, decltype(d)::value,
-                                                          decltype(c)::value>),
+                                                          decltype(c)::value, decltype(e)::value,
+                                                          decltype(st)::value>),
                                            grid, block, 0, s, gv, r, starts, n_start, a, q, digest,
                                            steps);
                     });
@@ -128,11 +131,14 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
     const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
-    walk::dispatch4(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
-                    p.cutoff > 0.0, [&](auto wt, auto w, auto d, auto c) {
+    const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_EDGE;
+    const bool stream = (p.stream >= 0 ? p.stream : g->tuning.diag_stream) != 0;
+    walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
+                    p.cutoff > 0.0, edge, stream, [&](auto wt, auto w, auto d, auto c, auto e, auto st) {
                         using WT = decltype(wt);
                         hipLaunchKernelGGL((k_diag_walk<WT, decltype(w)::value, decltype(d)::value,
-                                                        decltype(c)::value>),
+                                                        decltype(c)::value, decltype(e)::value,
+                                                        decltype(st)::value>),
                                            grid, block, 0, s, gv, starts, n_start, a, state,
                                            static_cast<WT *>(x), digest, steps);
                     });

@@ -86,10 +86,10 @@ struct Pos {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// Edge record load; STREAM marks it non-temporal.  The entry a step picks is
+// Record loads; STREAM marks them non-temporal.  The entry a step picks is
 // uniform over all stored entries (the walk's edge distribution), so records
-// are rarely reused from cache; keeping them out of the cache leaves it to
-// the vector the action walks read at every step.
+// are rarely reused from cache; keeping them out of the cache can leave it to
+// the vector the action walks read at every step (the autotuner decides).
 template <bool STREAM>
 __device__ __forceinline__ uint4 load_edge(const uint4 *e) {
     if constexpr (STREAM) {
@@ -100,19 +100,38 @@ __device__ __forceinline__ uint4 load_edge(const uint4 *e) {
     }
 }
 
+template <bool STREAM>
+__device__ __forceinline__ int32_t load_col(const int32_t *c) {
+    if constexpr (STREAM)
+        return __builtin_nontemporal_load(c);
+    else
+        return *c;
+}
+
 // One transition out of row p (deg > 0) with the block of random words x.
 // Updates W (times s * sum |a|, sign of the entry) and returns the new row.
-template <bool WEIGHTED, class WT, bool STREAM = false>
+// Unweighted rows either read one edge record (EDGE: the entry carries the
+// next row's record) or the column and then the next row's record (two
+// dependent loads, but 4 + 8 bytes instead of 16 and a row-record array
+// that caches well); both pick the same entry.
+template <bool WEIGHTED, class WT, bool STREAM = false, bool EDGE = true>
 __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
                                     WT &W) {
     Pos n;
     if constexpr (!WEIGHTED) {
         const uint32_t j = dev::uniform_index(x.x, x.y, p.deg);
         W = W * static_cast<WT>(scale * static_cast<double>(p.deg));
-        const uint4 e = load_edge<STREAM>(g.edge + (int64_t(p.start) + j));
-        n.l = e.x;
-        n.start = e.y;
-        n.deg = e.z;
+        if constexpr (EDGE) {
+            const uint4 e = load_edge<STREAM>(g.edge + (int64_t(p.start) + j));
+            n.l = e.x;
+            n.start = e.y;
+            n.deg = e.z;
+        } else {
+            n.l = static_cast<uint32_t>(load_col<STREAM>(g.col + (int64_t(p.start) + j)));
+            const uint2 r = g.node[n.l];
+            n.start = r.x;
+            n.deg = r.y;
+        }
     } else {
         const double ra = g.rowabs[p.l];
         const uint32_t j = cdf_search(g.cum + p.start, p.deg, dev::unit53(x.x, x.y) * ra);
@@ -131,7 +150,7 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
 // One action walk (walk index w from start row k): returns
 // sum_t c_{t+2} W_t r_{l_t}; adds the recorded states to *nsteps and folds
 // the path into *h.
-template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF, bool EDGE = true, bool STREAM = true>
 __device__ __forceinline__ double action_walk(const GraphView &g, const double *__restrict__ r,
                                               const WalkArgs &a, uint32_t k, uint2 rk, double r_k,
                                               uint32_t w, uint64_t *h, unsigned long long *nsteps) {
@@ -149,7 +168,7 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
         if (more) {
             const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
                                                a.key0, a.key1);
-            nxt = step<WEIGHTED, WT, true>(g, p, x, a.scale, Wn);
+            nxt = step<WEIGHTED, WT, STREAM, EDGE>(g, p, x, a.scale, Wn);
         }
         wacc += static_cast<double>(static_cast<WT>(a.coef[t]) * W * static_cast<WT>(rl));
         if (DIGEST)
@@ -166,7 +185,7 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
 
 // One diagonal walk: writes (l_t, c_{t+2} W_t) to vstate[t*stride],
 // vx[t*stride] for t = 0..K-2 (state -1 once the walk has ended).
-template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF>
+template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF, bool EDGE = true, bool STREAM = false>
 __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a, uint32_t k,
                                           uint2 rk, uint32_t w, int32_t *__restrict__ vstate,
                                           WT *__restrict__ vx, int64_t stride, uint64_t *h,
@@ -184,7 +203,7 @@ __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a,
         if (more) {
             const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
                                                a.key0, a.key1);
-            nxt = step<WEIGHTED, WT>(g, p, x, a.scale, Wn);
+            nxt = step<WEIGHTED, WT, STREAM, EDGE>(g, p, x, a.scale, Wn);
         }
         vstate[int64_t(t) * stride] = static_cast<int32_t>(p.l);
         vx[int64_t(t) * stride] = static_cast<WT>(a.coef[t]) * W;
@@ -202,7 +221,46 @@ __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a,
         vstate[int64_t(t) * stride] = -1;
 }
 
-// Runtime flags to template arguments.
+// Runtime flags to template arguments, sampler layout included (weighted
+// rows have one layout: the sampler flags are ignored for them).
+template <class F>
+void dispatch6(bool fp32, bool weighted, bool digest, bool cutoff, bool edge, bool stream, F &&f) {
+    auto with_s = [&](auto wt, auto w, auto d, auto c, auto e) {
+        if (stream && !decltype(w)::value)
+            f(wt, w, d, c, e, std::true_type{});
+        else
+            f(wt, w, d, c, e, std::false_type{});
+    };
+    auto with_e = [&](auto wt, auto w, auto d, auto c) {
+        if (edge || decltype(w)::value)
+            with_s(wt, w, d, c, std::true_type{});
+        else
+            with_s(wt, w, d, c, std::false_type{});
+    };
+    auto with_c = [&](auto wt, auto w, auto d) {
+        if (cutoff)
+            with_e(wt, w, d, std::true_type{});
+        else
+            with_e(wt, w, d, std::false_type{});
+    };
+    auto with_d = [&](auto wt, auto w) {
+        if (digest)
+            with_c(wt, w, std::true_type{});
+        else
+            with_c(wt, w, std::false_type{});
+    };
+    auto with_w = [&](auto wt) {
+        if (weighted)
+            with_d(wt, std::true_type{});
+        else
+            with_d(wt, std::false_type{});
+    };
+    if (fp32)
+        with_w(float{});
+    else
+        with_w(double{});
+}
+
 template <class F>
 void dispatch4(bool fp32, bool weighted, bool digest, bool cutoff, F &&f) {
     auto with_c = [&](auto wt, auto w, auto d) {

@@ -48,9 +48,13 @@ MCMF_FN_COEFFS = 2
 
 MCMF_SYMMETRIC = 1
 MCMF_VALIDATE = 2
+MCMF_DIGRAPH = 4
 
 MCMF_PRECISION_FP64 = 0
 MCMF_PRECISION_FP32_WEIGHTS = 1
+
+MCMF_SAMPLER_EDGE = 0
+MCMF_SAMPLER_ROW = 1
 
 
 class mcmf_fn(ctypes.Structure):
@@ -74,6 +78,19 @@ class mcmf_stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class mcmf_tuning(ctypes.Structure):
+    _fields_ = [("action_sampler", ctypes.c_int32), ("action_stream", ctypes.c_int32),
+                ("diag_sampler", ctypes.c_int32), ("diag_stream", ctypes.c_int32),
+                ("action_ms", ctypes.c_double * 4), ("diag_ms", ctypes.c_double * 4),
+                ("sample_rows", ctypes.c_int64), ("reserved", ctypes.c_uint32 * 6)]
+
+    def as_dict(self) -> dict:
+        return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
+                "diag_sampler": self.diag_sampler, "diag_stream": self.diag_stream,
+                "action_ms": list(self.action_ms), "diag_ms": list(self.diag_ms),
+                "sample_rows": self.sample_rows}
 
 
 MCMF_REQ_DIAG = 0
@@ -149,6 +166,13 @@ _lib.mcmf_server_query.argtypes = [_P, ctypes.POINTER(mcmf_server_stats)]
 _lib.mcmf_server_query.restype = ctypes.c_int
 _lib.mcmf_server_destroy.argtypes = [_P]
 _lib.mcmf_server_destroy.restype = None
+_lib.mcmf_graph_set_tuning.argtypes = [_P, ctypes.POINTER(mcmf_tuning)]
+_lib.mcmf_graph_set_tuning.restype = ctypes.c_int
+_lib.mcmf_graph_get_tuning.argtypes = [_P, ctypes.POINTER(mcmf_tuning)]
+_lib.mcmf_graph_get_tuning.restype = ctypes.c_int
+_lib.mcmf_tune.argtypes = [_P, ctypes.POINTER(mcmf_fn), ctypes.c_int64, ctypes.c_int32,
+                           ctypes.POINTER(mcmf_tuning)]
+_lib.mcmf_tune.restype = ctypes.c_int
 _lib.mcmf_status_string.argtypes = [ctypes.c_int]
 _lib.mcmf_status_string.restype = ctypes.c_char_p
 _lib.mcmf_last_error.argtypes = []
@@ -157,6 +181,7 @@ _lib.mcmf_last_error.restype = ctypes.c_char_p
 EXPORTED = ["mcmf_graph_create", "mcmf_graph_destroy", "mcmf_graph_info", "mcmf_diag",
             "mcmf_action", "mcmf_batch", "mcmf_server_create", "mcmf_server_submit",
             "mcmf_server_wait", "mcmf_server_query", "mcmf_server_destroy",
+            "mcmf_graph_set_tuning", "mcmf_graph_get_tuning", "mcmf_tune",
             "mcmf_status_string", "mcmf_last_error"]
 
 
@@ -333,6 +358,22 @@ def mcmf_batch(reqs, opts: Optional[mcmf_batch_opts] = None,
         r.status = arr[i].status
         r.walk_steps = arr[i].walk_steps
     _raise(st)
+
+
+def mcmf_graph_set_tuning(g: int, t: mcmf_tuning) -> None:
+    _raise(_lib.mcmf_graph_set_tuning(g, ctypes.byref(t)))
+
+
+def mcmf_graph_get_tuning(g: int) -> mcmf_tuning:
+    t = mcmf_tuning()
+    _raise(_lib.mcmf_graph_get_tuning(g, ctypes.byref(t)))
+    return t
+
+
+def mcmf_tune(g: int, f: mcmf_fn, n_walks: int, K: int) -> mcmf_tuning:
+    t = mcmf_tuning()
+    _raise(_lib.mcmf_tune(g, ctypes.byref(f), n_walks, K, ctypes.byref(t)))
+    return t
 
 
 def mcmf_server_create(opts: Optional[mcmf_server_opts] = None) -> int:

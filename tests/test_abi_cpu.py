@@ -91,7 +91,7 @@ def test_struct_layouts_match_header(tmp_path):
     structs = {"mcmf_fn": M.mcmf_fn, "mcmf_opts": M.mcmf_opts, "mcmf_stats": M.mcmf_stats,
                "mcmf_request": M.mcmf_request, "mcmf_batch_opts": M.mcmf_batch_opts,
                "mcmf_server_opts": M.mcmf_server_opts, "mcmf_ticket_info": M.mcmf_ticket_info,
-               "mcmf_server_stats": M.mcmf_server_stats}
+               "mcmf_server_stats": M.mcmf_server_stats, "mcmf_tuning": M.mcmf_tuning}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "mcmf.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
@@ -158,3 +158,23 @@ def test_server_argument_errors_need_no_device():
     assert lib.mcmf_server_wait(None, 1, None) == M.MCMF_E_ARG
     assert lib.mcmf_server_query(None, None) == M.MCMF_E_ARG
     lib.mcmf_server_destroy(None)
+
+
+def test_digraph_flag_errors_need_no_device():
+    import ctypes
+    from paper_2308_01037_amd import mcmf as M
+    lib = M._lib
+    out = ctypes.c_void_p()
+    rp = np.array([0, 1, 2], dtype=np.int64)
+    col = np.array([1, 0], dtype=np.int32)
+    assert lib.mcmf_graph_create(2, rp.ctypes.data, col.ctypes.data, None,
+                                 M.MCMF_DIGRAPH | M.MCMF_SYMMETRIC, ctypes.byref(out)) == M.MCMF_E_ARG
+    assert lib.mcmf_graph_create(2, rp.ctypes.data, col.ctypes.data, None, 8,
+                                 ctypes.byref(out)) == M.MCMF_E_ARG
+    bad = np.array([1, 2], dtype=np.int32)
+    assert lib.mcmf_graph_create(2, rp.ctypes.data, bad.ctypes.data, None, M.MCMF_DIGRAPH,
+                                 ctypes.byref(out)) == M.MCMF_E_CSR
+    assert "outside" in M.mcmf_last_error()
+    down = np.array([0, 2, 1], dtype=np.int64)
+    assert lib.mcmf_graph_create(2, down.ctypes.data, col.ctypes.data, None, M.MCMF_DIGRAPH,
+                                 ctypes.byref(out)) == M.MCMF_E_CSR

@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--qps", type=float, default=0.0,
                     help="serve: arrival rate (0: the sequential path's measured capacity)")
     ap.add_argument("--seed", type=int, default=7, help="batch/serve: workload seed")
+    ap.add_argument("--tune", metavar="CACHE",
+                    help="hotpath: autotune the walk kernels first (mcmf_tune, outside the timed "
+                         "region), caching the choice in the JSON file CACHE")
     return ap.parse_args()
 
 
@@ -530,6 +533,11 @@ def main():
 
     g = M.Graph.from_csr(csr)
     n = csr.n
+    tuned = None
+    if args.tune:
+        from paper_2308_01037_amd import tuning
+        tuned = tuning.autotune(g, csr, M.make_fn(M.MCMF_FN_EXP, beta), N, K, args.tune)
+        log(f"tuning: {tuned}")
     stream = torch.cuda.current_stream().cuda_stream
     v = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -651,6 +659,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if tuned is not None:
+        result["tuning"] = tuned
     g.close()
     print(json.dumps(result), flush=True)
 

@@ -83,11 +83,13 @@ def _open(path: str):
     lib.oracle_coeffs.argtypes = [cint, cint, P]
     lib.oracle_coeffs.restype = cint
     lib.oracle_action.argtypes = [i64, P, P, P, P, cint, f64, i64, u64, u32, f64, P, P, i64,
-                                  cint, P, P, P, P]
+                                  cint, P, P, P, P, P]
     lib.oracle_action.restype = cint
     lib.oracle_diag.argtypes = [i64, P, P, P, P, cint, f64, i64, u64, u32, f64, P, i64, cint,
-                                cint, P, P, P]
+                                cint, P, P, P, P]
     lib.oracle_diag.restype = cint
+    lib.oracle_allocation.argtypes = [i64, P, P, P, cint, P, i64, i64, P]
+    lib.oracle_allocation.restype = cint
     return lib
 
 
@@ -159,14 +161,35 @@ def _coeff_array(fn, K: int) -> np.ndarray:
 
 # ---------------------------------------------------------------- estimators
 
+def _walks_array(walks, n):
+    if walks is None:
+        return None
+    w = np.ascontiguousarray(walks, dtype=np.int64)
+    if w.size != n:
+        raise OracleError("walks must have length n")
+    return w
+
+
+def allocation(g, Ns: int, starts, symmetric: bool = True):
+    """Walks per start row with p_k proportional to ||C_k||_2 (Eq.
+    initial_prob): N_k = max(1, round(Ns p_k)); int64[n], 0 off the starts."""
+    row_ptr, col, val = _csr_arrays(g)
+    st = np.ascontiguousarray(starts, dtype=np.int32)
+    out = np.zeros(max(g.n, 1), dtype=np.int64)
+    _check(_load().oracle_allocation(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), 1 if symmetric else 0,
+                                     _ptr(st), st.size, int(Ns), _ptr(out)))
+    return out[:g.n]
+
+
 def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int = 0,
            cutoff: float = 0.0, rows=None, expect: bool = False, want_q: bool = False,
-           want_digest: bool = False):
+           want_digest: bool = False, walks=None):
     """RandFunmAction.  Returns dict(y, q, digest, steps).
 
     ``fn``: FN_EXP, FN_RESOLVENT or an explicit coefficient array c_0..c_K.
     ``rows``: output rows (default all); walks start only where needed.
     ``expect``: exact expectation of the estimator instead of sampling.
+    ``walks``: walks per start row (int64[n]) instead of N for every row.
     """
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
@@ -183,15 +206,16 @@ def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request:
                                  float(scale), int(N), int(seed), int(request), float(cutoff),
                                  _ptr(v), _ptr(out_rows), 0 if out_rows is None else out_rows.size,
                                  1 if expect else 0, _ptr(y), _ptr(q), _ptr(dig),
-                                 ctypes.addressof(steps)))
+                                 ctypes.addressof(steps), _ptr(_walks_array(walks, g.n))))
     return {"y": y[:n_out], "q": None if q is None else q[:g.n],
             "digest": None if dig is None else dig[:g.n], "steps": steps.value}
 
 
 def diag(g, fn, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int = 0,
          cutoff: float = 0.0, rows=None, expect: bool = False, assume_symmetric: bool = False,
-         want_digest: bool = False):
-    """RandFunmDiag.  Returns dict(d, digest, steps)."""
+         want_digest: bool = False, walks=None):
+    """RandFunmDiag.  Returns dict(d, digest, steps).  ``walks``: walks per
+    start row (int64[n]) instead of N for every row."""
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
     r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
@@ -202,7 +226,8 @@ def diag(g, fn, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int 
     _check(_load().oracle_diag(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(c), K,
                                float(scale), int(N), int(seed), int(request), float(cutoff),
                                _ptr(r), 0 if r is None else r.size, 1 if assume_symmetric else 0,
-                               1 if expect else 0, _ptr(d), _ptr(dig), ctypes.addressof(steps)))
+                               1 if expect else 0, _ptr(d), _ptr(dig), ctypes.addressof(steps),
+                               _ptr(_walks_array(walks, g.n))))
     return {"d": d[:count], "digest": None if dig is None else dig[:g.n], "steps": steps.value}
 
 

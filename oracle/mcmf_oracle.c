@@ -331,7 +331,8 @@ static int check_params(const oparams *p)
 int oracle_action(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                   const double *c, int K, double s, int64_t N, uint64_t seed, uint32_t request,
                   double cutoff, const double *v, const int32_t *out_rows, int64_t n_out,
-                  int mode, double *y, double *q_out, uint64_t *digest, uint64_t *steps)
+                  int mode, double *y, double *q_out, uint64_t *digest, uint64_t *steps,
+                  const int64_t *walks)
 {
     ograph g;
     oparams p;
@@ -401,9 +402,15 @@ int oracle_action(int64_t n, const int64_t *row_ptr, const int32_t *col, const d
         if (!start[k])
             continue;
         if (mode == 0) {
+            /* N walks from every start row, or walks[k] (Eq. initial_prob). */
+            const int64_t Nk = walks ? walks[k] : N;
             double sum = 0.0;
             uint32_t w;
-            for (w = 0; w < (uint32_t)N; ++w) {
+            if (Nk < 1) {
+                rc = ORC_E_ARG;
+                goto done;
+            }
+            for (w = 0; w < (uint32_t)Nk; ++w) {
                 int cnt = walk(&g, &p, k, w, st, wt, &dg), t;
                 double a = 0.0;
                 for (t = 0; t < cnt; ++t)
@@ -411,7 +418,7 @@ int oracle_action(int64_t n, const int64_t *row_ptr, const int32_t *col, const d
                 sum = sum + a;
                 nsteps += (uint64_t)cnt;
             }
-            q[k] = sum / (double)N;
+            q[k] = sum / (double)Nk;
         } else {
             double sum = 0.0;
             memset(acc, 0, sizeof(double) * (size_t)n);
@@ -503,7 +510,7 @@ int oracle_is_symmetric(int64_t n, const int64_t *row_ptr, const int32_t *col, c
 int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                 const double *c, int K, double s, int64_t N, uint64_t seed, uint32_t request,
                 double cutoff, const int32_t *rows, int64_t n_rows, int assume_symmetric,
-                int mode, double *d, uint64_t *digest, uint64_t *steps)
+                int mode, double *d, uint64_t *digest, uint64_t *steps, const int64_t *walks)
 {
     ograph g;
     oparams p;
@@ -512,7 +519,7 @@ int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
     int64_t *touched = NULL;
     unsigned char *inS = NULL, *start = NULL;
     uint64_t nsteps = 0;
-    int64_t i, e, k, pidx, count;
+    int64_t i, e, k, pidx, count, Nk = N;
     int rc = check_csr(n, row_ptr, col);
     if (rc)
         return rc;
@@ -547,7 +554,12 @@ int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
         goto done;
     if (mode == 0 && K >= 2) {
         /* every state a start row's walks can visit, to clear Q_k afterwards */
-        touched = (int64_t *)malloc(sizeof(int64_t) * (size_t)N * (size_t)(K - 1));
+        int64_t most = N;
+        if (walks)
+            for (k = 0; k < n; ++k)
+                if (walks[k] > most)
+                    most = walks[k];
+        touched = (int64_t *)malloc(sizeof(int64_t) * (size_t)most * (size_t)(K - 1));
         if (!touched)
             goto done;
     }
@@ -574,7 +586,12 @@ int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
             continue;
         if (mode == 0) {
             uint32_t w;
-            for (w = 0; w < (uint32_t)N; ++w) {
+            Nk = walks ? walks[k] : N;
+            if (Nk < 1) {
+                rc = ORC_E_ARG;
+                goto done;
+            }
+            for (w = 0; w < (uint32_t)Nk; ++w) {
                 int cnt = walk(&g, &p, k, w, st, wt, &dg), t;
                 for (t = 0; t < cnt; ++t) {
                     Q[st[t]] = Q[st[t]] + c[t + 2] * wt[t];
@@ -598,7 +615,7 @@ int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
                 inner = inner + entry(&g, e2) * Q[col[e2]];
             inner = s * inner;
             if (mode == 0)
-                inner = inner / (double)N;
+                inner = inner / (double)Nk;
             dsum[ii] = dsum[ii] + (s * entry(&g, e)) * inner;
         }
         /* Drop Q_k. */
@@ -631,6 +648,62 @@ done:
     free(Q); free(dsum); free(inS); free(start); free(touched); free(st); free(wt);
     free(rho); free(nxt);
     return rc;
+}
+
+/*
+ * Walk allocation of Definition 1 (i) (Eq. initial_prob) with N_i = N_s p_i
+ * as in Algorithms 2-3: p_k = ||C_k||_2 / sum over the start rows of ||C||_2,
+ * and N_k = max(1, round(N_s p_k)) for every start row (one walk at least, so
+ * each start row's term stays defined).  The column norms are summed in
+ * column order: for symmetric A, C_k = R_k is summed along row k; otherwise
+ * (unweighted only) ||C_k||^2 is the number of entries in column k.  The
+ * total runs over starts[] in the order given.  walks_out[k] (length n) is
+ * set for the start rows and 0 elsewhere.
+ */
+int oracle_allocation(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                      int symmetric, const int32_t *starts, int64_t n_start, int64_t Ns,
+                      int64_t *walks_out)
+{
+    double *norm = NULL, total = 0.0;
+    int64_t i, e;
+    int rc = check_csr(n, row_ptr, col);
+    if (rc)
+        return rc;
+    if (!walks_out || (n_start > 0 && !starts) || Ns < 1 || (!symmetric && val))
+        return ORC_E_ARG;
+    norm = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!norm)
+        return ORC_E_NOMEM;
+    if (symmetric) {
+        for (i = 0; i < n; ++i) {
+            double sq = 0.0;
+            for (e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                double a = val ? val[e] : 1.0;
+                sq = sq + a * a;
+            }
+            norm[i] = sqrt(sq);
+        }
+    } else {
+        for (e = 0; e < row_ptr[n]; ++e)
+            norm[col[e]] = norm[col[e]] + 1.0;
+        for (i = 0; i < n; ++i)
+            norm[i] = sqrt(norm[i]);
+    }
+    memset(walks_out, 0, sizeof(int64_t) * (size_t)n);
+    for (i = 0; i < n_start; ++i) {
+        if (starts[i] < 0 || starts[i] >= n) {
+            free(norm);
+            return ORC_E_ARG;
+        }
+        total = total + norm[starts[i]];
+    }
+    for (i = 0; i < n_start; ++i) {
+        const int64_t k = starts[i];
+        int64_t w = total > 0.0 ? llround((double)Ns * (norm[k] / total)) : 1;
+        walks_out[k] = w < 1 ? 1 : w;
+    }
+    free(norm);
+    return ORC_OK;
 }
 
 /* c_0..c_K: kind 0 exp (c_k = c_{k-1}/k), kind 1 resolvent (c_k = 1). */

@@ -32,7 +32,7 @@ MUTATIONS = {
                                 "double target = u53 * u53 * g->rowabs[l];"),
     "rowabs without absolute value": ("sum = sum + fabs(entry(g, e));", "sum = sum + entry(g, e);"),
     "scale dropped from diag gather": ("inner = s * inner;", "inner = inner;"),
-    "wrong walk normalisation": ("q[k] = sum / (double)N;", "q[k] = sum / (double)(N + 1);"),
+    "wrong walk normalisation": ("q[k] = sum / (double)Nk;", "q[k] = sum / (double)(Nk + 1);"),
     "weight recorded after update": ("wt[cnt] = W;", "wt[cnt] = W * (p->s * g->rowabs[l]);"),
     "diag scattered to start row": ("dsum[ii] = dsum[ii] + (s * entry(&g, e)) * inner;",
                                     "dsum[k] = dsum[k] + (s * entry(&g, e)) * inner;"),
@@ -43,6 +43,9 @@ MUTATIONS = {
     "philox rounds": ("round < 10; ++round", "round < 9; ++round"),
     "walks of a row share one stream": ("ctr[1] = w;", "ctr[1] = 0;"),
     "action gather misses scale": ("        yi = yi + s * sum;", "        yi = yi + sum;"),
+    "allocation by squared norms": ("norm[i] = sqrt(sq);", "norm[i] = sq;"),
+    "allocation truncates": ("llround((double)Ns * (norm[k] / total))",
+                             "(int64_t)((double)Ns * (norm[k] / total))"),
 }
 
 PINS = [
@@ -57,6 +60,7 @@ PINS = [
     lambda orc: P.test_unbiased(orc, "rmat"),
     lambda orc: P.test_complete_graph_exp_diag_closed_form(orc),
     lambda orc: P.test_error_decays_as_inverse_sqrt_N(orc),
+    lambda orc: P.test_allocation_follows_column_norms(orc, "weighted"),
 ]
 
 

@@ -343,3 +343,76 @@ def test_argument_errors(orc):
         orc.diag(g, orc.FN_EXP, N=2, K=5, rows=np.array([7], np.int32))
     with pytest.raises(orc.OracleError):
         orc.action(g, [1.0, 1.0], np.ones(5), N=2, K=5)
+
+
+# ------------------------------------------------------------------ walk allocation
+
+
+def _allocation_by_formula(A, starts, Ns):
+    """N_k = max(1, round-half-up(Ns ||C_k|| / sum over starts of ||C||)), with
+    column norms from the dense matrix (Eq. initial_prob)."""
+    import math
+    norms = np.sqrt((np.asarray(A) ** 2).sum(axis=0))
+    total = 0.0
+    for k in starts:
+        total += norms[k]
+    out = np.zeros(A.shape[0], dtype=np.int64)
+    for k in starts:
+        out[k] = max(1, int(math.floor(Ns * (norms[k] / total) + 0.5)))
+    return out
+
+
+@pytest.mark.parametrize("which", ["weighted", "rmat", "directed"])
+def test_allocation_follows_column_norms(orc, which):
+    if which == "weighted":
+        g = G.with_random_weights(G.erdos_renyi_dense(60, 0.1, seed=4), seed=5, negative_fraction=0.4)
+        sym = True
+    elif which == "rmat":
+        g = G.rmat(8, seed=6)
+        sym = True
+    else:
+        rng = np.random.default_rng(9)
+        src, dst = rng.integers(0, 80, 400), rng.integers(0, 80, 400)
+        keep = src != dst
+        g = G.from_edges(80, src[keep], dst[keep], symmetric=False)
+        sym = False
+    starts = np.nonzero(g.deg > 0)[0].astype(np.int32)
+    for Ns in (1, 50, 5000, 123457):
+        got = orc.allocation(g, Ns, starts, symmetric=sym)
+        want = _allocation_by_formula(g.dense(), starts, Ns)
+        assert np.array_equal(got, want), (which, Ns)
+    # Every start row gets a walk, the rest none; the total is Ns up to rounding.
+    got = orc.allocation(g, 5000, starts, symmetric=sym)
+    assert np.all(got[starts] >= 1) and got.sum() - got[starts].sum() == 0
+    assert abs(int(got.sum()) - 5000) <= starts.size
+
+
+def test_per_row_walk_counts(orc):
+    g = G.erdos_renyi_dense(40, 0.15, seed=7)
+    K, s = 6, 0.15
+    c = orc.coeffs(orc.FN_EXP, K)
+    # Equal per-row counts reproduce the uniform run exactly.
+    same = np.where(g.deg > 0, 24, 0)
+    a = orc.action(g, c, np.ones(g.n), N=24, K=K, scale=s, seed=3, want_digest=True)
+    b = orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, seed=3, want_digest=True, walks=same)
+    assert np.array_equal(a["y"], b["y"]) and np.array_equal(a["digest"], b["digest"])
+    a = orc.diag(g, c, N=24, K=K, scale=s, seed=3, want_digest=True)
+    b = orc.diag(g, c, N=1, K=K, scale=s, seed=3, want_digest=True, walks=same)
+    assert np.array_equal(a["d"], b["d"]) and np.array_equal(a["digest"], b["digest"])
+    # Unequal counts: still unbiased (each start row's average is), and the
+    # step count is the sum over rows of walks * (K - 1) on a graph without
+    # dead ends.
+    starts = np.nonzero(g.deg > 0)[0].astype(np.int32)
+    walks = orc.allocation(g, 40 * starts.size, starts)
+    dense = orc.dense_series(g.dense(), c, s)
+    ys = [orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, seed=11, request=r, walks=walks)["y"]
+          for r in range(30)]
+    ds = [orc.diag(g, c, N=1, K=K, scale=s, seed=11, request=r, walks=walks)["d"] for r in range(30)]
+    assert _z_test(ys, dense @ np.ones(g.n)) < 5.0
+    assert _z_test(ds, np.diag(dense)) < 5.0
+    r = orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, seed=11, walks=walks)
+    assert r["steps"] == int(walks.sum()) * (K - 1)
+    with pytest.raises(orc.OracleError):
+        bad = walks.copy()
+        bad[starts[0]] = 0
+        orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, walks=bad)

@@ -112,6 +112,19 @@ typedef struct {
 #define MCMF_PRECISION_FP64 0
 #define MCMF_PRECISION_FP32_WEIGHTS 1
 
+/* Allocation of walks over the start rows.  MCMF_ALLOC_PER_ROW: n_walks
+ * walks from every start row.  MCMF_ALLOC_NORM (Definition 1 (i), Eq.
+ * initial_prob, with N_i = N_s P(l0 = i) of Algorithms 2-3): n_walks is the
+ * total N_s; start row k gets N_k = max(1, round(N_s ||C_k||_2 / sum over the
+ * start rows of ||C||_2)) walks, rounding half away from zero (one walk at
+ * least keeps every start row's term defined).  Column norms: for a graph
+ * created with MCMF_SYMMETRIC, ||C_k|| = ||R_k|| summed along row k in stored
+ * order; otherwise (unweighted graphs only) ||C_k||^2 is the number of
+ * entries in column k.  The total is summed over the start rows in ascending
+ * order.  mcmf_diag and mcmf_action only (not mcmf_batch). */
+#define MCMF_ALLOC_PER_ROW 0
+#define MCMF_ALLOC_NORM 1
+
 typedef struct {
     uint64_t seed;          /* RNG key */
     uint32_t request_id;    /* fourth Philox counter word; same id => same walks */
@@ -124,12 +137,15 @@ typedef struct {
                                the recorded states; 0 for rows that start no walk */
     double *q_out;          /* optional out (mcmf_action only), n entries: q_k of
                                Algorithm 3 per start row, 0 elsewhere */
-    uint32_t reserved[8];   /* must be zero */
+    int32_t *walks_out;     /* optional out, n entries: walks started from each row
+                               (0 for rows that start none) */
+    int32_t allocation;     /* MCMF_ALLOC_* */
+    uint32_t reserved[5];   /* must be zero */
 } mcmf_opts;
 
 typedef struct {
     uint64_t start_rows;    /* rows that started walks */
-    uint64_t walks;         /* start_rows * n_walks */
+    uint64_t walks;         /* walks started (start_rows * n_walks per row) */
     uint64_t walk_steps;    /* recorded walk states (K-1 per full walk) */
     uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather */
     double ms_setup;        /* marks, start set, temporaries */

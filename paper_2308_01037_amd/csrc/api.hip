@@ -157,6 +157,118 @@ Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int3
             return fail(MCMF_E_ARG, "unknown precision %d", o->precision);
         if (!(o->weight_cutoff >= 0.0) || !std::isfinite(o->weight_cutoff))
             return fail(MCMF_E_ARG, "weight_cutoff must be finite and >= 0");
+        if (o->allocation != MCMF_ALLOC_PER_ROW && o->allocation != MCMF_ALLOC_NORM)
+            return fail(MCMF_E_ARG, "unknown allocation %d", o->allocation);
+        if (o->allocation == MCMF_ALLOC_NORM && !g->symmetric && g->weighted)
+            return fail(MCMF_E_UNSUPPORTED,
+                        "MCMF_ALLOC_NORM on a weighted graph needs one created with MCMF_SYMMETRIC");
+    }
+    return {};
+}
+
+namespace {
+
+__global__ void k_col_count(const int32_t *__restrict__ col, int64_t nnz, unsigned int *__restrict__ cnt) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e < nnz)
+        atomicAdd(&cnt[col[e]], 1u);
+}
+
+// ||C_k||_2 of each start row: along row k (symmetric graphs, in stored
+// order, one thread per row) or from the column counts (unweighted).
+__global__ void k_start_norms(const int32_t *__restrict__ starts, int64_t n_start,
+                              const uint2 *__restrict__ node, const double *__restrict__ val,
+                              const unsigned int *__restrict__ colcount, double *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_start)
+        return;
+    const int32_t k = starts[i];
+    double sq = 0.0;
+    if (colcount) {
+        sq = static_cast<double>(colcount[k]);
+    } else {
+        const uint2 rk = node[k];
+        for (uint32_t j = 0; j < rk.y; ++j) {
+            const double a = val ? val[int64_t(rk.x) + j] : 1.0;
+            sq = sq + a * a;
+        }
+    }
+    out[i] = sqrt(sq);
+}
+
+} // namespace
+
+Status allocate_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t Ns, int K,
+                      Allocation &A, hipStream_t s) {
+    A.host_walks.assign(static_cast<size_t>(n_start), 0);
+    A.host_rec.assign(static_cast<size_t>(n_start + 1), 0);
+    A.total = 0;
+    A.max_walks = 0;
+    if (n_start == 0)
+        return {};
+    DevBuf<double> norms;
+    DevBuf<unsigned int> cnt;
+    MCMF_TRY(norms.alloc(n_start, s));
+    if (!g->symmetric) {
+        MCMF_TRY(cnt.alloc(g->n > 0 ? g->n : 1, s));
+        MCMF_TRY(fill_i32(reinterpret_cast<int32_t *>(cnt.ptr), 0, g->n, s));
+        if (g->nnz > 0) {
+            hipLaunchKernelGGL(k_col_count, dim3(static_cast<uint32_t>((g->nnz + 255) / 256)), dim3(256), 0, s,
+                               g->col, g->nnz, cnt.ptr);
+            MCMF_HIP(hipGetLastError());
+        }
+    }
+    hipLaunchKernelGGL(k_start_norms, dim3(static_cast<uint32_t>((n_start + 255) / 256)), dim3(256), 0, s,
+                       starts, n_start, g->node, g->val, g->symmetric ? nullptr : cnt.ptr, norms.ptr);
+    MCMF_HIP(hipGetLastError());
+    std::vector<double> hn(static_cast<size_t>(n_start));
+    MCMF_HIP(hipMemcpyAsync(hn.data(), norms.ptr, sizeof(double) * n_start, hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    double total = 0.0;
+    for (double x : hn)
+        total = total + x;
+    int64_t rec = 0;
+    for (int64_t i = 0; i < n_start; ++i) {
+        int64_t w = total > 0.0 ? std::llround(static_cast<double>(Ns) * (hn[i] / total)) : 1;
+        w = std::max<int64_t>(w, 1);
+        if (w > (int64_t(1) << 31) - 1)
+            return fail(MCMF_E_ARG, "MCMF_ALLOC_NORM gives a row %lld walks, above 2^31 - 1",
+                        static_cast<long long>(w));
+        A.host_walks[i] = static_cast<int32_t>(w);
+        A.host_rec[i] = rec;
+        rec += w * (K - 1);
+        A.total += w;
+        A.max_walks = std::max(A.max_walks, w);
+    }
+    A.host_rec[n_start] = rec;
+    MCMF_TRY(A.walks.alloc(n_start, s));
+    MCMF_TRY(A.rec.alloc(n_start + 1, s));
+    MCMF_HIP(hipMemcpyAsync(A.walks.ptr, A.host_walks.data(), sizeof(int32_t) * n_start,
+                            hipMemcpyHostToDevice, s));
+    MCMF_HIP(hipMemcpyAsync(A.rec.ptr, A.host_rec.data(), sizeof(int64_t) * (n_start + 1),
+                            hipMemcpyHostToDevice, s));
+    // The host vectors must outlive the asynchronous copies.
+    MCMF_HIP(hipStreamSynchronize(s));
+    return {};
+}
+
+// walks_out: the walks per row (0 off the start rows).
+Status write_walks_out(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t N_uniform,
+                       const Allocation *A, int32_t *walks_out, hipStream_t s) {
+    std::vector<int32_t> hs(static_cast<size_t>(n_start));
+    if (n_start > 0) {
+        MCMF_HIP(hipMemcpyAsync(hs.data(), starts, sizeof(int32_t) * n_start, hipMemcpyDeviceToHost, s));
+        MCMF_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> w(static_cast<size_t>(g->n), 0);
+    for (int64_t i = 0; i < n_start; ++i)
+        w[static_cast<size_t>(hs[i])] = A ? A->host_walks[i] : static_cast<int32_t>(N_uniform);
+    if (classify(walks_out) == Mem::Device) {
+        if (g->n)
+            MCMF_HIP(hipMemcpyAsync(walks_out, w.data(), sizeof(int32_t) * g->n, hipMemcpyHostToDevice, s));
+        MCMF_HIP(hipStreamSynchronize(s));
+    } else if (g->n) {
+        std::copy(w.begin(), w.end(), walks_out);
     }
     return {};
 }
@@ -255,10 +367,19 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
     MCMF_TRY(tm.mark(1));
     MCMF_TRY(spmv_r(g, vin.ptr, f->scale, rec.ptr, s));
     MCMF_TRY(tm.mark(2));
+    const bool by_norm = o && o->allocation == MCMF_ALLOC_NORM && K >= 2;
+    Allocation alloc;
+    if (by_norm)
+        MCMF_TRY(allocate_walks(g, g->active, g->n_active, N, K, alloc, s));
     if (K >= 2) {
-        const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        if (by_norm)
+            p.row_walks = alloc.walks.ptr;
         MCMF_TRY(action_walks(g, rec.ptr, g->active, g->n_active, p, qptr, dig.ptr, steps.ptr, s));
     }
+    if (o && o->walks_out)
+        MCMF_TRY(write_walks_out(g, g->active, K >= 2 ? g->n_active : 0, N, by_norm ? &alloc : nullptr,
+                                 o->walks_out, s));
     MCMF_TRY(tm.mark(3));
     MCMF_TRY(spmv_assemble(g, vin.ptr, rec.ptr, K >= 2 ? qptr : nullptr, c[0], K >= 1 ? c[1] : 0.0,
                            f->scale, yout.ptr, s));
@@ -286,7 +407,8 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
     if (stats) {
         memset(stats, 0, sizeof *stats);
         stats->start_rows = K >= 2 ? static_cast<uint64_t>(g->n_active) : 0;
-        stats->walks = stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
+        stats->walks = by_norm ? static_cast<uint64_t>(alloc.total)
+                               : stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
         stats->walk_steps = nsteps;
         stats->ms_setup = tm.ms(0, 1);
         stats->ms_spmv = tm.ms(1, 2) + tm.ms(3, 4);
@@ -386,24 +508,56 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     MCMF_TRY(tm.mark(1));
     float ms_walk = 0.f, ms_gather = 0.f;
     EventList chunk_events;
+    const bool by_norm = o && o->allocation == MCMF_ALLOC_NORM && K >= 2;
+    Allocation alloc;
+    if (by_norm)
+        MCMF_TRY(allocate_walks(g, starts, n_start, N, K, alloc, s));
+    if (o && o->walks_out)
+        MCMF_TRY(write_walks_out(g, starts, K >= 2 ? n_start : 0, N, by_norm ? &alloc : nullptr,
+                                 o->walks_out, s));
     if (K >= 2 && n_start > 0) {
-        const WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
+        if (by_norm) {
+            // The gather indexes the whole start list; its table is planned
+            // for the row with the most walks.
+            p.row_walks = alloc.walks.ptr;
+            p.row_rec = alloc.rec.ptr;
+            p.n_walks = alloc.max_walks;
+        }
         // Visit records of a chunk of start rows: 12 bytes per visit (8 with
-        // FP32 walk weights).
+        // FP32 walk weights).  Chunk boundaries: rows [bounds[i], bounds[i+1]).
         const int64_t per_row = N * (K - 1);
         const int64_t xbytes = p.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
         int64_t chunk_bytes = int64_t(2) << 30;
         if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
             chunk_bytes = std::max<int64_t>(1, strtoll(e, nullptr, 10));
-        int64_t rows_per_chunk = chunk_bytes / (per_row * (4 + xbytes));
-        rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(rows_per_chunk, n_start));
+        const int64_t chunk_recs = std::max<int64_t>(1, chunk_bytes / (4 + xbytes));
+        std::vector<int64_t> bounds(1, 0);
+        int64_t most_recs = 0;
+        if (by_norm) {
+            int64_t c0 = 0;
+            while (c0 < n_start) {
+                int64_t c1 = c0 + 1; // at least one row per chunk
+                while (c1 < n_start && alloc.host_rec[c1 + 1] - alloc.host_rec[c0] <= chunk_recs)
+                    ++c1;
+                most_recs = std::max(most_recs, alloc.host_rec[c1] - alloc.host_rec[c0]);
+                bounds.push_back(c1);
+                c0 = c1;
+            }
+        } else {
+            int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(chunk_recs / per_row, n_start));
+            for (int64_t c0 = rows_per_chunk; c0 < n_start; c0 += rows_per_chunk)
+                bounds.push_back(c0);
+            bounds.push_back(n_start);
+            most_recs = rows_per_chunk * per_row;
+        }
         DevBuf<int32_t> vstate;
         DevBuf<unsigned char> vx;
-        MCMF_TRY(vstate.alloc(rows_per_chunk * per_row, s));
-        MCMF_TRY(vx.alloc(rows_per_chunk * per_row * xbytes, s));
+        MCMF_TRY(vstate.alloc(most_recs, s));
+        MCMF_TRY(vx.alloc(most_recs * xbytes, s));
         // Per-chunk events are read only after the call's final synchronisation,
         // so timing does not stall the stream between chunks.
-        const int64_t n_chunks = (n_start + rows_per_chunk - 1) / rows_per_chunk;
+        const int64_t n_chunks = static_cast<int64_t>(bounds.size()) - 1;
         DevBuf<unsigned long long> queues; // one work counter per gather launch
         MCMF_TRY(queues.alloc(n_chunks, s));
         MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_chunks, s));
@@ -413,11 +567,16 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
                 MCMF_HIP(hipEventCreate(&e));
         }
         for (int64_t ci = 0; ci < n_chunks; ++ci) {
-            const int64_t c0 = ci * rows_per_chunk;
-            const int64_t rows_here = std::min(rows_per_chunk, n_start - c0);
+            const int64_t c0 = bounds[ci];
+            const int64_t rows_here = bounds[ci + 1] - c0;
             if (stats)
                 MCMF_HIP(hipEventRecord(chunk_events[2 * ci], s));
-            MCMF_TRY(diag_walks(g, starts + c0, rows_here, p, vstate.ptr, vx.ptr, dig.ptr,
+            WalkParams pw = p; // the walk launch indexes this chunk's rows
+            if (by_norm) {
+                pw.row_walks = alloc.walks.ptr + c0;
+                pw.row_rec = alloc.rec.ptr + c0;
+            }
+            MCMF_TRY(diag_walks(g, starts + c0, rows_here, pw, vstate.ptr, vx.ptr, dig.ptr,
                                 counters.ptr, s));
             if (stats)
                 MCMF_HIP(hipEventRecord(chunk_events[2 * ci + 1], s));
@@ -459,7 +618,8 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         }
         memset(stats, 0, sizeof *stats);
         stats->start_rows = K >= 2 ? static_cast<uint64_t>(n_start) : 0;
-        stats->walks = stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
+        stats->walks = by_norm ? static_cast<uint64_t>(alloc.total)
+                               : stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
         stats->walk_steps = hc[0];
         stats->gather_probes = hc[1];
         stats->ms_setup = tm.ms(0, 1);

@@ -66,6 +66,8 @@ struct GatherArgs {
     const int32_t *vstate; // records of start row row_begin onwards
     const void *vx;        // double[] or float[] (FP32 walk weights)
     const uint8_t *in_set; // null: every row requested
+    const int32_t *row_walks; // per start row (whole start list); null: N each
+    const int64_t *row_rec;   // first visit record per start row (with row_walks)
     double scale;
     uint32_t nb; // buckets
     double *dacc;
@@ -109,9 +111,13 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
                             static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
         job.p_begin = part * kBatch;
         job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
-        job.st = a.vstate + (kk - a.row_begin) * span;
-        gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + (kk - a.row_begin) * span,
-                                 probes);
+        int64_t rec = (kk - a.row_begin) * span;
+        if (a.row_walks) {
+            job.N = dev::uniform(static_cast<int64_t>(a.row_walks[kk]));
+            rec = dev::uniform(a.row_rec[kk] - a.row_rec[a.row_begin]);
+        }
+        job.st = a.vstate + rec;
+        gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + rec, probes);
     }
     if (a.probes) {
         const unsigned long long total = dev::block_sum(probes, red);
@@ -158,6 +164,8 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.vstate = state;
     a.vx = x;
     a.in_set = in_set;
+    a.row_walks = p.row_walks;
+    a.row_rec = p.row_rec;
     a.scale = p.scale;
     a.dacc = dacc;
     a.probes = probes;

@@ -1,6 +1,8 @@
 // Launchers of the library's kernels, callable from any translation unit.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace mcmf {
@@ -29,6 +31,11 @@ struct WalkParams {
     // Sampler layout and load policy: -1 = the graph's tuning.
     int sampler = -1;
     int stream = -1;
+    // Walks per start row (device, indexed like the start list passed to the
+    // walk launcher) and the first visit record of each of those rows
+    // (prefix sums of walks * (K-1)); null: n_walks for every row.
+    const int32_t *row_walks = nullptr;
+    const int64_t *row_rec = nullptr;
 };
 
 // r = s A v.
@@ -74,6 +81,20 @@ Status diag_finish(const mcmf_graph *g, const int32_t *rows, int64_t count, int 
                    double c1, double scale, const double *dacc, double *out, hipStream_t s);
 Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K,
                     const mcmf_opts *o);
+
+// Walks per start row of MCMF_ALLOC_NORM (device arrays for the kernels,
+// host copies for chunking and statistics).
+struct Allocation {
+    DevBuf<int32_t> walks;          // per start row
+    DevBuf<int64_t> rec;            // first visit record per start row, n_start + 1
+    std::vector<int32_t> host_walks;
+    std::vector<int64_t> host_rec;
+    int64_t total = 0, max_walks = 0;
+};
+Status allocate_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t Ns, int K,
+                      Allocation &A, hipStream_t s);
+Status write_walks_out(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t N_uniform,
+                       const Allocation *A, int32_t *walks_out, hipStream_t s);
 WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N);
 
 // Batched execution (batch.hip): argument check of one request, and a batch.

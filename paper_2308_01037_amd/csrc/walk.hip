@@ -25,10 +25,11 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
         const uint32_t k = static_cast<uint32_t>(starts[kk]);
         const uint2 rk = g.node[k];
         const double r_k = r[k];
+        const int64_t N = a.row_walks ? a.row_walks[kk] : a.N;
         double acc = 0.0;
         uint64_t dig = 0;
         unsigned long long nsteps = 0;
-        for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+        for (int64_t w64 = threadIdx.x; w64 < N; w64 += blockDim.x) {
             uint64_t h = dev::kFnvBasis;
             acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF, EDGE, STREAM>(
                 g, r, a, k, rk, r_k, static_cast<uint32_t>(w64), &h, &nsteps);
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(256) void k_action_walk(GraphView g, const double *
                 digest[k] = dg;
         }
         if (threadIdx.x == 0) {
-            q[k] = total / static_cast<double>(a.N);
+            q[k] = total / static_cast<double>(N);
             if (steps)
                 atomicAdd(steps, st);
         }
@@ -63,14 +64,15 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
     for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
         const uint32_t k = static_cast<uint32_t>(starts[kk]);
         const uint2 rk = g.node[k];
-        const int64_t row_base = kk * (a.K - 1) * a.N;
+        const int64_t N = a.row_walks ? a.row_walks[kk] : a.N;
+        const int64_t row_base = a.row_rec ? a.row_rec[kk] - a.row_rec[0] : kk * (a.K - 1) * a.N;
         uint64_t dig = 0;
         unsigned long long nsteps = 0;
-        for (int64_t w64 = threadIdx.x; w64 < a.N; w64 += blockDim.x) {
+        for (int64_t w64 = threadIdx.x; w64 < N; w64 += blockDim.x) {
             uint64_t h = dev::kFnvBasis;
             walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF, EDGE, STREAM>(g, a, k, rk, static_cast<uint32_t>(w64),
                                                            vstate + row_base + w64,
-                                                           vx + row_base + w64, a.N, &h, &nsteps);
+                                                           vx + row_base + w64, N, &h, &nsteps);
             if (DIGEST)
                 dig += h;
         }
@@ -107,7 +109,7 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
         return {};
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
-    const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
+    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks));
     const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.action_sampler) == MCMF_SAMPLER_EDGE;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.action_stream) != 0;
     walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
@@ -130,7 +132,7 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
         return {};
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
-    const dim3 grid = walk_grid(n_start), block(walk_block(p.n_walks));
+    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks));
     const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_EDGE;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.diag_stream) != 0;
     walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,

@@ -44,6 +44,8 @@ struct WalkArgs {
     int64_t N;
     uint32_t key0, key1, request;
     double cutoff;
+    const int32_t *row_walks; // null: N walks per start row
+    const int64_t *row_rec;   // first visit record per start row (with row_walks)
 };
 
 inline WalkArgs to_args(const WalkParams &p) {
@@ -56,6 +58,8 @@ inline WalkArgs to_args(const WalkParams &p) {
     a.key1 = p.key1;
     a.request = p.request;
     a.cutoff = p.cutoff;
+    a.row_walks = p.row_walks;
+    a.row_rec = p.row_rec;
     return a;
 }
 

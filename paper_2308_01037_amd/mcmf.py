@@ -53,6 +53,9 @@ MCMF_DIGRAPH = 4
 MCMF_PRECISION_FP64 = 0
 MCMF_PRECISION_FP32_WEIGHTS = 1
 
+MCMF_ALLOC_PER_ROW = 0
+MCMF_ALLOC_NORM = 1
+
 MCMF_SAMPLER_EDGE = 0
 MCMF_SAMPLER_ROW = 1
 
@@ -66,7 +69,8 @@ class mcmf_opts(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("request_id", ctypes.c_uint32),
                 ("precision", ctypes.c_int32), ("weight_cutoff", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("path_digest", ctypes.c_void_p),
-                ("q_out", ctypes.c_void_p), ("reserved", ctypes.c_uint32 * 8)]
+                ("q_out", ctypes.c_void_p), ("walks_out", ctypes.c_void_p),
+                ("allocation", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 5)]
 
 
 class mcmf_stats(ctypes.Structure):
@@ -242,7 +246,8 @@ def make_fn(kind: int = MCMF_FN_EXP, scale: float = 1.0, coeffs=None):
 
 
 def make_opts(seed: int = 0, request_id: int = 0, precision: int = MCMF_PRECISION_FP64,
-              weight_cutoff: float = 0.0, stream=None, path_digest=None, q_out=None):
+              weight_cutoff: float = 0.0, stream=None, path_digest=None, q_out=None,
+              allocation: int = MCMF_ALLOC_PER_ROW, walks_out=None):
     o = mcmf_opts()
     o.seed = seed
     o.request_id = request_id
@@ -251,8 +256,11 @@ def make_opts(seed: int = 0, request_id: int = 0, precision: int = MCMF_PRECISIO
     o.stream = stream
     _check_dtype(path_digest, np.uint64, "path_digest")
     _check_dtype(q_out, np.float64, "q_out")
+    _check_dtype(walks_out, np.int32, "walks_out")
     o.path_digest = _addr(path_digest)
     o.q_out = _addr(q_out)
+    o.walks_out = _addr(walks_out)
+    o.allocation = allocation
     return o
 
 

@@ -147,7 +147,8 @@ typedef struct {
     uint64_t start_rows;    /* rows that started walks */
     uint64_t walks;         /* walks started (start_rows * n_walks per row) */
     uint64_t walk_steps;    /* recorded walk states (K-1 per full walk) */
-    uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather */
+    uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather, plus the
+                               visit records each hub sweep of the gather reads */
     double ms_setup;        /* marks, start set, temporaries */
     double ms_spmv;         /* r = sA v and the final assembly (action);
                                the final assembly of the diagonal (diag) */
@@ -199,9 +200,18 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
 #define MCMF_SAMPLER_ROW 1  /* the picked column (4 bytes), then the next row's record
                                (8 bytes): two dependent loads, less data per step */
 
-/* Per-graph choices of the walk kernels.  They change memory traffic only,
- * never a result.  Defaults: action EDGE with non-temporal loads, diag EDGE
- * with cached loads. */
+/* Per-graph choices of the walk kernels and of the diagonal gather.  They
+ * change memory traffic and the order of floating-point sums only: walk paths
+ * and step counts never change.  Defaults: action EDGE with non-temporal
+ * loads, diag EDGE with cached loads, automatic hub threshold.
+ *
+ * Hub rows: a graph created unweighted with MCMF_SYMMETRIC and strictly
+ * increasing columns in every row keeps its (at most 32) rows of largest
+ * degree as hubs, with one 32-bit mask per node of the hubs it is adjacent
+ * to.  For a start row k next to a hub h, <Q_k, C_h> of Eq.
+ * rand_funm_formula_diag is then the sum of the visit weights of k's walks
+ * at states adjacent to h: one mask read per visit record, instead of one
+ * probe of Q_k per entry of row h. */
 typedef struct {
     int32_t action_sampler;  /* MCMF_SAMPLER_* of mcmf_action walks */
     int32_t action_stream;   /* 1: the walk's record loads are non-temporal */
@@ -210,7 +220,13 @@ typedef struct {
     double action_ms[4];     /* mcmf_tune only: ms of each action variant, index sampler*2+stream */
     double diag_ms[4];       /* mcmf_tune only: ms of each diag-walk variant, same index */
     int64_t sample_rows;     /* mcmf_tune only: start rows in the timed sample */
-    uint32_t reserved[6];    /* must be zero on input */
+    int32_t hub_min_degree;  /* diagonal gather (unweighted graphs): a hub row (below) of at
+                                least this many entries is summed by the hub pass instead of
+                                being probed entry by entry; 0 = automatic, a degree of at
+                                least n_walks (K - 1) / 4; INT32_MAX turns the pass off */
+    int32_t hub_count;       /* out of mcmf_graph_get_tuning: hub rows the graph holds;
+                                ignored on input */
+    uint32_t reserved[4];    /* must be zero on input */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the

@@ -524,6 +524,10 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
             p.row_rec = alloc.rec.ptr;
             p.n_walks = alloc.max_walks;
         }
+        // Hub rows: the walks sum them, the gather leaves them out.
+        p.hub_act = g->weighted ? 0u : active_hubs(g, p.n_walks, K);
+        p.in_set = all ? nullptr : in_set.ptr;
+        p.dacc = dacc.ptr;
         // Visit records of a chunk of start rows: 12 bytes per visit (8 with
         // FP32 walk weights).  Chunk boundaries: rows [bounds[i], bounds[i+1]).
         const int64_t per_row = N * (K - 1);

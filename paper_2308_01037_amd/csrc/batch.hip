@@ -53,6 +53,10 @@ struct BReq {
     double *dacc;              // diag sums
     const int64_t *item_off;   // diag: gather work items of the start list
     int64_t wpp;               // walks per gather pass
+    const uint32_t *hubmask;   // diag: the graph's hub masks
+    const uint8_t *hub_of;
+    const int32_t *hub_row;
+    uint32_t hub_act;          // diag: hubs summed by the hub pass
 };
 
 // A run of one request's start rows inside a walk launch.  A task is one
@@ -268,6 +272,11 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         job.scale = R.a.scale;
         job.dacc = R.dacc;
         job.overflow = probes_out + 1;
+        job.hubmask = R.hubmask;
+        job.hub_of = R.hub_of;
+        job.hub_row = R.hub_row;
+        job.hub_act = R.hub_act;
+        job.hub_pass = true;
         gather_row<WEIGHTED, VT>(sh, job, reinterpret_cast<const VT *>(vxb + sg.xoff) + rel * span,
                                  probes);
     }
@@ -467,6 +476,12 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.in_set = P.all ? nullptr : P.in_set.ptr;
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
+        if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted) {
+            B.hubmask = q.graph->hubmask;
+            B.hub_of = q.graph->hub_of;
+            B.hub_row = q.graph->hub_rows;
+            B.hub_act = active_hubs(q.graph, q.n_walks, q.K);
+        }
     }
     DevBuf<unsigned long long> counters; // per request steps, then probes, overflow
     MCMF_TRY(counters.alloc(n_reqs + 2, s));

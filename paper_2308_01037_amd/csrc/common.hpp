@@ -122,6 +122,10 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c);
 
 int num_cus();
 
+// Hub rows of the diagonal gather: at most one per bit of a 32-bit mask.
+constexpr int kMaxHubs = 32;
+constexpr uint8_t kNoHub = 0xFF;
+
 } // namespace mcmf
 
 // Opaque graph handle: the device copy of A and its per-row metadata.
@@ -144,9 +148,10 @@ struct mcmf_graph {
     double *cum = nullptr;      // [nnz] running sums of |a| per row (weighted only)
     double *diagval = nullptr;  // [n] a_ii (only when the graph has loops)
     uint2 *node = nullptr;      // [n] {first entry, row length}
-    // [nnz] per stored entry a_ij: {j, first entry of row j, length of row j, 0}.
-    // A walk step then needs one dependent load: the entry it picks already
-    // carries the record of the row it moves to.
+    // [nnz] per stored entry a_ij: {j, first entry of row j, length of row j,
+    // hubmask[j] (0 without hubs)}.  A walk step then needs one dependent
+    // load: the entry it picks already carries the record of the row it
+    // moves to.
     uint4 *edge = nullptr;
     int32_t *active = nullptr;  // [n_active] rows with entries, ascending
     // [n_active + 1] first diagonal-gather work item of each active row
@@ -159,6 +164,17 @@ struct mcmf_graph {
     int64_t bin_offset[3] = {0, 0, 0};
     size_t bytes = 0;
     // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
-    mcmf_tuning tuning = {MCMF_SAMPLER_EDGE, 1, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, {}};
+    mcmf_tuning tuning = {MCMF_SAMPLER_EDGE, 1, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {}};
+    // Hub rows (unweighted symmetric graphs with strictly increasing rows):
+    // the rows of largest degree, at most kMaxHubs.  hubmask[j] has bit h set
+    // when j is a column of row hub_rows[h] (by symmetry: when j is adjacent
+    // to hub h); hub_of[i] = h for hub row i, kNoHub elsewhere.
+    bool strict_rows = false;
+    int32_t n_hubs = 0;
+    int32_t hub_rows_host[mcmf::kMaxHubs] = {};
+    int64_t hub_deg_host[mcmf::kMaxHubs] = {};
+    int32_t *hub_rows = nullptr; // [kMaxHubs]
+    uint32_t *hubmask = nullptr; // [n]
+    uint8_t *hub_of = nullptr;   // [n]
 
 };

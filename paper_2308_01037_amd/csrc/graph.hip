@@ -1,6 +1,7 @@
 // CSR graph store in device memory and its per-row metadata (row records,
 // rows with entries, length bins, |a| sums and running sums for weighted
 // rows), plus the small utility kernels (fills, ordered compaction).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -103,7 +104,7 @@ enum : int {
     kErrRowPtr = 1,    // decreasing row_ptr
     kErrColumn = 2,    // column outside [0, n)
     kErrValue = 4,     // non-finite value
-    kErrUnsorted = 8,  // row not strictly increasing (needed by the symmetry check)
+    kErrUnsorted = 8,  // row not strictly increasing (symmetry check, hub rows)
     kErrAsymmetric = 16,
 };
 
@@ -114,10 +115,10 @@ __global__ void k_check_row_ptr(const int64_t *row_ptr, int64_t n, int *err) {
             atomicOr(err, kErrRowPtr);
 }
 
-// One wavefront per row: column range, finite values, and (optionally) strict order.
+// One wavefront per row: column range, finite values, and strict order.
 __global__ __launch_bounds__(kThreads) void k_check_entries(const int64_t *row_ptr, int64_t n,
                                                             const int32_t *col, const double *val,
-                                                            int check_sorted, int *err) {
+                                                            int *err) {
     const int lane = threadIdx.x & 63;
     const int64_t waves = int64_t(gridDim.x) * (blockDim.x / 64);
     for (int64_t i = blockIdx.x * int64_t(blockDim.x / 64) + (threadIdx.x >> 6); i < n; i += waves) {
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_check_entries(const int64_t *row_p
                 bad |= kErrColumn;
             if (val && !isfinite(val[k]))
                 bad |= kErrValue;
-            if (check_sorted && k + 1 < e && col[k + 1] <= c)
+            if (k + 1 < e && col[k + 1] <= c)
                 bad |= kErrUnsorted;
         }
         if (bad)
@@ -169,14 +170,28 @@ __global__ void k_graph_meta(const int64_t *row_ptr, int64_t n, const double *va
         atomicMax(dmax, local_max);
 }
 
-// edge[e] = {col[e], record of row col[e]} for every stored entry.
-__global__ void k_build_edges(const int32_t *col, int64_t nnz, const uint2 *node, uint4 *edge) {
+// edge[e] = {col[e], record of row col[e], hubs adjacent to col[e]} for
+// every stored entry (hubmask null: no hubs).
+__global__ void k_build_edges(const int32_t *col, int64_t nnz, const uint2 *node,
+                              const uint32_t *hubmask, uint4 *edge) {
     for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nnz;
          e += int64_t(gridDim.x) * blockDim.x) {
         const int32_t j = col[e];
         const uint2 rj = node[j];
-        edge[e] = make_uint4(static_cast<uint32_t>(j), rj.x, rj.y, 0u);
+        edge[e] = make_uint4(static_cast<uint32_t>(j), rj.x, rj.y, hubmask ? hubmask[j] : 0u);
     }
+}
+
+// Hub h (one workgroup each): bit h in the mask of every column of its row.
+__global__ void k_hub_marks(const int32_t *hub_rows, const uint2 *node, const int32_t *col,
+                            uint32_t *hubmask, uint8_t *hub_of) {
+    const int h = blockIdx.x;
+    const int32_t row = hub_rows[h];
+    const uint2 r = node[row];
+    for (uint32_t e = threadIdx.x; e < r.y; e += blockDim.x)
+        atomicOr(&hubmask[col[int64_t(r.x) + e]], 1u << h);
+    if (threadIdx.x == 0)
+        hub_of[row] = static_cast<uint8_t>(h);
 }
 
 // a_ji == a_ij for every stored a_ij (rows sorted): one wavefront per row,
@@ -248,9 +263,53 @@ void free_graph(mcmf_graph *g) {
     dev_free_sync(g->active, sizeof(int32_t) * g->n_active);
     dev_free_sync(g->active_items, sizeof(int64_t) * (g->n_active + 1));
     dev_free_sync(g->bin_rows, sizeof(int32_t) * g->n);
+    dev_free_sync(g->hubmask, sizeof(uint32_t) * g->n);
+    dev_free_sync(g->hub_of, sizeof(uint8_t) * g->n);
+    dev_free_sync(g->hub_rows, sizeof(int32_t) * kMaxHubs);
     if (g->stream)
         (void)hipStreamDestroy(g->stream);
     delete g;
+}
+
+// The graph's hub rows: the kMaxHubs rows of largest degree (ties: lower
+// row first), chosen on the host from the row records, and their masks.
+Status build_hubs(mcmf_graph *g, hipStream_t s) {
+    const int64_t n = g->n;
+    std::vector<uint2> node(static_cast<size_t>(n));
+    MCMF_HIP(hipMemcpyAsync(node.data(), g->node, sizeof(uint2) * n, hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipStreamSynchronize(s));
+    std::vector<std::pair<uint32_t, int32_t>> top; // (degree, row), degree descending
+    auto before = [](const std::pair<uint32_t, int32_t> &a, const std::pair<uint32_t, int32_t> &b) {
+        return a.first > b.first;
+    };
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t d = node[static_cast<size_t>(i)].y;
+        if (d == 0 || (static_cast<int>(top.size()) == kMaxHubs && d <= top.back().first))
+            continue;
+        const std::pair<uint32_t, int32_t> x(d, static_cast<int32_t>(i));
+        top.insert(std::upper_bound(top.begin(), top.end(), x, before), x);
+        if (static_cast<int>(top.size()) > kMaxHubs)
+            top.pop_back();
+    }
+    g->n_hubs = static_cast<int32_t>(top.size());
+    if (g->n_hubs == 0)
+        return {};
+    for (int h = 0; h < g->n_hubs; ++h) {
+        g->hub_rows_host[h] = top[h].second;
+        g->hub_deg_host[h] = top[h].first;
+    }
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->hubmask), sizeof(uint32_t) * n));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->hub_of), sizeof(uint8_t) * n));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->hub_rows), sizeof(int32_t) * kMaxHubs));
+    MCMF_TRY(fill_impl<uint32_t>(g->hubmask, 0u, n, s));
+    MCMF_TRY(fill_impl<uint8_t>(g->hub_of, kNoHub, n, s));
+    MCMF_HIP(hipMemcpyAsync(g->hub_rows, g->hub_rows_host, sizeof(int32_t) * kMaxHubs,
+                            hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_hub_marks, dim3(g->n_hubs), dim3(kThreads), 0, s, g->hub_rows, g->node, g->col,
+                       g->hubmask, g->hub_of);
+    MCMF_HIP(hipGetLastError());
+    MCMF_HIP(hipStreamSynchronize(s));
+    return {};
 }
 
 Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32_t *col,
@@ -318,7 +377,7 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     const bool check_sym = validate && g->symmetric;
     if (n > 0) {
         hipLaunchKernelGGL(k_check_entries, dim3(grid_for(n, 4)), dim3(kThreads), 0, s, d_rp.ptr,
-                           n, g->col, validate ? g->val : nullptr, check_sym ? 1 : 0, d_err.ptr);
+                           n, g->col, validate ? g->val : nullptr, d_err.ptr);
         MCMF_HIP(hipGetLastError());
     }
     MCMF_TRY(read_flag(d_err.ptr, &err, s));
@@ -326,7 +385,8 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
         return fail(MCMF_E_CSR, "a column index lies outside [0, n)");
     if (err & kErrValue)
         return fail(MCMF_E_CSR, "a stored value is not finite");
-    if (err & kErrUnsorted)
+    g->strict_rows = (err & kErrUnsorted) == 0;
+    if (check_sym && (err & kErrUnsorted))
         return fail(MCMF_E_NOT_SYMMETRIC,
                     "the symmetry check needs strictly increasing columns within each row");
 
@@ -336,9 +396,11 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
                            g->val, g->node, d_active.ptr, d_bin.ptr, g->rowabs, g->cum, d_dmax.ptr);
         MCMF_HIP(hipGetLastError());
     }
+    if (!g->weighted && g->symmetric && g->strict_rows && nnz > 0)
+        MCMF_TRY(build_hubs(g, s));
     if (nnz > 0) {
         hipLaunchKernelGGL(k_build_edges, dim3(grid_for(nnz)), dim3(kThreads), 0, s, g->col, nnz,
-                           g->node, g->edge);
+                           g->node, g->hubmask, g->edge);
         MCMF_HIP(hipGetLastError());
     }
     if (check_sym && n > 0) {
@@ -374,11 +436,25 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     MCMF_HIP(hipStreamSynchronize(s));
     g->bytes = (sizeof(int32_t) + sizeof(uint4)) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
                sizeof(int64_t) * (g->n_active + 1) +
-               (g->weighted ? sizeof(double) * (2 * nnz + n) : 0);
+               (g->weighted ? sizeof(double) * (2 * nnz + n) : 0) +
+               (g->n_hubs > 0 ? (sizeof(uint32_t) + sizeof(uint8_t)) * n + sizeof(int32_t) * kMaxHubs : 0);
     return {};
 }
 
 } // namespace
+
+uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K) {
+    if (g->n_hubs == 0)
+        return 0u;
+    int64_t min_deg = g->tuning.hub_min_degree;
+    if (min_deg <= 0)
+        min_deg = std::max<int64_t>(1, n_walks * (K - 1) / 4);
+    uint32_t m = 0u;
+    for (int h = 0; h < g->n_hubs; ++h)
+        if (g->hub_deg_host[h] >= min_deg)
+            m |= 1u << h;
+    return m;
+}
 
 Status fill_u8(uint8_t *out, uint8_t value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }
 Status fill_i32(int32_t *out, int32_t value, int64_t n, hipStream_t s) { return fill_impl(out, value, n, s); }

@@ -13,6 +13,11 @@ Status fill_i32(int32_t *out, int32_t value, int64_t n, hipStream_t s);
 Status fill_f64(double *out, double value, int64_t n, hipStream_t s);
 Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s);
 
+// Mask of the graph's hubs that the diagonal gather sums by the hub pass for
+// n_walks walks per start row and K (the tuning's hub_min_degree, or by
+// default hubs of degree >= n_walks (K - 1) / 4); 0 without hubs.
+uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K);
+
 // Ascending indices i < n with flags[i] == match written to out; *count (host)
 // receives how many.  Synchronises the stream to read the count back.
 Status compact(const uint8_t *flags, int64_t n, uint8_t match, int32_t *out, int64_t *count,
@@ -36,6 +41,12 @@ struct WalkParams {
     // (prefix sums of walks * (K-1)); null: n_walks for every row.
     const int32_t *row_walks = nullptr;
     const int64_t *row_rec = nullptr;
+    // Diagonal walks: hubs whose sums <Q_k, C_h> the walk kernel adds into
+    // dacc as it records the visits (0: none), and the requested rows (null:
+    // all).
+    uint32_t hub_act = 0;
+    const uint8_t *in_set = nullptr;
+    double *dacc = nullptr;
 };
 
 // r = s A v.

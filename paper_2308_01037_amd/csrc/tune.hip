@@ -37,6 +37,8 @@ Status check_tuning(const mcmf_tuning *t) {
         return fail(MCMF_E_ARG, "unknown sampler layout");
     if (!flag_ok(t->action_stream) || !flag_ok(t->diag_stream))
         return fail(MCMF_E_ARG, "stream flags must be 0 or 1");
+    if (t->hub_min_degree < 0)
+        return fail(MCMF_E_ARG, "hub_min_degree must be >= 0 (got %d)", t->hub_min_degree);
     return {};
 }
 
@@ -138,6 +140,7 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     MCMF_HIP(hipStreamSynchronize(s));
     g->tuning = best;
     *out = best;
+    out->hub_count = g->n_hubs;
     return {};
 }
 
@@ -158,6 +161,7 @@ extern "C" mcmf_status mcmf_graph_set_tuning(mcmf_graph *g, const mcmf_tuning *t
     g->tuning.action_stream = t->action_stream;
     g->tuning.diag_sampler = t->diag_sampler;
     g->tuning.diag_stream = t->diag_stream;
+    g->tuning.hub_min_degree = t->hub_min_degree;
     return MCMF_OK;
 }
 
@@ -168,6 +172,7 @@ extern "C" mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t
         return MCMF_E_ARG;
     }
     *t = g->tuning;
+    t->hub_count = g->n_hubs;
     return MCMF_OK;
 }
 

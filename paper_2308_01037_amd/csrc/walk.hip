@@ -61,20 +61,47 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
                                                    uint64_t *__restrict__ digest,
                                                    unsigned long long *steps) {
     __shared__ unsigned long long redu[4];
+    __shared__ double hsum[kMaxHubs];
     for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
         const uint32_t k = static_cast<uint32_t>(starts[kk]);
         const uint2 rk = g.node[k];
         const int64_t N = a.row_walks ? a.row_walks[kk] : a.N;
         const int64_t row_base = a.row_rec ? a.row_rec[kk] - a.row_rec[0] : kk * (a.K - 1) * a.N;
+        // Requested hubs adjacent to k: their <Q_k, C_h> are summed here.
+        uint32_t hub_k = 0u;
+        if constexpr (!WEIGHTED) {
+            if (a.hub_act != 0u) {
+                hub_k = static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(g.hubmask[k]))) & a.hub_act;
+                if (hub_k != 0u && a.in_set) {
+                    const int lane = threadIdx.x & 63;
+                    const bool keep = lane < kMaxHubs && ((hub_k >> lane) & 1u) && a.in_set[g.hub_row[lane]];
+                    hub_k = static_cast<uint32_t>(__ballot(keep));
+                }
+                if (hub_k != 0u) {
+                    if (threadIdx.x < kMaxHubs)
+                        hsum[threadIdx.x] = 0.0;
+                    __syncthreads();
+                }
+            }
+        }
         uint64_t dig = 0;
         unsigned long long nsteps = 0;
         for (int64_t w64 = threadIdx.x; w64 < N; w64 += blockDim.x) {
             uint64_t h = dev::kFnvBasis;
             walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF, EDGE, STREAM>(g, a, k, rk, static_cast<uint32_t>(w64),
                                                            vstate + row_base + w64,
-                                                           vx + row_base + w64, N, &h, &nsteps);
+                                                           vx + row_base + w64, N, &h, &nsteps,
+                                                           hub_k, hsum);
             if (DIGEST)
                 dig += h;
+        }
+        if (hub_k != 0u) {
+            // dacc[h] += s a_kh * s <Q_k, C_h> / N, as the gather adds it.
+            __syncthreads();
+            const int t = threadIdx.x;
+            if (t < kMaxHubs && ((hub_k >> t) & 1u) && hsum[t] != 0.0)
+                atomicAdd(&a.dacc[g.hub_row[t]], a.scale * (a.scale * hsum[t]) * (1.0 / static_cast<double>(N)));
+            __syncthreads();
         }
         const unsigned long long st = dev::block_sum(nsteps, redu);
         if (DIGEST) {

@@ -46,6 +46,9 @@ struct WalkArgs {
     double cutoff;
     const int32_t *row_walks; // null: N walks per start row
     const int64_t *row_rec;   // first visit record per start row (with row_walks)
+    uint32_t hub_act;         // diag: hubs summed by the walk kernel (0: none)
+    const uint8_t *in_set;    // diag: requested rows (null: all)
+    double *dacc;             // diag: gather sums
 };
 
 inline WalkArgs to_args(const WalkParams &p) {
@@ -60,6 +63,9 @@ inline WalkArgs to_args(const WalkParams &p) {
     a.cutoff = p.cutoff;
     a.row_walks = p.row_walks;
     a.row_rec = p.row_rec;
+    a.hub_act = p.hub_act;
+    a.in_set = p.in_set;
+    a.dacc = p.dacc;
     return a;
 }
 
@@ -70,6 +76,8 @@ struct GraphView {
     const double *val;
     const double *rowabs;
     const double *cum;
+    const uint32_t *hubmask; // per node: adjacent hubs (null: no hubs)
+    const int32_t *hub_row;  // hub index -> row
 };
 
 inline GraphView view(const mcmf_graph *g) {
@@ -80,12 +88,15 @@ inline GraphView view(const mcmf_graph *g) {
     v.val = g->val;
     v.rowabs = g->rowabs;
     v.cum = g->cum;
+    v.hubmask = g->hubmask;
+    v.hub_row = g->hub_rows;
     return v;
 }
 
-// Walk state of one walk: row, its record, weight.
+// Walk state of one walk: row, its record and (EDGE records only) the mask
+// of hubs adjacent to the row.
 struct Pos {
-    uint32_t l, start, deg;
+    uint32_t l, start, deg, hm;
 };
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -130,11 +141,13 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
             n.l = e.x;
             n.start = e.y;
             n.deg = e.z;
+            n.hm = e.w;
         } else {
             n.l = static_cast<uint32_t>(load_col<STREAM>(g.col + (int64_t(p.start) + j)));
             const uint2 r = g.node[n.l];
             n.start = r.x;
             n.deg = r.y;
+            n.hm = 0u;
         }
     } else {
         const double ra = g.rowabs[p.l];
@@ -146,6 +159,7 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
         const uint2 r = g.node[n.l];
         n.start = r.x;
         n.deg = r.y;
+        n.hm = 0u;
     }
     return n;
 }
@@ -159,7 +173,7 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
                                               const WalkArgs &a, uint32_t k, uint2 rk, double r_k,
                                               uint32_t w, uint64_t *h, unsigned long long *nsteps) {
     const int last = a.K - 2;
-    Pos p{k, rk.x, rk.y};
+    Pos p{k, rk.x, rk.y, 0u};
     double rl = r_k;
     WT W = WT(1);
     double wacc = 0.0;
@@ -188,14 +202,19 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
 }
 
 // One diagonal walk: writes (l_t, c_{t+2} W_t) to vstate[t*stride],
-// vx[t*stride] for t = 0..K-2 (state -1 once the walk has ended).
+// vx[t*stride] for t = 0..K-2 (state -1 once the walk has ended).  With
+// hub_k != 0 (unweighted graphs; the hubs adjacent to k whose sums this
+// walk feeds) each recorded weight is also added to hsum[h] (LDS) for every
+// hub h in hub_k adjacent to l_t: the walk's share of <Q_k, C_h>.
 template <class WT, bool WEIGHTED, bool DIGEST, bool CUTOFF, bool EDGE = true, bool STREAM = false>
 __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a, uint32_t k,
                                           uint2 rk, uint32_t w, int32_t *__restrict__ vstate,
                                           WT *__restrict__ vx, int64_t stride, uint64_t *h,
-                                          unsigned long long *nsteps) {
+                                          unsigned long long *nsteps, uint32_t hub_k = 0u,
+                                          double *hsum = nullptr) {
     const int last = a.K - 2;
-    Pos p{k, rk.x, rk.y};
+    // k itself is adjacent to every hub in hub_k.
+    Pos p{k, rk.x, rk.y, hub_k};
     WT W = WT(1);
     int t = 0;
     for (; t <= last; ++t) {
@@ -209,8 +228,18 @@ __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a,
                                                a.key0, a.key1);
             nxt = step<WEIGHTED, WT, STREAM, EDGE>(g, p, x, a.scale, Wn);
         }
+        const WT xt = static_cast<WT>(a.coef[t]) * W;
         vstate[int64_t(t) * stride] = static_cast<int32_t>(p.l);
-        vx[int64_t(t) * stride] = static_cast<WT>(a.coef[t]) * W;
+        vx[int64_t(t) * stride] = xt;
+        if constexpr (!WEIGHTED) {
+            if (hub_k != 0u) {
+                uint32_t m = ((EDGE || t == 0) ? p.hm : g.hubmask[p.l]) & hub_k;
+                while (m != 0u) {
+                    atomicAdd(&hsum[__ffs(m) - 1], static_cast<double>(xt));
+                    m &= m - 1u;
+                }
+            }
+        }
         if (DIGEST)
             *h = dev::fnv_step(*h, p.l);
         ++*nsteps;

@@ -88,13 +88,15 @@ class mcmf_tuning(ctypes.Structure):
     _fields_ = [("action_sampler", ctypes.c_int32), ("action_stream", ctypes.c_int32),
                 ("diag_sampler", ctypes.c_int32), ("diag_stream", ctypes.c_int32),
                 ("action_ms", ctypes.c_double * 4), ("diag_ms", ctypes.c_double * 4),
-                ("sample_rows", ctypes.c_int64), ("reserved", ctypes.c_uint32 * 6)]
+                ("sample_rows", ctypes.c_int64), ("hub_min_degree", ctypes.c_int32),
+                ("hub_count", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
                 "diag_sampler": self.diag_sampler, "diag_stream": self.diag_stream,
                 "action_ms": list(self.action_ms), "diag_ms": list(self.diag_ms),
-                "sample_rows": self.sample_rows}
+                "sample_rows": self.sample_rows, "hub_min_degree": self.hub_min_degree,
+                "hub_count": self.hub_count}
 
 
 MCMF_REQ_DIAG = 0

@@ -38,7 +38,8 @@ def autotune(graph, csr, fn: M.mcmf_fn, n_walks: int, K: int, cache_path: str) -
     cache = _load(cache_path)
     if key in cache:
         d = cache[key]
-        t = M.mcmf_tuning()
+        t = M.mcmf_graph_get_tuning(graph.handle)  # keeps the graph's other settings
+        t.hub_count = 0
         for name in ("action_sampler", "action_stream", "diag_sampler", "diag_stream"):
             setattr(t, name, int(d[name]))
         M.mcmf_graph_set_tuning(graph.handle, t)

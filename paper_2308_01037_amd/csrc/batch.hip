@@ -56,7 +56,8 @@ struct BReq {
     const uint32_t *hubmask;   // diag: the graph's hub masks
     const uint8_t *hub_of;
     const int32_t *hub_row;
-    uint32_t hub_act;          // diag: hubs summed by the hub pass
+    uint32_t hub_act;          // diag: hubs left out of the gather's probes
+    int32_t hub_pass;          // diag: 1 = the gather sums them (else the walks, a.hub_act)
 };
 
 // A run of one request's start rows inside a walk launch.  A task is one
@@ -91,7 +92,8 @@ constexpr int64_t kRowTaskWalks = 128; // N at or above which a task is one row
 template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
 __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t rel, uint32_t k, uint2 rk,
                                          int64_t w, int32_t *vstate, unsigned char *vxb, double &acc,
-                                         uint64_t &h, unsigned long long &ns) {
+                                         uint64_t &h, unsigned long long &ns, uint32_t hub_k = 0u,
+                                         double *hsum = nullptr) {
     const int64_t N = R.a.N;
     if (R.kind == MCMF_REQ_ACTION) {
         acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF>(R.g, R.r, R.a, k, rk, R.r[k],
@@ -101,7 +103,7 @@ __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t 
         WT *vx = reinterpret_cast<WT *>(vxb + sg.xoff) + rel * span;
         walk::diag_walk<WT, WEIGHTED, DIGEST, CUTOFF>(R.g, R.a, k, rk, static_cast<uint32_t>(w),
                                                        vstate + sg.slot_base + rel * span + w, vx + w, N,
-                                                       &h, &ns);
+                                                       &h, &ns, hub_k, hsum);
     }
 }
 
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
                                                              unsigned long long *queue) {
     __shared__ double red[kWalkThreads / 64];
     __shared__ unsigned long long redu[kWalkThreads / 64];
+    __shared__ double hsum[kMaxHubs];
     __shared__ int64_t task_slot;
     const int tid = threadIdx.x;
     // Tasks come from a queue counter in order, so the rows in flight stay a
@@ -146,12 +149,39 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
             const int64_t rel = local;
             const uint32_t k = static_cast<uint32_t>(dev::uniform(R.starts[sg.kk0 + rel]));
             const uint2 rk = R.g.node[k];
+            // Diagonal requests: requested hubs adjacent to k are summed here.
+            uint32_t hub_k = 0u;
+            if constexpr (!WEIGHTED) {
+                if (R.a.hub_act != 0u) {
+                    hub_k = static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(R.g.hubmask[k]))) &
+                            R.a.hub_act;
+                    if (hub_k != 0u && R.a.in_set) {
+                        const int lane = tid & 63;
+                        const bool keep = lane < kMaxHubs && ((hub_k >> lane) & 1u) &&
+                                          R.a.in_set[R.g.hub_row[lane]];
+                        hub_k = static_cast<uint32_t>(__ballot(keep));
+                    }
+                    if (hub_k != 0u) {
+                        if (tid < kMaxHubs)
+                            hsum[tid] = 0.0;
+                        __syncthreads();
+                    }
+                }
+            }
             double acc = 0.0;
             uint64_t dig = 0;
             for (int64_t w = tid; w < N; w += blockDim.x) {
                 h = dev::kFnvBasis;
-                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns);
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
+                                                       hub_k, hsum);
                 dig += h;
+            }
+            if (hub_k != 0u) {
+                __syncthreads();
+                if (tid < kMaxHubs && ((hub_k >> tid) & 1u) && hsum[tid] != 0.0)
+                    atomicAdd(&R.a.dacc[R.g.hub_row[tid]],
+                              R.a.scale * (R.a.scale * hsum[tid]) * (1.0 / static_cast<double>(N)));
+                __syncthreads();
             }
             if (R.kind == MCMF_REQ_ACTION) {
                 const double total = dev::block_sum(acc, red);
@@ -276,7 +306,7 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         job.hub_of = R.hub_of;
         job.hub_row = R.hub_row;
         job.hub_act = R.hub_act;
-        job.hub_pass = true;
+        job.hub_pass = R.hub_pass != 0;
         gather_row<WEIGHTED, VT>(sh, job, reinterpret_cast<const VT *>(vxb + sg.xoff) + rel * span,
                                  probes);
     }
@@ -477,10 +507,19 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
         if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted) {
+            // Hub rows: summed by the walks when a task is one start row,
+            // else by the gather.
             B.hubmask = q.graph->hubmask;
             B.hub_of = q.graph->hub_of;
             B.hub_row = q.graph->hub_rows;
             B.hub_act = active_hubs(q.graph, q.n_walks, q.K);
+            if (q.n_walks >= kRowTaskWalks) {
+                B.a.hub_act = B.hub_act;
+                B.a.in_set = B.in_set;
+                B.a.dacc = B.dacc;
+            } else {
+                B.hub_pass = 1;
+            }
         }
     }
     DevBuf<unsigned long long> counters; // per request steps, then probes, overflow

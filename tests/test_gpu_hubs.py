@@ -91,20 +91,25 @@ def test_hub_pass_with_several_walk_passes():
         check_same(on, off)
 
 
-def test_fp32_weights_and_batch_use_the_hub_pass():
+@pytest.mark.parametrize("N", [48, 160])
+def test_fp32_weights_and_batch_use_the_hub_pass(N):
+    # N < 128: the batched gather sums the hubs; N >= 128 (one start row per
+    # walk task): the batched walk kernel does.
     csr = G.rmat(12, seed=9)
-    K, N, s = 14, 48, 0.8 / csr.d_max
+    K, s = 14, 0.8 / csr.d_max
+    top = np.argsort(-np.diff(csr.row_ptr), kind="stable")[:32]
+    sel = np.concatenate([G.random_rows(csr.n, 200, seed=4), top[::2]]).astype(np.int32)
     with graph(csr) as g:
+        def reqs():
+            return [Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6),
+                    Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6,
+                        precision=M.MCMF_PRECISION_FP32_WEIGHTS),
+                    Req(g, csr, M.MCMF_REQ_DIAG, "resolvent", s, N, K, seed=7, request=2, rows=sel)]
         hubs(g, OFF)
-        want = Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6).single()
-        want32 = Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6,
-                     precision=M.MCMF_PRECISION_FP32_WEIGHTS).single()
+        want = [q.single() for q in reqs()]
         hubs(g, 1)
-        reqs = [Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6),
-                Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, N, K, seed=6,
-                    precision=M.MCMF_PRECISION_FP32_WEIGHTS)]
-        got, _ = run_batch(reqs)
-        for r, w in zip(got, [want, want32]):
+        got, _ = run_batch(reqs())
+        for r, w in zip(got, want):
             assert np.array_equal(r["digest"], w["digest"])
             assert r["steps"] == w["steps"]
             assert_close(r["x"], w["x"], 1e-10)

@@ -595,11 +595,15 @@ def main():
     alg_total = sum(k["bytes"] for k in kernels.values())
     # Launches of the dominant kernel in the timed region (one per action query;
     # one walk and one gather launch per visit-buffer chunk of a diagonal query).
+    # The library's visit buffer: MCMF_DIAG_CHUNK_BYTES, else 1/32 of device
+    # memory within [256 MiB, 8 GiB].
+    chunk_bytes = int(os.environ.get("MCMF_DIAG_CHUNK_BYTES", "0")) or min(
+        8 << 30, max(256 << 20, torch.cuda.get_device_properties(0).total_memory // 32))
+
     def launches_of(what, st):
         if what == "action":
             return 1
-        per_row = N * (K - 1) * 12
-        rows_per_chunk = max(1, (2 << 30) // per_row)
+        rows_per_chunk = max(1, (chunk_bytes // 12) // (N * (K - 1)))
         return -(-st["start_rows"] // rows_per_chunk)
     launches = sum(launches_of(what, st) for what, _, st, _ in records
                    if (what == "action") == (dominant == "action_walk"))

@@ -278,6 +278,11 @@ mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64
  *   out      double[n_rows] (or [n])
  *   stats    optional
  *
+ * Device memory: the visit records (12 bytes per walk step, 8 with FP32
+ * weights) go through one buffer of at most the MCMF_DIAG_CHUNK_BYTES
+ * environment value, else 1/32 of device memory within [256 MiB, 8 GiB]; a
+ * larger total is walked and gathered in chunks of start rows.
+ *
  * Errors: MCMF_E_ARG (null g/f/out, K out of range, n_walks < 1 with K >= 2,
  * n_rows < 0, a row outside [0, n), non-finite scale or coefficients,
  * n_coeffs < K+1, non-zero reserved words), MCMF_E_NOT_SYMMETRIC,
@@ -342,7 +347,8 @@ typedef struct {
                                    launch that graph (one submission for the batch) */
     int32_t reserved0;          /* must be zero */
     uint64_t visit_chunk_bytes; /* diagonal visit-record buffer of the batch; 0: the
-                                   MCMF_DIAG_CHUNK_BYTES environment value or 2 GiB */
+                                   MCMF_DIAG_CHUNK_BYTES environment value, else 1/32 of
+                                   device memory within [256 MiB, 8 GiB] (as mcmf_diag) */
     uint32_t reserved[4];       /* must be zero */
 } mcmf_batch_opts;
 

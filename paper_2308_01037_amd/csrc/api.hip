@@ -532,9 +532,7 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         // FP32 walk weights).  Chunk boundaries: rows [bounds[i], bounds[i+1]).
         const int64_t per_row = N * (K - 1);
         const int64_t xbytes = p.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
-        int64_t chunk_bytes = int64_t(2) << 30;
-        if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
-            chunk_bytes = std::max<int64_t>(1, strtoll(e, nullptr, 10));
+        const int64_t chunk_bytes = default_visit_chunk_bytes();
         const int64_t chunk_recs = std::max<int64_t>(1, chunk_bytes / (4 + xbytes));
         std::vector<int64_t> bounds(1, 0);
         int64_t most_recs = 0;

@@ -289,8 +289,8 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         const uint2 rk = R.g.node[job.k];
         job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
                             static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
-        job.p_begin = part * kBatch;
-        job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
+        job.p_begin = part * kItem;
+        job.p_end = job.rk.y - job.p_begin < kItem ? job.rk.y : job.p_begin + kItem;
         job.st = vstate + sg.slot_base + rel * span;
         job.N = R.a.N;
         job.K = R.a.K;
@@ -554,9 +554,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     // chunks = diag rows only.  Each chunk holds at most `budget` bytes of
     // visit records.  Walk runs are kept per walk-kernel variant, gather runs
     // per (gather variant, table size): one launch each.
-    int64_t budget = int64_t(2) << 30;
-    if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
-        budget = std::max<int64_t>(1, strtoll(e, nullptr, 10));
+    int64_t budget = default_visit_chunk_bytes();
     if (o && o->visit_chunk_bytes)
         budget = static_cast<int64_t>(std::min<uint64_t>(o->visit_chunk_bytes, uint64_t(1) << 62));
     struct GatherGroup {

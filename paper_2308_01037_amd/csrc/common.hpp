@@ -122,6 +122,11 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c);
 
 int num_cus();
 
+// Default size of a call's diagonal visit-record buffer: the
+// MCMF_DIAG_CHUNK_BYTES environment value, else 1/32 of device memory
+// clamped to [256 MiB, 8 GiB] (fewer, larger chunks mean fewer launch tails).
+int64_t default_visit_chunk_bytes();
+
 // Hub rows of the diagonal gather: at most one per bit of a 32-bit mask.
 constexpr int kMaxHubs = 32;
 constexpr uint8_t kNoHub = 0xFF;

@@ -118,8 +118,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
         const uint2 rk = a.node[job.k];
         job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
                             static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
-        job.p_begin = part * kBatch;
-        job.p_end = job.rk.y - job.p_begin < uint32_t(kBatch) ? job.rk.y : job.p_begin + kBatch;
+        job.p_begin = part * kItem;
+        job.p_end = job.rk.y - job.p_begin < kItem ? job.rk.y : job.p_begin + kItem;
         int64_t rec = (kk - a.row_begin) * span;
         if (a.row_walks) {
             job.N = dev::uniform(static_cast<int64_t>(a.row_walks[kk]));

@@ -1,5 +1,6 @@
 // Error state, device-memory accounting, pointer classification and the
 // function-coefficient tables.
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -291,6 +292,20 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c) {
     default:
         return fail(MCMF_E_ARG, "unknown function kind %d", f->kind);
     }
+}
+
+int64_t default_visit_chunk_bytes() {
+    if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
+        return std::max<int64_t>(1, strtoll(e, nullptr, 10));
+    static int64_t bytes = [] {
+        size_t free_b = 0, total_b = 0;
+        if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+            (void)hipGetLastError();
+            return int64_t(2) << 30;
+        }
+        return std::min<int64_t>(int64_t(8) << 30, std::max<int64_t>(int64_t(256) << 20, int64_t(total_b / 32)));
+    }();
+    return bytes;
 }
 
 int num_cus() {

@@ -8,7 +8,8 @@
   the resolvent with gamma = 0.85/lambda_max, K = 40, N = 256.  Sampled
   output rows are recomputed by the oracle (it replays only the walks those
   rows need) and must match to 1e-10 with bit-exact path digests; every
-  output must also satisfy x >= h (all terms are non-negative).
+  output must also satisfy x >= h (all terms are non-negative).  The sample
+  includes a hub row, whose diagonal the walk kernel sums.
 """
 import numpy as np
 import pytest
@@ -71,6 +72,10 @@ def _sample_rows(csr, seed):
         rows.append(int(rng.choice(mid)))
     iso = np.nonzero(deg == 0)[0]
     rows.append(int(iso[0]))
+    # The smallest of the 32 hub rows: its diagonal is summed by the walks
+    # (one mask test per visit) instead of probed.
+    top = np.lexsort((np.arange(csr.n), -deg))[:32]
+    rows.append(int(top[-1]))
     return np.array(rows, dtype=np.int32)
 
 

@@ -605,9 +605,17 @@ def main():
             return 1
         rows_per_chunk = max(1, (chunk_bytes // 12) // (N * (K - 1)))
         return -(-st["start_rows"] // rows_per_chunk)
-    launches = sum(launches_of(what, st) for what, _, st, _ in records
-                   if (what == "action") == (dominant == "action_walk"))
+    def launches_of_kernel(kind):
+        return sum(launches_of(what, st) for what, _, st, _ in records
+                   if (what == "action") == (kind == "action_walk"))
+    launches = launches_of_kernel(dominant)
     traffic = load_traffic(dominant)
+    # Fabric bytes per launch from the committed counters (while the sources
+    # match), over this run's time per launch: the walks' real traffic.
+    for kind, k in kernels.items():
+        t = load_traffic(kind)
+        n_l = launches_of_kernel(kind)
+        k["gbs_counter"] = t / (k["ms"] / n_l * 1e-3) / 1e9 if t and n_l and k["ms"] > 0 else None
     if args.copy_probe_bytes:
         src = torch.ones(args.copy_probe_bytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -648,7 +656,8 @@ def main():
         "queries_per_s": len(records) / elapsed,
         "query_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "hbm_gbs_algorithmic": alg_total / elapsed / 1e9,
-        "kernels": {k: {"ms_per_step": v_["ms"] / args.steps, "gbs_algorithmic": v_["gbs"]}
+        "kernels": {k: {"ms_per_step": v_["ms"] / args.steps, "gbs_algorithmic": v_["gbs"],
+                        "gbs_counter": v_["gbs_counter"]}
                     for k, v_ in kernels.items()},
         "roofline": {
             "kernel": dominant,

@@ -142,3 +142,49 @@ def test_hub_threshold_argument_error():
         with pytest.raises(M.MCMFError) as e:
             M.mcmf_graph_set_tuning(g.handle, t)
         assert e.value.status == M.MCMF_E_ARG
+
+
+def test_hub_pass_closed_form_complete_bipartite():
+    # K_{p,q}: the diagonal is the closed form on every walk, so the hub sums
+    # (all 5 rows of the small side are hubs, plus 27 rows of the other side)
+    # must give it to rounding.
+    p, q, K, s = 5, 300, 10, 0.9 / 300
+    csr = G.complete_bipartite(p, q)
+    c = oracle.coeffs(oracle.FN_EXP, K)
+
+    def closed(own, other):
+        return c[0] + sum(c[2 * m] * s ** (2 * m) * own * (own * other) ** (m - 1)
+                          for m in range(1, K // 2 + 1))
+    want = np.array([closed(q, p)] * p + [closed(p, q)] * q)
+    with graph(csr) as g:
+        assert hubs(g, 1) == 32
+        on, off = both(g, "exp", 16, K, s, seed=3)
+        check_same(on, off)
+        assert on["stats"]["gather_probes"] < off["stats"]["gather_probes"]
+    assert_close(on["d"], want, 1e-12, what="K_pq closed form with hub sums")
+
+
+def test_hub_rows_with_self_loops_and_digraph():
+    # Self-loops on hub rows (a hub adjacent to itself) and the symmetrised
+    # digraph B = [[0, A], [A^T, 0]], whose hubs are rows of both halves.
+    rng = np.random.default_rng(8)
+    n = 600
+    src = np.concatenate([rng.integers(0, n, 6000), np.zeros(300, np.int64), np.arange(0, 40)])
+    dst = np.concatenate([rng.integers(0, n, 6000), rng.integers(0, n, 300), np.arange(0, 40)])
+    csr = G.from_edges(n, src, dst, keep_loops=True)
+    with graph(csr) as g:
+        assert hubs(g, 1) == 32
+        on, off = both(g, "resolvent", 24, 9, 0.5 / csr.d_max, seed=4)
+        check_same(on, off)
+        o = oracle.diag(csr, oracle_fn("resolvent"), N=24, K=9, scale=0.5 / csr.d_max, seed=4)
+        assert_close(on["d"], o["d"], 1e-10, what="loops vs oracle")
+    dg = G.from_edges(n, src, dst, symmetric=False)
+    h = M.mcmf_graph_create(dg.n, dg.row_ptr.astype(np.int64), dg.col.astype(np.int32), None,
+                            M.MCMF_DIGRAPH)
+    g = M.Graph(h)
+    try:
+        assert hubs(g, 1) == 32
+        on, off = both(g, "exp", 20, 8, 0.5 / g.info["d_max"], seed=6)
+        check_same(on, off)
+    finally:
+        g.close()

@@ -223,7 +223,8 @@ typedef struct {
     int32_t hub_min_degree;  /* diagonal gather (unweighted graphs): a hub row (below) of at
                                 least this many entries is summed by the hub pass instead of
                                 being probed entry by entry; 0 = automatic, a degree of at
-                                least n_walks (K - 1) / 4; INT32_MAX turns the pass off */
+                                least n_walks (K - 1) / 4; INT32_MAX turns the pass off.
+                                Batched requests with n_walks < 32 never use it */
     int32_t hub_count;       /* out of mcmf_graph_get_tuning: hub rows the graph holds;
                                 ignored on input */
     uint32_t reserved[4];    /* must be zero on input */

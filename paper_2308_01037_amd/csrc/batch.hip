@@ -53,11 +53,8 @@ struct BReq {
     double *dacc;              // diag sums
     const int64_t *item_off;   // diag: gather work items of the start list
     int64_t wpp;               // walks per gather pass
-    const uint32_t *hubmask;   // diag: the graph's hub masks
-    const uint8_t *hub_of;
-    const int32_t *hub_row;
-    uint32_t hub_act;          // diag: hubs left out of the gather's probes
-    int32_t hub_pass;          // diag: 1 = the gather sums them (else the walks, a.hub_act)
+    const uint8_t *hub_of;     // diag: hub index per node
+    uint32_t hub_act;          // diag: hubs the walks sum (a.hub_act), left out of the probes
 };
 
 // A run of one request's start rows inside a walk launch.  A task is one
@@ -88,6 +85,8 @@ struct GSeg {
 };
 
 constexpr int64_t kRowTaskWalks = 128; // N at or above which a task is one row
+constexpr int64_t kHubMinWalks = 32;   // packed tasks hold at most 256/32 rows of hub sums
+constexpr int kHubRows = kWalkThreads / kHubMinWalks;
 
 template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
 __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t rel, uint32_t k, uint2 rk,
@@ -115,7 +114,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
                                                              unsigned long long *queue) {
     __shared__ double red[kWalkThreads / 64];
     __shared__ unsigned long long redu[kWalkThreads / 64];
-    __shared__ double hsum[kMaxHubs];
+    __shared__ double hsum[kHubRows * kMaxHubs]; // per row of the task, per hub
     __shared__ int64_t task_slot;
     const int tid = threadIdx.x;
     // Tasks come from a queue counter in order, so the rows in flight stay a
@@ -195,18 +194,53 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
             }
         } else {
             // Several rows, one walk per thread.
-            const int64_t rel = local * sg.rows_per_task + tid / N;
+            const int slot = tid / static_cast<int>(N);
+            const int64_t rel = local * sg.rows_per_task + slot;
             const int64_t w = tid % N;
-            if (tid < int64_t(sg.rows_per_task) * N && rel < sg.rows) {
+            const bool mine = tid < int64_t(sg.rows_per_task) * N && rel < sg.rows;
+            // Diagonal requests with N >= kHubMinWalks: each row's requested
+            // hubs are summed into its own slice of hsum.
+            uint32_t hub_k = 0u;
+            if constexpr (!WEIGHTED) {
+                if (R.a.hub_act != 0u) {
+                    if (mine) {
+                        hub_k = R.g.hubmask[R.starts[sg.kk0 + rel]] & R.a.hub_act;
+                        if (R.a.in_set) {
+                            for (uint32_t m = hub_k; m != 0u; m &= m - 1u) {
+                                const int b = __ffs(m) - 1;
+                                if (!R.a.in_set[R.g.hub_row[b]])
+                                    hub_k &= ~(1u << b);
+                            }
+                        }
+                    }
+                    for (int i = tid; i < kHubRows * kMaxHubs; i += blockDim.x)
+                        hsum[i] = 0.0;
+                    __syncthreads();
+                }
+            }
+            if (mine) {
                 const uint32_t k = static_cast<uint32_t>(R.starts[sg.kk0 + rel]);
                 const uint2 rk = R.g.node[k];
                 double acc = 0.0;
-                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns);
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
+                                                       hub_k, hsum + slot * kMaxHubs);
                 if (R.kind == MCMF_REQ_ACTION && acc != 0.0)
                     atomicAdd(&R.q[k], acc / static_cast<double>(N));
                 if (DIGEST)
                     atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]),
                               static_cast<unsigned long long>(h));
+            }
+            if constexpr (!WEIGHTED) {
+                if (R.a.hub_act != 0u) {
+                    // Only bits of a row's hub_k were summed: a non-zero entry
+                    // is a requested hub adjacent to that row.
+                    __syncthreads();
+                    for (int i = tid; i < kHubRows * kMaxHubs; i += blockDim.x)
+                        if (hsum[i] != 0.0)
+                            atomicAdd(&R.a.dacc[R.g.hub_row[i % kMaxHubs]],
+                                      R.a.scale * (R.a.scale * hsum[i]) * (1.0 / static_cast<double>(N)));
+                    __syncthreads();
+                }
             }
         }
         const unsigned long long st = dev::block_sum(ns, redu);
@@ -302,11 +336,8 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         job.scale = R.a.scale;
         job.dacc = R.dacc;
         job.overflow = probes_out + 1;
-        job.hubmask = R.hubmask;
         job.hub_of = R.hub_of;
-        job.hub_row = R.hub_row;
         job.hub_act = R.hub_act;
-        job.hub_pass = R.hub_pass != 0;
         gather_row<WEIGHTED, VT>(sh, job, reinterpret_cast<const VT *>(vxb + sg.xoff) + rel * span,
                                  probes);
     }
@@ -506,20 +537,13 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.in_set = P.all ? nullptr : P.in_set.ptr;
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
-        if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted) {
-            // Hub rows: summed by the walks when a task is one start row,
-            // else by the gather.
-            B.hubmask = q.graph->hubmask;
+        if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kHubMinWalks) {
+            // Hub rows: the walks sum them, the gather leaves them out.
             B.hub_of = q.graph->hub_of;
-            B.hub_row = q.graph->hub_rows;
             B.hub_act = active_hubs(q.graph, q.n_walks, q.K);
-            if (q.n_walks >= kRowTaskWalks) {
-                B.a.hub_act = B.hub_act;
-                B.a.in_set = B.in_set;
-                B.a.dacc = B.dacc;
-            } else {
-                B.hub_pass = 1;
-            }
+            B.a.hub_act = B.hub_act;
+            B.a.in_set = B.in_set;
+            B.a.dacc = B.dacc;
         }
     }
     DevBuf<unsigned long long> counters; // per request steps, then probes, overflow

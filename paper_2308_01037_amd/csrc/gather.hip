@@ -74,10 +74,8 @@ struct GatherArgs {
     unsigned long long *probes;
     unsigned long long *overflow; // set if a table ever fills (a planning error)
     unsigned long long *queue;
-    const uint32_t *hubmask;
     const uint8_t *hub_of;
-    const int32_t *hub_row;
-    uint32_t hub_act;
+    uint32_t hub_act; // hubs the walks summed: left out of the probes
 };
 
 template <bool WEIGHTED, class VT>
@@ -103,11 +101,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.scale = a.scale;
     job.dacc = a.dacc;
     job.overflow = a.overflow;
-    job.hubmask = a.hubmask;
     job.hub_of = a.hub_of;
-    job.hub_row = a.hub_row;
     job.hub_act = a.hub_act;
-    job.hub_pass = false; // the walk kernel summed the hubs
     for (;;) {
         const int64_t item = dev::uniform(first + next_item(a.queue, &item_slot));
         if (item >= last)
@@ -179,9 +174,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.dacc = dacc;
     a.probes = probes;
     a.queue = queue;
-    a.hubmask = g->hubmask;
     a.hub_of = g->hub_of;
-    a.hub_row = g->hub_rows;
     a.hub_act = p.hub_act;
     const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - kStaticLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);

@@ -14,18 +14,12 @@
 //     total; after the batch each neighbour's total goes out with one FP64
 //     atomic:   dacc[i] += s a_ki * s <Q_k, C_i> / N.
 //  3. Hub rows (unweighted graphs): for a neighbour h of k among the graph's
-//     hubs (its highest-degree rows), <Q_k, C_h> is the sum of the visit
-//     weights at states adjacent to h.  Every item leaves those neighbours
-//     out of step 2; the sums come either from the walk kernel (which sees
-//     each state's hub mask in the edge record it loads anyway) or, with
-//     hub_pass, from the first item of the row, which reads the per-node
-//     mask of each visit while inserting it (step 1).  Either replaces
-//     deg(h) probes per such pair by work per visit.
+//     active hubs (its highest-degree rows), <Q_k, C_h> is summed by the walk
+//     kernel instead (it sees each state's hub mask in the edge record it
+//     loads anyway); every item leaves those neighbours out of step 2.
 //  When the row's visits cannot fit the table at once, the walks are taken
 //  in passes (Q_k is linear in the walks) and the gather repeats per pass.
 #pragma once
-
-#include <type_traits>
 
 #include "device.hpp"
 #include "ops.hpp"
@@ -45,7 +39,6 @@ constexpr int kPerLane = 8;                // entries per lane per chunk
 constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
 constexpr int kGroups = kGatherThreads / kGroup;
 constexpr int kSlots = 8;                  // slots per bucket
-constexpr int kVisits = 4;                 // visit records per thread in flight (table build)
 constexpr int32_t kEmpty = -1;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
@@ -251,36 +244,9 @@ struct RowJob {
     double scale;
     double *dacc;
     unsigned long long *overflow;
-    const uint32_t *hubmask; // per node: the hubs it is adjacent to
     const uint8_t *hub_of;   // per node: its hub index, or kNoHub
-    const int32_t *hub_row;  // hub index -> row
-    uint32_t hub_act;        // hubs summed outside the probes (0: none)
-    bool hub_pass;           // true: this gather sums them; false: the walks did
+    uint32_t hub_act;        // hubs summed by the walks, not probed here (0: none)
 };
-
-// The lowest four set bits of *rest, one bit per entry (0 when none is
-// left), removed from *rest.
-__device__ __forceinline__ void take_hubs(uint32_t *rest, uint32_t (&hb)[4]) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        hb[u] = *rest & (0u - *rest);
-        *rest &= *rest - 1u;
-    }
-}
-
-// dacc[hub] += s * s * <Q_k, C_hub> / N for each hub bit in hb, from the
-// per-thread partial sums h (workgroup-wide reductions).
-__device__ __forceinline__ void flush_hubs(const RowJob &j, const uint32_t (&hb)[4], const double (&h)[4],
-                                           double inv_n, unsigned long long *red) {
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        if (hb[u] == 0u)
-            break;
-        const double tot = dev::block_sum(h[u], reinterpret_cast<double *>(red));
-        if (threadIdx.x == 0 && tot != 0.0)
-            atomicAdd(&j.dacc[j.hub_row[__ffs(hb[u]) - 1]], j.scale * (j.scale * tot) * inv_n);
-    }
-}
 
 // Runs the job with all threads of the workgroup (kGatherThreads).
 template <bool WEIGHTED, class VT>
@@ -295,18 +261,6 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
     const int32_t k = j.k;
     const uint2 rk = j.rk;
     const int32_t *st = j.st;
-    // Requested active hubs adjacent to k (first item of the row only).
-    uint32_t hub_k = 0u;
-    if constexpr (!WEIGHTED) {
-        if (j.hub_act != 0u && j.hub_pass && j.p_begin == 0) {
-            hub_k = static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(j.hubmask[k]))) & j.hub_act;
-            if (hub_k != 0u && j.in_set) {
-                const int lane = threadIdx.x & 63;
-                const bool keep = lane < kMaxHubs && ((hub_k >> lane) & 1u) && j.in_set[j.hub_row[lane]];
-                hub_k = static_cast<uint32_t>(__ballot(keep));
-            }
-        }
-    }
     for (int64_t w0 = 0; w0 < j.N; w0 += j.walks_per_pass) {
         const int64_t nw = (j.N - w0 < j.walks_per_pass) ? (j.N - w0) : j.walks_per_pass;
         // (1) Q_k from walks [w0, w0 + nw).
@@ -319,57 +273,6 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             tab.filter[i] = 0u;
         __syncthreads();
         const int64_t count = nw * (j.K - 1);
-        // Visit i of this pass -> its record (t-major: t * N + w).
-        auto slot_of = [&](int64_t i) -> int64_t {
-            const int64_t t = i / nw;
-            return t * j.N + w0 + (i - t * nw);
-        };
-        // The first four hubs ride along with the inserts.
-        uint32_t rest = hub_k;
-        uint32_t hb[4];
-        take_hubs(&rest, hb);
-        double h[4] = {0.0, 0.0, 0.0, 0.0};
-        // Visits [first, count) of the pass, kVisits per thread at a time: the
-        // record loads (and mask loads) of a group are issued together before
-        // its inserts.  INSERT: add to the table (else hub sums only).
-        auto sweep = [&](int64_t first, auto insert_tag, auto &&slot) {
-            constexpr bool INSERT = decltype(insert_tag)::value;
-            const bool hubs = !WEIGHTED && hb[0] != 0u;
-            for (int64_t i0 = first + threadIdx.x; i0 < count; i0 += kVisits * int64_t(blockDim.x)) {
-                int32_t sv[kVisits];
-                double xv[kVisits];
-                uint32_t mv[kVisits];
-#pragma unroll
-                for (int u = 0; u < kVisits; ++u) {
-                    const int64_t i = i0 + int64_t(u) * blockDim.x;
-                    const int64_t at = i < count ? slot(i) : 0;
-                    sv[u] = i < count ? st[at] : -1;
-                    xv[u] = i < count ? static_cast<double>(xs[at]) : 0.0;
-                }
-                if (hubs) {
-#pragma unroll
-                    for (int u = 0; u < kVisits; ++u)
-                        mv[u] = sv[u] >= 0 ? j.hubmask[sv[u]] : 0u;
-                }
-#pragma unroll
-                for (int u = 0; u < kVisits; ++u) {
-                    if (sv[u] < 0)
-                        continue;
-                    if constexpr (INSERT) {
-                        if (!tab.insert(sv[u], xv[u]))
-                            atomicAdd(j.overflow, 1ull);
-                    }
-                    if (hubs) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            h[v] += (mv[u] & hb[v]) ? xv[u] : 0.0;
-                    }
-                }
-            }
-        };
-        auto same = [](int64_t i) { return i; };
-        const std::true_type with_insert;
-        const std::false_type hubs_only;
         if (nw == j.N) {
             // Step 0 of every walk sits at k: insert the sum of those visits once
             // instead of N colliding atomic updates of one slot.
@@ -379,35 +282,18 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
             if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
                 atomicAdd(j.overflow, 1ull);
-            // k is adjacent to every hub in hub_k.
-            if (threadIdx.x == 0) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    h[u] = hb[u] != 0u ? x0 : 0.0;
+            for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
+                const int32_t s = st[i];
+                if (s >= 0 && !tab.insert(s, static_cast<double>(xs[i])))
+                    atomicAdd(j.overflow, 1ull);
             }
-            sweep(nw, with_insert, same);
         } else {
-            sweep(0, with_insert, slot_of);
-        }
-        if constexpr (!WEIGHTED) {
-            if (hb[0] != 0u) {
-                flush_hubs(j, hb, h, inv_n, red);
-                if (threadIdx.x == 0)
-                    probes += static_cast<unsigned long long>(count);
-                // Further hubs, four per sweep over the visits.
-                while (rest != 0u) {
-                    take_hubs(&rest, hb);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        h[u] = 0.0;
-                    if (nw == j.N)
-                        sweep(0, hubs_only, same);
-                    else
-                        sweep(0, hubs_only, slot_of);
-                    flush_hubs(j, hb, h, inv_n, red);
-                    if (threadIdx.x == 0)
-                        probes += static_cast<unsigned long long>(count);
-                }
+            for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
+                const int64_t t = i / nw;
+                const int64_t slot = t * j.N + w0 + (i - t * nw);
+                const int32_t s = st[slot];
+                if (s >= 0 && !tab.insert(s, static_cast<double>(xs[slot])))
+                    atomicAdd(j.overflow, 1ull);
             }
         }
         // (2) columns of the requested neighbours, kBatch neighbours at a time.
@@ -425,7 +311,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                     const int32_t i = j.col[e];
                     bool take = !j.in_set || j.in_set[i];
                     if constexpr (!WEIGHTED) {
-                        // Active hubs are summed by the hub pass instead.
+                        // Active hubs are summed by the walks instead.
                         if (take && j.hub_act != 0u) {
                             const uint32_t hx = j.hub_of[i];
                             take = hx == kNoHub || ((j.hub_act >> hx) & 1u) == 0u;

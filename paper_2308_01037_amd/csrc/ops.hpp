@@ -13,9 +13,11 @@ Status fill_i32(int32_t *out, int32_t value, int64_t n, hipStream_t s);
 Status fill_f64(double *out, double value, int64_t n, hipStream_t s);
 Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s);
 
-// Mask of the graph's hubs that the diagonal gather sums by the hub pass for
-// n_walks walks per start row and K (the tuning's hub_min_degree, or by
-// default hubs of degree >= n_walks (K - 1) / 4); 0 without hubs.
+// Mask of the graph's hubs whose sums (by the walk kernel) replace the
+// gather's probes for n_walks walks per start row and K: hubs of degree >=
+// the tuning's hub_min_degree, by default >= n_walks (K - 1) / 4 (the walk
+// adds a few operations per visit; a hub saves one probe per entry of its
+// row per adjacent start row); 0 without hubs.
 uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K);
 
 // Ascending indices i < n with flags[i] == match written to out; *count (host)

@@ -91,10 +91,10 @@ def test_hub_pass_with_several_walk_passes():
         check_same(on, off)
 
 
-@pytest.mark.parametrize("N", [48, 160])
+@pytest.mark.parametrize("N", [16, 48, 160])
 def test_fp32_weights_and_batch_use_the_hub_pass(N):
-    # N < 128: the batched gather sums the hubs; N >= 128 (one start row per
-    # walk task): the batched walk kernel does.
+    # Batched walk tasks: N >= 128 one start row per task, 32 <= N < 128
+    # several rows each with its own hub sums, N < 32 no hub sums at all.
     csr = G.rmat(12, seed=9)
     K, s = 14, 0.8 / csr.d_max
     top = np.argsort(-np.diff(csr.row_ptr), kind="stable")[:32]

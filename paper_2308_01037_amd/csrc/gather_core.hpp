@@ -39,6 +39,7 @@ constexpr int kPerLane = 8;                // entries per lane per chunk
 constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
 constexpr int kGroups = kGatherThreads / kGroup;
 constexpr int kSlots = 8;                  // slots per bucket
+constexpr int kVisits = 4;                 // visit records per thread in flight (table build)
 constexpr int32_t kEmpty = -1;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
@@ -282,10 +283,21 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
             if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
                 atomicAdd(j.overflow, 1ull);
-            for (int64_t i = nw + threadIdx.x; i < count; i += blockDim.x) {
-                const int32_t s = st[i];
-                if (s >= 0 && !tab.insert(s, static_cast<double>(xs[i])))
-                    atomicAdd(j.overflow, 1ull);
+            // kVisits records per thread: their loads are issued together
+            // before the inserts.
+            for (int64_t i0 = nw + threadIdx.x; i0 < count; i0 += kVisits * int64_t(blockDim.x)) {
+                int32_t sv[kVisits];
+                double xv[kVisits];
+#pragma unroll
+                for (int u = 0; u < kVisits; ++u) {
+                    const int64_t i = i0 + int64_t(u) * blockDim.x;
+                    sv[u] = i < count ? st[i] : -1;
+                    xv[u] = i < count ? static_cast<double>(xs[i]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kVisits; ++u)
+                    if (sv[u] >= 0 && !tab.insert(sv[u], xv[u]))
+                        atomicAdd(j.overflow, 1ull);
             }
         } else {
             for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {

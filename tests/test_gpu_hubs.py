@@ -69,8 +69,8 @@ def test_hub_pass_matches_probes_and_oracle(rows, fn):
 
 
 def test_automatic_threshold_and_more_than_four_hubs_per_row():
-    # A dense core: rows adjacent to many hubs take several sweeps (four
-    # hubs per sweep) over their visits.
+    # A dense core: many rows are adjacent to most of the 32 hubs, so a walk
+    # adds each visit into several hub sums.
     csr = G.rmat(11, edge_factor=64, seed=3)
     K, N, s = 10, 64, 0.5 / csr.d_max
     with graph(csr) as g:

@@ -139,12 +139,13 @@ struct Table {
         return 0.0;
     }
 
-    // Lookup of N keys stage by stage so that their LDS reads overlap: all
-    // filter words, then the home buckets and values in two halves (to bound
-    // register use), then the rare keys that need further buckets.
-    // key < 0 means "no key" (result 0).
-    template <int N>
-    __device__ __forceinline__ void lookup_n(const int32_t (&key)[N], double (&out)[N]) const {
+    // acc + sum_u w[u] Q[key[u]] (w[u] = 1 unweighted) over N keys, looked up
+    // stage by stage so that their LDS reads overlap: all filter words, then
+    // the home buckets and values in two halves (to bound register use), then
+    // the rare keys that need further buckets.  key < 0 means "no key".
+    template <int N, bool WEIGHTED>
+    __device__ __forceinline__ double lookup_sum(const int32_t (&key)[N], const double (&w)[N],
+                                                 double acc) const {
         static_assert(N % 2 == 0, "N must be even");
         constexpr int H = N / 2;
         uint32_t fw[N], m[N];
@@ -187,8 +188,10 @@ struct Table {
             for (int v = 0; v < H; ++v)
                 got[v] = vals[slot[v] >= 0 ? kSlots * b[v] + slot[v] : 0u];
 #pragma unroll
-            for (int v = 0; v < H; ++v)
-                out[half * H + v] = slot[v] >= 0 ? got[v] : 0.0;
+            for (int v = 0; v < H; ++v) {
+                const double q = slot[v] >= 0 ? got[v] : 0.0;
+                acc += WEIGHTED ? w[half * H + v] * q : q;
+            }
         }
         while (pending) {
             const int u = __ffs(pending) - 1;
@@ -204,10 +207,17 @@ struct Table {
                 bx = (bx + 1 == nb) ? 0 : bx + 1;
                 r = probe_bucket(kx, bx, &more);
             }
+            if constexpr (WEIGHTED) {
+                double wx = w[0];
 #pragma unroll
-            for (int v = 0; v < N; ++v)
-                out[v] = (v == u) ? r : out[v];
+                for (int v = 1; v < N; ++v)
+                    wx = (v == u) ? w[v] : wx;
+                acc += wx * r;
+            } else {
+                acc += r;
+            }
         }
+        return acc;
     }
 };
 
@@ -402,11 +412,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                         }
                         probes += gl == 0 ? len - off0 : 0;
                     }
-                    double qv[kPerLane];
-                    tab.lookup_n<kPerLane>(key, qv);
-#pragma unroll
-                    for (int u = 0; u < kPerLane; ++u)
-                        acc += WEIGHTED ? wv[u] * qv[u] : qv[u];
+                    acc = tab.lookup_sum<kPerLane, WEIGHTED>(key, wv, acc);
                 }
                 const double g = dev::group_sum<kGroup>(acc);
                 if (gl == 0 && g != 0.0)

@@ -199,11 +199,17 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
                                the next row's record (one dependent load) */
 #define MCMF_SAMPLER_ROW 1  /* the picked column (4 bytes), then the next row's record
                                (8 bytes): two dependent loads, less data per step */
+#define MCMF_SAMPLER_VALUE 2 /* mcmf_action on unweighted graphs only: per-call 16-byte
+                               records {next row's record, r of the next row}, so a
+                               step makes one load and no separate read of r = sAv.
+                               Costs 16 bytes per stored entry during the call; falls
+                               back to EDGE with a path digest, on weighted graphs or
+                               when 16 nnz exceeds 1/16 of device memory */
 
 /* Per-graph choices of the walk kernels and of the diagonal gather.  They
  * change memory traffic and the order of floating-point sums only: walk paths
- * and step counts never change.  Defaults: action EDGE with non-temporal
- * loads, diag EDGE with cached loads, automatic hub threshold.
+ * and step counts never change.  Defaults: action VALUE with cached loads,
+ * diag EDGE with cached loads, automatic hub threshold.
  *
  * Hub rows: a graph created unweighted with MCMF_SYMMETRIC and strictly
  * increasing columns in every row keeps its (at most 32) rows of largest
@@ -217,7 +223,8 @@ typedef struct {
     int32_t action_stream;   /* 1: the walk's record loads are non-temporal */
     int32_t diag_sampler;    /* MCMF_SAMPLER_* of mcmf_diag walks */
     int32_t diag_stream;     /* 1: non-temporal record loads */
-    double action_ms[4];     /* mcmf_tune only: ms of each action variant, index sampler*2+stream */
+    double action_ms[4];     /* mcmf_tune only: ms of each EDGE/ROW action variant, index
+                                sampler*2+stream */
     double diag_ms[4];       /* mcmf_tune only: ms of each diag-walk variant, same index */
     int64_t sample_rows;     /* mcmf_tune only: start rows in the timed sample */
     int32_t hub_min_degree;  /* diagonal gather (unweighted graphs): a hub row (below) of at
@@ -227,7 +234,8 @@ typedef struct {
                                 Batched requests with n_walks < 32 never use it */
     int32_t hub_count;       /* out of mcmf_graph_get_tuning: hub rows the graph holds;
                                 ignored on input */
-    uint32_t reserved[4];    /* must be zero on input */
+    double action_value_ms[2]; /* mcmf_tune only: ms of the VALUE action walk, index stream
+                                  (0 when the graph cannot use it) */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the

@@ -58,6 +58,10 @@ Status spmv_assemble(const mcmf_graph *g, const double *v, const double *r, cons
                      double c0, double c1, double scale, double *y, hipStream_t s);
 
 // Action walks: q[k] for every k in starts[0..n_start).  digest/steps optional.
+// Whether the action's value records (16 bytes per stored entry, held for
+// the length of a call) stay within 1/16 of device memory.
+bool value_records_fit(const mcmf_graph *g);
+
 Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
                     const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
                     hipStream_t s);

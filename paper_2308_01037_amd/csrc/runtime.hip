@@ -294,18 +294,23 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c) {
     }
 }
 
-int64_t default_visit_chunk_bytes() {
-    if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
-        return std::max<int64_t>(1, strtoll(e, nullptr, 10));
-    static int64_t bytes = [] {
+uint64_t device_memory_bytes() {
+    static uint64_t bytes = [] {
         size_t free_b = 0, total_b = 0;
         if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
             (void)hipGetLastError();
-            return int64_t(2) << 30;
+            return uint64_t(64) << 30;
         }
-        return std::min<int64_t>(int64_t(8) << 30, std::max<int64_t>(int64_t(256) << 20, int64_t(total_b / 32)));
+        return static_cast<uint64_t>(total_b);
     }();
     return bytes;
+}
+
+int64_t default_visit_chunk_bytes() {
+    if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
+        return std::max<int64_t>(1, strtoll(e, nullptr, 10));
+    return std::min<int64_t>(int64_t(8) << 30,
+                             std::max<int64_t>(int64_t(256) << 20, static_cast<int64_t>(device_memory_bytes() / 32)));
 }
 
 int num_cus() {

@@ -28,13 +28,11 @@ __global__ void k_stride_sample(const int32_t *__restrict__ active, int64_t stri
 Status check_tuning(const mcmf_tuning *t) {
     if (!t)
         return fail(MCMF_E_ARG, "tuning is NULL");
-    for (uint32_t r : t->reserved)
-        if (r)
-            return fail(MCMF_E_ARG, "reserved tuning words must be zero");
     auto sampler_ok = [](int32_t v) { return v == MCMF_SAMPLER_EDGE || v == MCMF_SAMPLER_ROW; };
     auto flag_ok = [](int32_t v) { return v == 0 || v == 1; };
-    if (!sampler_ok(t->action_sampler) || !sampler_ok(t->diag_sampler))
-        return fail(MCMF_E_ARG, "unknown sampler layout");
+    if (!(sampler_ok(t->action_sampler) || t->action_sampler == MCMF_SAMPLER_VALUE) ||
+        !sampler_ok(t->diag_sampler))
+        return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only)");
     if (!flag_ok(t->action_stream) || !flag_ok(t->diag_stream))
         return fail(MCMF_E_ARG, "stream flags must be 0 or 1");
     if (t->hub_min_degree < 0)
@@ -55,6 +53,8 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     for (double &x : best.action_ms)
         x = 0.0;
     for (double &x : best.diag_ms)
+        x = 0.0;
+    for (double &x : best.action_value_ms)
         x = 0.0;
     if (g->n_active == 0) {
         *out = best;
@@ -134,6 +134,21 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     // Weighted graphs have one layout: the choice only matters unweighted.
     best.action_sampler = ba >> 1;
     best.action_stream = ba & 1;
+    // Value records (unweighted graphs that can hold them); the record build
+    // is part of the timed call.
+    if (!g->weighted && value_records_fit(g)) {
+        for (int st = 0; st < 2; ++st) {
+            p.sampler = MCMF_SAMPLER_VALUE;
+            p.stream = st;
+            MCMF_TRY(time_it([&]() { return action_walks(g, r.ptr, rows.ptr, m, p, q.ptr, nullptr, steps.ptr, s); },
+                             &best.action_value_ms[st]));
+        }
+        const int st = best.action_value_ms[0] <= best.action_value_ms[1] ? 0 : 1;
+        if (best.action_value_ms[st] < best.action_ms[ba]) {
+            best.action_sampler = MCMF_SAMPLER_VALUE;
+            best.action_stream = st;
+        }
+    }
     best.diag_sampler = bd >> 1;
     best.diag_stream = bd & 1;
     best.sample_rows = m;

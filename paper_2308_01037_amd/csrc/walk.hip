@@ -2,6 +2,8 @@
 // action, Eq. rand_funm_Q for the diagonal).  One workgroup per start row k
 // runs that row's walks; lane w runs walk w (and w + blockDim, ...).  The walk
 // itself is in walk_core.hpp.
+#include <algorithm>
+
 #include "walk_core.hpp"
 
 namespace mcmf {
@@ -114,6 +116,50 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
     }
 }
 
+// Action over value records (unweighted graphs, no path digest).
+template <class WT, bool CUTOFF, bool STREAM>
+__global__ __launch_bounds__(256) void k_action_walk_value(const uint2 *__restrict__ node,
+                                                           const uint4 *__restrict__ rec,
+                                                           const double *__restrict__ r,
+                                                           const int32_t *__restrict__ starts,
+                                                           int64_t n_start, WalkArgs a,
+                                                           double *__restrict__ q,
+                                                           unsigned long long *steps) {
+    __shared__ double red[4];
+    __shared__ unsigned long long redu[4];
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+        const uint32_t k = static_cast<uint32_t>(starts[kk]);
+        const uint2 rk = node[k];
+        const double r_k = r[k];
+        const int64_t N = a.row_walks ? a.row_walks[kk] : a.N;
+        double acc = 0.0;
+        unsigned long long nsteps = 0;
+        for (int64_t w64 = threadIdx.x; w64 < N; w64 += blockDim.x)
+            acc += walk::action_walk_value<WT, CUTOFF, STREAM>(rec, a, k, rk, r_k,
+                                                               static_cast<uint32_t>(w64), &nsteps);
+        const double total = dev::block_sum(acc, red);
+        const unsigned long long st = dev::block_sum(nsteps, redu);
+        if (threadIdx.x == 0) {
+            q[k] = total / static_cast<double>(N);
+            if (steps)
+                atomicAdd(steps, st);
+        }
+    }
+}
+
+// rec[e] = {first entry of row col[e], its length, r[col[e]]} from the edge
+// records.
+__global__ void k_value_records(const uint4 *__restrict__ edge, int64_t nnz, const double *__restrict__ r,
+                                uint4 *__restrict__ rec) {
+    for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < nnz;
+         e += int64_t(gridDim.x) * blockDim.x) {
+        const uint4 x = edge[e];
+        const double v = r[x.x];
+        rec[e] = make_uint4(x.y, x.z, static_cast<uint32_t>(__double2loint(v)),
+                            static_cast<uint32_t>(__double2hiint(v)));
+    }
+}
+
 int walk_block(int64_t N) {
     if (N >= 256)
         return 256;
@@ -129,6 +175,10 @@ dim3 walk_grid(int64_t n_start) {
 
 } // namespace
 
+bool value_records_fit(const mcmf_graph *g) {
+    return static_cast<uint64_t>(g->nnz) * sizeof(uint4) <= device_memory_bytes() / 16;
+}
+
 Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
                     const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
                     hipStream_t s) {
@@ -137,8 +187,32 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
     const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks));
-    const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.action_sampler) == MCMF_SAMPLER_EDGE;
+    const int sampler = p.sampler >= 0 ? p.sampler : g->tuning.action_sampler;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.action_stream) != 0;
+    if (sampler == MCMF_SAMPLER_VALUE && !g->weighted && !digest && value_records_fit(g)) {
+        DevBuf<uint4> rec;
+        MCMF_TRY(rec.alloc(g->nnz, s));
+        if (g->nnz > 0) {
+            const int64_t blocks = std::min<int64_t>((g->nnz + 255) / 256, int64_t(1) << 20);
+            hipLaunchKernelGGL(k_value_records, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
+                               g->edge, g->nnz, r, rec.ptr);
+            MCMF_HIP(hipGetLastError());
+        }
+        const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
+        const bool cut = p.cutoff > 0.0;
+        auto launch = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, block, 0, s, g->node, rec.ptr, r, starts, n_start, a, q, steps);
+        };
+        if (fp32)
+            cut ? (stream ? launch(k_action_walk_value<float, true, true>) : launch(k_action_walk_value<float, true, false>))
+                : (stream ? launch(k_action_walk_value<float, false, true>) : launch(k_action_walk_value<float, false, false>));
+        else
+            cut ? (stream ? launch(k_action_walk_value<double, true, true>) : launch(k_action_walk_value<double, true, false>))
+                : (stream ? launch(k_action_walk_value<double, false, true>) : launch(k_action_walk_value<double, false, false>));
+        MCMF_HIP(hipGetLastError());
+        return {};
+    }
+    const bool edge = sampler != MCMF_SAMPLER_ROW;
     walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
                     p.cutoff > 0.0, edge, stream, [&](auto wt, auto w, auto d, auto c, auto e, auto st) {
                         using WT = decltype(wt);

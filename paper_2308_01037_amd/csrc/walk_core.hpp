@@ -201,6 +201,49 @@ __device__ __forceinline__ double action_walk(const GraphView &g, const double *
     return wacc;
 }
 
+// One action walk over value records (unweighted rows): rec[e] = {first
+// entry of row col[e], its length, r[col[e]] as two words}, built per call,
+// so a step loads one 16-byte record and needs no separate read of r.  The
+// walk is the same as action_walk's (same draws, entries, weights and sum);
+// only the row index itself is not carried.
+template <class WT, bool CUTOFF, bool STREAM>
+__device__ __forceinline__ double action_walk_value(const uint4 *__restrict__ rec, const WalkArgs &a,
+                                                    uint32_t k, uint2 rk, double r_k, uint32_t w,
+                                                    unsigned long long *nsteps) {
+    const int last = a.K - 2;
+    uint32_t start = rk.x, deg = rk.y;
+    double rl = r_k;
+    WT W = WT(1);
+    double wacc = 0.0;
+    for (int t = 0; t <= last; ++t) {
+        if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
+            break;
+        const bool more = t < last && deg > 0;
+        uint32_t n_start = start, n_deg = deg;
+        double n_r = rl;
+        WT Wn = W;
+        if (more) {
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            const uint32_t j = dev::uniform_index(x.x, x.y, deg);
+            Wn = W * static_cast<WT>(a.scale * static_cast<double>(deg));
+            const uint4 e = load_edge<STREAM>(rec + (int64_t(start) + j));
+            n_start = e.x;
+            n_deg = e.y;
+            n_r = __hiloint2double(static_cast<int>(e.w), static_cast<int>(e.z));
+        }
+        wacc += static_cast<double>(static_cast<WT>(a.coef[t]) * W * static_cast<WT>(rl));
+        ++*nsteps;
+        if (!more)
+            break;
+        start = n_start;
+        deg = n_deg;
+        W = Wn;
+        rl = n_r;
+    }
+    return wacc;
+}
+
 // One diagonal walk: writes (l_t, c_{t+2} W_t) to vstate[t*stride],
 // vx[t*stride] for t = 0..K-2 (state -1 once the walk has ended).  With
 // hub_k != 0 (unweighted graphs; the hubs adjacent to k whose sums this

@@ -58,6 +58,7 @@ MCMF_ALLOC_NORM = 1
 
 MCMF_SAMPLER_EDGE = 0
 MCMF_SAMPLER_ROW = 1
+MCMF_SAMPLER_VALUE = 2
 
 
 class mcmf_fn(ctypes.Structure):
@@ -89,14 +90,14 @@ class mcmf_tuning(ctypes.Structure):
                 ("diag_sampler", ctypes.c_int32), ("diag_stream", ctypes.c_int32),
                 ("action_ms", ctypes.c_double * 4), ("diag_ms", ctypes.c_double * 4),
                 ("sample_rows", ctypes.c_int64), ("hub_min_degree", ctypes.c_int32),
-                ("hub_count", ctypes.c_int32), ("reserved", ctypes.c_uint32 * 4)]
+                ("hub_count", ctypes.c_int32), ("action_value_ms", ctypes.c_double * 2)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
                 "diag_sampler": self.diag_sampler, "diag_stream": self.diag_stream,
                 "action_ms": list(self.action_ms), "diag_ms": list(self.diag_ms),
                 "sample_rows": self.sample_rows, "hub_min_degree": self.hub_min_degree,
-                "hub_count": self.hub_count}
+                "hub_count": self.hub_count, "action_value_ms": list(self.action_value_ms)}
 
 
 MCMF_REQ_DIAG = 0

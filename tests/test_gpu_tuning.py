@@ -49,7 +49,7 @@ def test_every_variant_matches_oracle(maker, sampler, stream):
 def test_tuning_argument_errors():
     with graph(G.path(5)) as g:
         t = M.mcmf_tuning()
-        t.action_sampler = 2
+        t.action_sampler = -1
         with pytest.raises(M.MCMFError):
             M.mcmf_graph_set_tuning(g.handle, t)
         t = M.mcmf_tuning()
@@ -57,7 +57,11 @@ def test_tuning_argument_errors():
         with pytest.raises(M.MCMFError):
             M.mcmf_graph_set_tuning(g.handle, t)
         t = M.mcmf_tuning()
-        t.reserved[1] = 1
+        t.diag_sampler = M.MCMF_SAMPLER_VALUE  # value records are for the action only
+        with pytest.raises(M.MCMFError):
+            M.mcmf_graph_set_tuning(g.handle, t)
+        t = M.mcmf_tuning()
+        t.action_sampler = 3
         with pytest.raises(M.MCMFError):
             M.mcmf_graph_set_tuning(g.handle, t)
         with pytest.raises(M.MCMFError):
@@ -72,8 +76,11 @@ def test_autotune_measures_then_caches(tmp_path):
         a = tuning.autotune(g, csr, f, 64, 20, path)
         assert not a["cached"] and a["sample_rows"] > 0
         assert all(ms > 0 for ms in a["action_ms"]) and all(ms > 0 for ms in a["diag_ms"])
-        best_a = int(np.argmin(a["action_ms"]))
-        assert (a["action_sampler"], a["action_stream"]) == (best_a >> 1, best_a & 1)
+        assert all(ms > 0 for ms in a["action_value_ms"])
+        # The fastest of the four EDGE/ROW variants and the two VALUE ones.
+        times = list(a["action_ms"]) + list(a["action_value_ms"])
+        choice = [(v >> 1, v & 1) for v in range(4)] + [(M.MCMF_SAMPLER_VALUE, 0), (M.MCMF_SAMPLER_VALUE, 1)]
+        assert (a["action_sampler"], a["action_stream"]) == choice[int(np.argmin(times))]
         t = M.mcmf_graph_get_tuning(g.handle)
         assert (t.diag_sampler, t.diag_stream) == (a["diag_sampler"], a["diag_stream"])
     with graph(csr) as g2:
@@ -88,3 +95,53 @@ def test_autotune_measures_then_caches(tmp_path):
         y = gpu_diag(g2, "exp", 32, 12, 1.0 / csr.d_max, seed=9, want_digest=True)
         assert np.array_equal(x["digest"], y["digest"])
         assert_close(x["d"], y["d"], 1e-12)
+
+
+@pytest.mark.parametrize("stream", [0, 1])
+def test_value_records_action_matches_edge_and_oracle(stream):
+    # The VALUE action walk makes the same draws, weights and sums as EDGE: its
+    # estimate equals EDGE's bit for bit, for FP64 and FP32 weights, with a
+    # weight cutoff and with walks allocated by column norm; a path digest or a
+    # weighted graph falls back to EDGE.
+    import torch
+    csr = G.rmat(12, seed=6)
+    K, N, s = 14, 40, 0.9 / csr.d_max
+    v = np.random.default_rng(2).random(csr.n)
+
+    def run(g, sampler, n_walks=N, **kw):
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.action_sampler, t.action_stream, t.hub_count = sampler, stream, 0
+        M.mcmf_graph_set_tuning(g.handle, t)
+        vt = torch.as_tensor(v, device="cuda")
+        out = torch.empty(csr.n, dtype=torch.float64, device="cuda")
+        st = M.mcmf_stats()
+        M.mcmf_action(g.handle, M.make_fn(M.MCMF_FN_RESOLVENT, s), vt, n_walks, K,
+                      M.make_opts(seed=4, stream=torch.cuda.current_stream().cuda_stream, **kw), out, st)
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), st.walk_steps
+
+    with graph(csr) as g:
+        for kw in ({}, {"precision": M.MCMF_PRECISION_FP32_WEIGHTS}, {"weight_cutoff": 1e-4},
+                   {"allocation": M.MCMF_ALLOC_NORM}):
+            n_walks = N * 50 if kw.get("allocation") else N  # N_s in total for the norm allocation
+            a, sa = run(g, M.MCMF_SAMPLER_VALUE, n_walks, **kw)
+            b, sb = run(g, M.MCMF_SAMPLER_EDGE, n_walks, **kw)
+            assert sa == sb, kw
+            assert np.array_equal(a, b), kw
+        o = oracle.action(csr, oracle_fn("resolvent"), v, N=N, K=K, scale=s, seed=4)
+        assert_close(run(g, M.MCMF_SAMPLER_VALUE)[0], o["y"], 1e-10)
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.action_sampler, t.hub_count = M.MCMF_SAMPLER_VALUE, 0
+        M.mcmf_graph_set_tuning(g.handle, t)
+        r = gpu_action(g, "resolvent", v, N, K, s, seed=4, want_digest=True)
+        o = oracle.action(csr, oracle_fn("resolvent"), v, N=N, K=K, scale=s, seed=4, want_digest=True)
+        assert np.array_equal(r["digest"], o["digest"])
+    wcsr = G.with_random_weights(csr, seed=3)
+    with graph(wcsr) as g:
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.action_sampler, t.hub_count = M.MCMF_SAMPLER_VALUE, 0
+        M.mcmf_graph_set_tuning(g.handle, t)
+        ws = 0.5 / float(np.max(np.add.reduceat(np.abs(wcsr.val), wcsr.row_ptr[:-1])))
+        r = gpu_action(g, "exp", v, N, K, ws, seed=4)
+        o = oracle.action(wcsr, oracle_fn("exp"), v, N=N, K=K, scale=ws, seed=4)
+        assert_close(r["y"], o["y"], 1e-10)

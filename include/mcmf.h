@@ -353,7 +353,10 @@ typedef struct {
     void *stream;               /* hipStream_t the batch is ordered on, or NULL for the
                                    stream of the first request's graph */
     int32_t use_graph;          /* 1: record the batch's launches in a hipGraph, then
-                                   launch that graph (one submission for the batch) */
+                                   launch that graph (one submission for the batch).  If
+                                   another host thread invalidates the capture (some HIP
+                                   calls in threads left in the default capture-interaction
+                                   mode do), the batch is launched directly instead */
     int32_t reserved0;          /* must be zero */
     uint64_t visit_chunk_bytes; /* diagonal visit-record buffer of the batch; 0: the
                                    MCMF_DIAG_CHUNK_BYTES environment value, else 1/32 of

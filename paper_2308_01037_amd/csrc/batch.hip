@@ -554,7 +554,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     // Gather plan of each diagonal request: its own table size (so a request
     // with few walks keeps a small table and many workgroups per CU) and
     // walks per pass.
-    const size_t table_lds = 160 * 1024 - gather::kStaticLds;
+    const size_t table_lds = gather::kMaxTableLds;
     std::vector<uint32_t> req_nb(n_reqs, 0);
     std::vector<size_t> req_lds(n_reqs, 0);
     for (int64_t i = 0; i < n_reqs; ++i) {
@@ -693,9 +693,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     }
     for (int v = 0; v < kGatherVariants; ++v)
         if (lds_max[v] > 0)
-            MCMF_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(gather_kernel(v)),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize,
-                                         static_cast<int>(lds_max[v])));
+            MCMF_TRY(gather::allow_table_lds(reinterpret_cast<const void *>(gather_kernel(v))));
     // Persistent gather workgroups per group: as many as fit at once.
     std::vector<int64_t> group_blocks;
     for (const Chunk &c : chunks)
@@ -792,23 +790,35 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         MCMF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         Status st = enqueue();
         hipError_t ce = hipStreamEndCapture(s, &graph);
-        if (st) {
+        if (ce == hipErrorStreamCaptureInvalidated) {
+            // Another host thread made a call that invalidates captures in
+            // progress (the runtime checks some calls against every capture
+            // in the process).  Nothing captured has run: run the batch's
+            // launches directly instead.
+            (void)hipGetLastError();
             if (graph)
                 (void)hipGraphDestroy(graph);
-            return st;
-        }
-        MCMF_HIP(ce);
-        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        if (ie != hipSuccess) {
+            clear_error();
+            MCMF_TRY(enqueue());
+        } else {
+            if (st) {
+                if (graph)
+                    (void)hipGraphDestroy(graph);
+                return st;
+            }
+            MCMF_HIP(ce);
+            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (ie != hipSuccess) {
+                (void)hipGraphDestroy(graph);
+                MCMF_HIP(ie);
+            }
+            hipError_t le = hipGraphLaunch(exec, s);
+            hipError_t se = hipStreamSynchronize(s);
+            (void)hipGraphExecDestroy(exec);
             (void)hipGraphDestroy(graph);
-            MCMF_HIP(ie);
+            MCMF_HIP(le);
+            MCMF_HIP(se);
         }
-        hipError_t le = hipGraphLaunch(exec, s);
-        hipError_t se = hipStreamSynchronize(s);
-        (void)hipGraphExecDestroy(exec);
-        (void)hipGraphDestroy(graph);
-        MCMF_HIP(le);
-        MCMF_HIP(se);
     } else {
         MCMF_TRY(enqueue());
     }

@@ -176,7 +176,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.queue = queue;
     a.hub_of = g->hub_of;
     a.hub_act = p.hub_act;
-    const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, 160 * 1024 - kStaticLds,
+    const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, kMaxTableLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);
     if (!plan.ok)
         return fail(MCMF_E_UNSUPPORTED, "no Q_k table layout fits LDS for N=%lld, K=%d",
@@ -188,7 +188,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
     auto launch = [&](auto kernel) -> Status {
         const void *fn = reinterpret_cast<const void *>(kernel);
-        MCMF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)));
+        MCMF_TRY(allow_table_lds(fn));
         // Persistent workgroups: as many as fit on the device at once.
         int per_cu = 0;
         MCMF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kGatherThreads, lds));

@@ -21,6 +21,10 @@
 //  in passes (Q_k is linear in the walks) and the gather repeats per pass.
 #pragma once
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "device.hpp"
 #include "ops.hpp"
 #include "plan.hpp"
@@ -461,6 +465,27 @@ __device__ __forceinline__ int64_t next_item(unsigned long long *counter, int64_
 // LDS bytes of the table for a plan, and of the fixed per-workgroup arrays.
 constexpr size_t kStaticLds = sizeof(Batch) + sizeof(uint32_t) * kWaves +
                               sizeof(unsigned long long) * kWaves + 512;
+
+// Largest dynamic LDS (table + filter) a gather plan may ask for.
+constexpr size_t kMaxTableLds = 160 * 1024 - kStaticLds;
+
+// Raises a gather kernel's dynamic-LDS limit to kMaxTableLds, once per
+// (kernel, device).  The limit is a property of the kernel shared by every
+// host thread: setting it per call to that call's table size would let a
+// concurrent call on another stream lower it under a launch of its own.
+inline Status allow_table_lds(const void *fn) {
+    static std::mutex mu;
+    static std::set<std::pair<const void *, int>> done;
+    int dev = 0;
+    MCMF_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.count({fn, dev}))
+        return {};
+    MCMF_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 static_cast<int>(kMaxTableLds)));
+    done.insert({fn, dev});
+    return {};
+}
 
 __device__ __forceinline__ Shared shared_views(unsigned char *smem, uint32_t nb, Batch *bt,
                                                uint32_t *scan, unsigned long long *red) {

@@ -44,6 +44,7 @@ struct Ticket {
     Clock::time_point submitted, started, finished;
     int32_t batch_size = 0;
     bool done = false;
+    std::string error; // the failing call's message (the slot thread's last error)
 };
 
 // Host-side sizing of one request, from sizes alone (no device access, so
@@ -130,6 +131,10 @@ uint64_t batch_estimate(const std::vector<std::shared_ptr<Ticket>> &b, uint64_t 
 
 void run_slot(mcmf_server *S, mcmf_server::Slot *slot) {
     (void)hipSetDevice(S->opts.device);
+    // This thread's allocations and copies must not invalidate another slot's
+    // hipGraph capture (the default, global interaction mode would).
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    (void)hipThreadExchangeStreamCaptureMode(&mode);
     for (;;) {
         std::vector<std::shared_ptr<Ticket>> batch;
         {
@@ -149,17 +154,21 @@ void run_slot(mcmf_server *S, mcmf_server::Slot *slot) {
         bo.stream = slot->stream;
         bo.use_graph = S->opts.use_graph;
         bo.visit_chunk_bytes = S->opts.visit_chunk_bytes;
+        std::vector<std::string> errors(reqs.size());
         Status st = run_batch(reqs.data(), static_cast<int64_t>(reqs.size()), &bo, nullptr);
         if (st && reqs.size() > 1) {
             // Isolate the failure: every request on its own.
-            for (auto &r : reqs) {
-                mcmf_request one = r;
+            for (size_t i = 0; i < reqs.size(); ++i) {
+                mcmf_request one = reqs[i];
                 Status s1 = run_batch(&one, 1, &bo, nullptr);
-                r.status = s1.code;
-                r.walk_steps = s1 ? 0 : one.walk_steps;
+                reqs[i].status = s1.code;
+                reqs[i].walk_steps = s1 ? 0 : one.walk_steps;
+                if (s1)
+                    errors[i] = mcmf_last_error();
             }
         } else if (st) {
             reqs[0].status = st.code;
+            errors[0] = mcmf_last_error();
         }
         const Clock::time_point t1 = Clock::now();
         {
@@ -171,6 +180,7 @@ void run_slot(mcmf_server *S, mcmf_server::Slot *slot) {
                 t.started = t0;
                 t.finished = t1;
                 t.batch_size = static_cast<int32_t>(batch.size());
+                t.error = errors[i];
                 t.done = true;
             }
             S->in_flight -= slot->est;
@@ -365,7 +375,7 @@ Status wait_ticket(mcmf_server *S, uint64_t id, mcmf_ticket_info *info) {
         info->est_steps = t->steps;
     }
     if (code != MCMF_OK)
-        return fail(code, "request failed: %s", mcmf_status_string(code));
+        return fail(code, "request failed: %s", t->error.empty() ? mcmf_status_string(code) : t->error.c_str());
     return {};
 }
 

@@ -35,8 +35,10 @@ constexpr int kWalkThreads = 256;
 
 // Walk kernel variant of a request: FP32 weights, weighted graph, weight
 // cutoff, path digest.
-enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4, kModeDigest = 8 };
-constexpr int kWalkModes = 16;
+// kModeValue: an action request walking over its own value records (see
+// walk_core.hpp, action_walk_value): unweighted graphs without a digest.
+enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4, kModeDigest = 8, kModeValue = 16 };
+constexpr int kWalkModes = 32;
 
 // Device descriptor of one request.
 struct BReq {
@@ -53,6 +55,7 @@ struct BReq {
     double *dacc;              // diag sums
     const int64_t *item_off;   // diag: gather work items of the start list
     int64_t wpp;               // walks per gather pass
+    const uint4 *rec;          // action, value mode: this request's value records
     const uint8_t *hub_of;     // diag: hub index per node
     uint32_t hub_act;          // diag: hubs the walks sum (a.hub_act), left out of the probes
 };
@@ -88,13 +91,17 @@ constexpr int64_t kRowTaskWalks = 128; // N at or above which a task is one row
 constexpr int64_t kHubMinWalks = 32;   // packed tasks hold at most 256/32 rows of hub sums
 constexpr int kHubRows = kWalkThreads / kHubMinWalks;
 
-template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
+template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST, bool VALUE>
 __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t rel, uint32_t k, uint2 rk,
                                          int64_t w, int32_t *vstate, unsigned char *vxb, double &acc,
                                          uint64_t &h, unsigned long long &ns, uint32_t hub_k = 0u,
                                          double *hsum = nullptr) {
     const int64_t N = R.a.N;
-    if (R.kind == MCMF_REQ_ACTION) {
+    if constexpr (VALUE) {
+        // Only action requests carry the value mode.
+        acc += walk::action_walk_value<WT, CUTOFF, false>(R.rec, R.a, k, rk, R.r[k], static_cast<uint32_t>(w),
+                                                          &ns);
+    } else if (R.kind == MCMF_REQ_ACTION) {
         acc += walk::action_walk<WT, WEIGHTED, DIGEST, CUTOFF>(R.g, R.r, R.a, k, rk, R.r[k],
                                                                 static_cast<uint32_t>(w), &h, &ns);
     } else {
@@ -106,7 +113,7 @@ __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t 
     }
 }
 
-template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST>
+template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST, bool VALUE>
 __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restrict__ reqs,
                                                              const WSeg *__restrict__ segs,
                                                              int n_segs, int64_t n_tasks,
@@ -171,7 +178,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
             uint64_t dig = 0;
             for (int64_t w = tid; w < N; w += blockDim.x) {
                 h = dev::kFnvBasis;
-                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST, VALUE>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
                                                        hub_k, hsum);
                 dig += h;
             }
@@ -222,7 +229,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
                 const uint32_t k = static_cast<uint32_t>(R.starts[sg.kk0 + rel]);
                 const uint2 rk = R.g.node[k];
                 double acc = 0.0;
-                one_walk<WT, WEIGHTED, CUTOFF, DIGEST>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
+                one_walk<WT, WEIGHTED, CUTOFF, DIGEST, VALUE>(R, sg, rel, k, rk, w, vstate, vxb, acc, h, ns,
                                                        hub_k, hsum + slot * kMaxHubs);
                 if (R.kind == MCMF_REQ_ACTION && acc != 0.0)
                     atomicAdd(&R.q[k], acc / static_cast<double>(N));
@@ -259,7 +266,10 @@ using WalkKernel = void (*)(const BReq *, const WSeg *, int, int64_t, int32_t *,
 template <int M>
 WalkKernel walk_kernel_of() {
     using WT = typename std::conditional<(M & kModeFp32) != 0, float, double>::type;
-    return &k_batch_walk<WT, (M & kModeWeighted) != 0, (M & kModeCutoff) != 0, (M & kModeDigest) != 0>;
+    // The value mode exists only unweighted without a digest; the other
+    // combinations never occur and share the plain kernel.
+    constexpr bool kValue = (M & kModeValue) != 0 && (M & (kModeWeighted | kModeDigest)) == 0;
+    return &k_batch_walk<WT, (M & kModeWeighted) != 0, (M & kModeCutoff) != 0, (M & kModeDigest) != 0, kValue>;
 }
 
 template <int... M>
@@ -365,6 +375,7 @@ struct Prep {
     mcmf_request *req = nullptr;
     std::vector<double> c;
     DevBuf<double> coef, r, q, dacc;
+    DevBuf<uint4> rec; // action value records (when used)
     DevBuf<uint8_t> in_set, start_flags;
     DevBuf<int32_t> start_list;
     DevBuf<int64_t> items;
@@ -405,7 +416,8 @@ Status check_request(mcmf_request &q) {
 
 namespace {
 
-Status prepare(Prep &P, hipStream_t s) {
+// value_budget: bytes of action value records the batch may still hold.
+Status prepare(Prep &P, hipStream_t s, uint64_t *value_budget) {
     mcmf_request &q = *P.req;
     const mcmf_graph *g = q.graph;
     const int64_t n = g->n;
@@ -429,6 +441,15 @@ Status prepare(Prep &P, hipStream_t s) {
             MCMF_TRY(P.q.alloc(n > 0 ? n : 1, s));
             P.starts = g->active;
             P.n_start = g->n_active;
+            // Value records when the graph's tuning asks for them (as a single
+            // call would) and the batch's share of memory allows.
+            const uint64_t bytes = static_cast<uint64_t>(g->nnz) * sizeof(uint4);
+            if (g->tuning.action_sampler == MCMF_SAMPLER_VALUE && !g->weighted && !q.path_digest &&
+                g->nnz > 0 && bytes <= *value_budget) {
+                MCMF_TRY(P.rec.alloc(g->nnz, s));
+                MCMF_TRY(build_value_records(g, P.r.ptr, P.rec.ptr, s));
+                *value_budget -= bytes;
+            }
         }
         return {};
     }
@@ -502,10 +523,11 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     const bool use_graph = o && o->use_graph;
 
     std::vector<std::unique_ptr<Prep>> preps(n_reqs);
+    uint64_t value_budget = device_memory_bytes() / 16; // action value records of the whole batch
     for (int64_t i = 0; i < n_reqs; ++i) {
         preps[i].reset(new Prep());
         preps[i]->req = &reqs[i];
-        Status st = prepare(*preps[i], s);
+        Status st = prepare(*preps[i], s, &value_budget);
         if (st) {
             reqs[i].status = st.code;
             return st;
@@ -529,7 +551,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.kind = q.kind;
         B.mode = (q.precision == MCMF_PRECISION_FP32_WEIGHTS ? kModeFp32 : 0) |
                  (q.graph->weighted ? kModeWeighted : 0) | (q.weight_cutoff > 0.0 ? kModeCutoff : 0) |
-                 (P.dig.ptr ? kModeDigest : 0);
+                 (P.dig.ptr ? kModeDigest : 0) | (P.rec.ptr ? kModeValue : 0);
+        B.rec = P.rec.ptr;
         B.starts = P.starts;
         B.r = P.r.ptr;
         B.q = P.q.ptr;

@@ -62,6 +62,10 @@ Status spmv_assemble(const mcmf_graph *g, const double *v, const double *r, cons
 // the length of a call) stay within 1/16 of device memory.
 bool value_records_fit(const mcmf_graph *g);
 
+// rec[e] = {first entry of row col[e], its length, r[col[e]]} (unweighted
+// graphs; rec holds nnz entries).
+Status build_value_records(const mcmf_graph *g, const double *r, uint4 *rec, hipStream_t s);
+
 Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
                     const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
                     hipStream_t s);

@@ -179,6 +179,16 @@ bool value_records_fit(const mcmf_graph *g) {
     return static_cast<uint64_t>(g->nnz) * sizeof(uint4) <= device_memory_bytes() / 16;
 }
 
+Status build_value_records(const mcmf_graph *g, const double *r, uint4 *rec, hipStream_t s) {
+    if (g->nnz <= 0)
+        return {};
+    const int64_t blocks = std::min<int64_t>((g->nnz + 255) / 256, int64_t(1) << 20);
+    hipLaunchKernelGGL(k_value_records, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, g->edge, g->nnz,
+                       r, rec);
+    MCMF_HIP(hipGetLastError());
+    return {};
+}
+
 Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts, int64_t n_start,
                     const WalkParams &p, double *q, uint64_t *digest, unsigned long long *steps,
                     hipStream_t s) {
@@ -192,12 +202,7 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     if (sampler == MCMF_SAMPLER_VALUE && !g->weighted && !digest && value_records_fit(g)) {
         DevBuf<uint4> rec;
         MCMF_TRY(rec.alloc(g->nnz, s));
-        if (g->nnz > 0) {
-            const int64_t blocks = std::min<int64_t>((g->nnz + 255) / 256, int64_t(1) << 20);
-            hipLaunchKernelGGL(k_value_records, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
-                               g->edge, g->nnz, r, rec.ptr);
-            MCMF_HIP(hipGetLastError());
-        }
+        MCMF_TRY(build_value_records(g, r, rec.ptr, s));
         const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
         const bool cut = p.cutoff > 0.0;
         auto launch = [&](auto kernel) {

@@ -62,6 +62,10 @@ void estimate(const mcmf_request &q, uint64_t *fixed, uint64_t *visits, uint64_t
     uint64_t starts = q.K >= 2 ? static_cast<uint64_t>(g->n_active) : 0;
     if (q.kind == MCMF_REQ_ACTION) {
         f += 8 * n * 4; // v and out staging, r, q
+        // Value records when the graph's tuning uses them (an upper bound:
+        // a batch may fall back to EDGE walks when they do not fit).
+        if (q.K >= 2 && g->tuning.action_sampler == MCMF_SAMPLER_VALUE && !g->weighted && !q.path_digest)
+            f += 16 * static_cast<uint64_t>(g->nnz);
     } else {
         const uint64_t count = q.rows ? static_cast<uint64_t>(q.n_rows) : n;
         f += 8 * n + 2 * n + 4 * n + 8 * (n + 1) + 12 * count; // dacc, marks, start list, items, rows/out

@@ -147,8 +147,8 @@ typedef struct {
     uint64_t start_rows;    /* rows that started walks */
     uint64_t walks;         /* walks started (start_rows * n_walks per row) */
     uint64_t walk_steps;    /* recorded walk states (K-1 per full walk) */
-    uint64_t gather_probes; /* mcmf_diag: column entries streamed by the gather, plus the
-                               visit records each hub sweep of the gather reads */
+    uint64_t gather_probes; /* mcmf_diag: column entries the gather probed (hub rows summed
+                               by the walks are not probed) */
     double ms_setup;        /* marks, start set, temporaries */
     double ms_spmv;         /* r = sA v and the final assembly (action);
                                the final assembly of the diagonal (diag) */
@@ -214,10 +214,13 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
  * Hub rows: a graph created unweighted with MCMF_SYMMETRIC and strictly
  * increasing columns in every row keeps its (at most 32) rows of largest
  * degree as hubs, with one 32-bit mask per node of the hubs it is adjacent
- * to.  For a start row k next to a hub h, <Q_k, C_h> of Eq.
- * rand_funm_formula_diag is then the sum of the visit weights of k's walks
- * at states adjacent to h: one mask read per visit record, instead of one
- * probe of Q_k per entry of row h. */
+ * to (also kept in the spare word of every edge record).  For a start row
+ * k next to a hub h, <Q_k, C_h> of Eq. rand_funm_formula_diag is then the
+ * sum of the visit weights of k's walks at states adjacent to h, which the
+ * diagonal walk adds up as it records the visits (the mask arrives with the
+ * record it loads anyway), instead of one probe of Q_k per entry of row h
+ * in the gather.  The graph's hubs, and the masks, assume the symmetry that
+ * MCMF_SYMMETRIC states. */
 typedef struct {
     int32_t action_sampler;  /* MCMF_SAMPLER_* of mcmf_action walks */
     int32_t action_stream;   /* 1: the walk's record loads are non-temporal */
@@ -227,11 +230,12 @@ typedef struct {
                                 sampler*2+stream */
     double diag_ms[4];       /* mcmf_tune only: ms of each diag-walk variant, same index */
     int64_t sample_rows;     /* mcmf_tune only: start rows in the timed sample */
-    int32_t hub_min_degree;  /* diagonal gather (unweighted graphs): a hub row (below) of at
-                                least this many entries is summed by the hub pass instead of
-                                being probed entry by entry; 0 = automatic, a degree of at
-                                least n_walks (K - 1) / 4; INT32_MAX turns the pass off.
-                                Batched requests with n_walks < 32 never use it */
+    int32_t hub_min_degree;  /* diagonal (unweighted graphs): a hub row (below) of at least
+                                this many entries has its sums taken by the walk kernel
+                                instead of being probed entry by entry by the gather;
+                                0 = automatic, a degree of at least n_walks (K - 1) / 4;
+                                INT32_MAX turns hub sums off.  Batched requests with
+                                n_walks < 32 never use them */
     int32_t hub_count;       /* out of mcmf_graph_get_tuning: hub rows the graph holds;
                                 ignored on input */
     double action_value_ms[2]; /* mcmf_tune only: ms of the VALUE action walk, index stream

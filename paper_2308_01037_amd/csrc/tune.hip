@@ -2,11 +2,13 @@
 //
 // The walk step has two sampler layouts (one 16-byte edge record, or the
 // column and then the next row's record) and two load policies (cached or
-// non-temporal).  Which is fastest depends on the graph: its size against
-// the caches, the locality of its node numbering, the degree spread.  The
-// tuner times the four variants of the action walk and of the diagonal
-// walk on an evenly strided sample of the rows with entries, with the
-// caller's function, walk count and K, and keeps the fastest of each.
+// non-temporal); the action walk of an unweighted graph has a third layout,
+// per-call value records that carry r of the next row.  Which is fastest
+// depends on the graph: its size against the caches, the locality of its
+// node numbering, the degree spread.  The tuner times every variant of the
+// action walk (value records included, their build counted) and of the
+// diagonal walk on an evenly strided sample of the rows with entries, with
+// the caller's function, walk count and K, and keeps the fastest of each.
 #include <algorithm>
 #include <cmath>
 #include <vector>

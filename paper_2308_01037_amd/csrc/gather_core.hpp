@@ -17,6 +17,11 @@
 //     active hubs (its highest-degree rows), <Q_k, C_h> is summed by the walk
 //     kernel instead (it sees each state's hub mask in the edge record it
 //     loads anyway); every item leaves those neighbours out of step 2.
+//  4. Small items (one batch of neighbours whose column entries number at
+//     most half the visits): the table first takes those entries as keys,
+//     then each visit is added to its key if present.  Q_k restricted to the
+//     entries the probes ask for gives the same inner products with one
+//     lookup per visit instead of one insert.
 //  When the row's visits cannot fit the table at once, the walks are taken
 //  in passes (Q_k is linear in the walks) and the gather repeats per pass.
 #pragma once
@@ -44,6 +49,9 @@ constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
 constexpr int kGroups = kGatherThreads / kGroup;
 constexpr int kSlots = 8;                  // slots per bucket
 constexpr int kVisits = 4;                 // visit records per thread in flight (table build)
+// A one-batch item keeps only its column entries in the table when its
+// column chunks hold at most visits * kRestrictDen / kRestrictNum entries.
+constexpr uint64_t kRestrictNum = 2, kRestrictDen = 1;
 constexpr int32_t kEmpty = -1;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
@@ -99,7 +107,9 @@ struct Table {
     // that slot, so the bucket is read again; a full bucket passes the probe
     // on.  Every lost claim fills a slot, which bounds the passes.  Returns
     // false only if every bucket is full (the plan rules that out).
-    __device__ bool insert(int32_t key, double x) const {
+    // Slot of key, claimed for it if the key is new, or -1 if every bucket is
+    // full (the plan rules that out).
+    __device__ int claim_slot(int32_t key) const {
         const uint32_t h = fhash(key);
         atomicOr(&filter[filter_word(h)], filter_mask(h));
         uint32_t b = bucket_of(key);
@@ -108,10 +118,8 @@ struct Table {
             const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
             const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
             const int j = slot_in(lo, hi, key);
-            if (j >= 0) {
-                atomicAdd(&vals[kSlots * b + j], x);
-                return true;
-            }
+            if (j >= 0)
+                return static_cast<int>(kSlots * b) + j;
             const int used = (lo.x != kEmpty) + (lo.y != kEmpty) + (lo.z != kEmpty) +
                              (lo.w != kEmpty) + (hi.x != kEmpty) + (hi.y != kEmpty) +
                              (hi.z != kEmpty) + (hi.w != kEmpty);
@@ -121,12 +129,38 @@ struct Table {
             }
             const uint32_t s = kSlots * b + used;
             const int32_t prev = atomicCAS(&keys[s], kEmpty, key);
-            if (prev == kEmpty || prev == key) {
-                atomicAdd(&vals[s], x);
-                return true;
-            }
+            if (prev == kEmpty || prev == key)
+                return static_cast<int>(s);
         }
-        return false;
+        return -1;
+    }
+
+    __device__ bool insert(int32_t key, double x) const {
+        const int s = claim_slot(key);
+        if (s < 0)
+            return false;
+        atomicAdd(&vals[s], x);
+        return true;
+    }
+
+    // Slot of key, or -1 when it is absent (no insert may run meanwhile).
+    __device__ int locate(int32_t key) const {
+        const uint32_t h = fhash(key);
+        const uint32_t m = filter_mask(h);
+        if ((filter[filter_word(h)] & m) != m)
+            return -1;
+        uint32_t b = bucket_of(key);
+        for (uint32_t tries = 0; tries < nb; ++tries) {
+            const int4 lo = *reinterpret_cast<const int4 *>(keys + kSlots * b);
+            const int4 hi = *reinterpret_cast<const int4 *>(keys + kSlots * b + 4);
+            const int j = slot_in(lo, hi, key);
+            if (j >= 0)
+                return static_cast<int>(kSlots * b) + j;
+            if (hi.w == kEmpty)
+                return -1; // slots fill in order: the key would be here
+            b = (b + 1 == nb) ? 0 : b + 1;
+        }
+        return -1;
     }
 
     // Value of key in bucket b, or: 0 with *more = false when the key is absent
@@ -276,9 +310,64 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
     const int32_t k = j.k;
     const uint2 rk = j.rk;
     const int32_t *st = j.st;
+    const int group = threadIdx.x / kGroup;
+    const int gl = threadIdx.x % kGroup;
+
+    // Neighbours [p0, p0 + m) of k into bt; returns the number of column
+    // chunks (kChunk entries each) of those that are requested and probed.
+    auto setup_batch = [&](uint32_t p0, uint32_t m) -> uint32_t {
+        __syncthreads(); // table complete / previous batch flushed
+        uint32_t nchunks = 0;
+        if (threadIdx.x < kBatch) {
+            const int t = threadIdx.x;
+            bt.sum[t] = 0.0;
+            bt.row[t] = -1;
+            bt.len[t] = 0;
+            if (uint32_t(t) < m) {
+                const int64_t e = int64_t(rk.x) + p0 + t;
+                const int32_t i = j.col[e];
+                bool take = !j.in_set || j.in_set[i];
+                if constexpr (!WEIGHTED) {
+                    // Active hubs are summed by the walks instead.
+                    if (take && j.hub_act != 0u) {
+                        const uint32_t hx = j.hub_of[i];
+                        take = hx == kNoHub || ((j.hub_act >> hx) & 1u) == 0u;
+                    }
+                }
+                if (take) {
+                    const uint2 ri = j.node[i];
+                    nchunks = (ri.y + kChunk - 1) / kChunk;
+                    bt.start[t] = ri.x;
+                    bt.len[t] = ri.y;
+                    bt.row[t] = i;
+                    bt.aki[t] = j.scale * (WEIGHTED ? j.val[e] : 1.0);
+                }
+            }
+        }
+        uint32_t total = 0;
+        const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
+        if (threadIdx.x < kBatch)
+            bt.prefix[threadIdx.x] = before;
+        if (threadIdx.x == 0)
+            bt.prefix[kBatch] = total;
+        __syncthreads();
+        return total;
+    };
+    // First neighbour (in bt) whose chunks reach chunk c.
+    auto owner = [&](uint32_t c) -> int {
+        int r = 0, hi = kBatch;
+        while (hi - r > 1) {
+            const int mid = (r + hi) >> 1;
+            if (bt.prefix[mid] <= c)
+                r = mid;
+            else
+                hi = mid;
+        }
+        return r;
+    };
+
     for (int64_t w0 = 0; w0 < j.N; w0 += j.walks_per_pass) {
         const int64_t nw = (j.N - w0 < j.walks_per_pass) ? (j.N - w0) : j.walks_per_pass;
-        // (1) Q_k from walks [w0, w0 + nw).
         __syncthreads();
         for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
             tab.keys[i] = kEmpty;
@@ -288,9 +377,70 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             tab.filter[i] = 0u;
         __syncthreads();
         const int64_t count = nw * (j.K - 1);
-        if (nw == j.N) {
-            // Step 0 of every walk sits at k: insert the sum of those visits once
-            // instead of N colliding atomic updates of one slot.
+        // An item of one neighbour batch whose columns hold fewer entries than
+        // half the visits: the table takes those entries as keys and the
+        // visits are added to the keys present (Q_k restricted to the entries
+        // the probes will ask for), instead of every visit being inserted.
+        const bool single = nw == j.N && j.p_end - j.p_begin <= uint32_t(kBatch);
+        uint32_t total0 = 0;
+        bool restricted = false;
+        if (single) {
+            total0 = setup_batch(j.p_begin, j.p_end - j.p_begin);
+            // total0 * kChunk bounds the batch's column entries from above.
+            restricted = uint64_t(total0) * kChunk * kRestrictNum <= static_cast<uint64_t>(count) * kRestrictDen;
+        }
+        if (restricted) {
+            // (1') the column entries of the batch as keys.
+            const uint32_t per = (total0 + kGroups - 1) / kGroups;
+            const uint32_t c_begin = group * per;
+            const uint32_t c_end = (c_begin + per < total0) ? c_begin + per : total0;
+            if (c_begin < c_end) {
+                int r = owner(c_begin);
+                for (uint32_t c = c_begin; c < c_end; ++c) {
+                    while (c >= bt.prefix[r + 1])
+                        ++r;
+                    const uint32_t off0 = (c - bt.prefix[r]) * kChunk;
+                    const uint32_t len = bt.len[r];
+                    const int64_t base = int64_t(bt.start[r]);
+#pragma unroll
+                    for (int u = 0; u < kPerLane; ++u) {
+                        const uint32_t off = off0 + gl + u * kGroup;
+                        if (off < len && tab.claim_slot(j.col[base + off]) < 0)
+                            atomicAdd(j.overflow, 1ull);
+                    }
+                }
+            }
+            __syncthreads();
+            // (2') every visit added to its key when the key is present.
+            double x0 = 0.0;
+            for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
+                x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
+            x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
+            if (threadIdx.x == 0 && x0 != 0.0) {
+                const int sk = tab.locate(k);
+                if (sk >= 0)
+                    atomicAdd(&tab.vals[sk], x0);
+            }
+            for (int64_t i0 = nw + threadIdx.x; i0 < count; i0 += kVisits * int64_t(blockDim.x)) {
+                int32_t sv[kVisits];
+                double xv[kVisits];
+#pragma unroll
+                for (int u = 0; u < kVisits; ++u) {
+                    const int64_t i = i0 + int64_t(u) * blockDim.x;
+                    sv[u] = i < count ? st[i] : -1;
+                    xv[u] = i < count ? static_cast<double>(xs[i]) : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < kVisits; ++u) {
+                    const int sl = sv[u] >= 0 ? tab.locate(sv[u]) : -1;
+                    if (sl >= 0)
+                        atomicAdd(&tab.vals[sl], xv[u]);
+                }
+            }
+        } else if (nw == j.N) {
+            // (1) Q_k from all walks.  Step 0 of every walk sits at k: insert
+            // the sum of those visits once instead of N colliding atomic
+            // updates of one slot.
             double x0 = 0.0;
             for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
                 x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
@@ -314,6 +464,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                         atomicAdd(j.overflow, 1ull);
             }
         } else {
+            // (1) Q_k from walks [w0, w0 + nw).
             for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {
                 const int64_t t = i / nw;
                 const int64_t slot = t * j.N + w0 + (i - t * nw);
@@ -325,57 +476,20 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
         // (2) columns of the requested neighbours, kBatch neighbours at a time.
         for (uint32_t p0 = j.p_begin; p0 < j.p_end; p0 += kBatch) {
             const uint32_t m = (j.p_end - p0 < uint32_t(kBatch)) ? j.p_end - p0 : uint32_t(kBatch);
-            __syncthreads(); // table complete / previous batch flushed
-            uint32_t nchunks = 0;
-            if (threadIdx.x < kBatch) {
-                const int t = threadIdx.x;
-                bt.sum[t] = 0.0;
-                bt.row[t] = -1;
-                bt.len[t] = 0;
-                if (uint32_t(t) < m) {
-                    const int64_t e = int64_t(rk.x) + p0 + t;
-                    const int32_t i = j.col[e];
-                    bool take = !j.in_set || j.in_set[i];
-                    if constexpr (!WEIGHTED) {
-                        // Active hubs are summed by the walks instead.
-                        if (take && j.hub_act != 0u) {
-                            const uint32_t hx = j.hub_of[i];
-                            take = hx == kNoHub || ((j.hub_act >> hx) & 1u) == 0u;
-                        }
-                    }
-                    if (take) {
-                        const uint2 ri = j.node[i];
-                        nchunks = (ri.y + kChunk - 1) / kChunk;
-                        bt.start[t] = ri.x;
-                        bt.len[t] = ri.y;
-                        bt.row[t] = i;
-                        bt.aki[t] = j.scale * (WEIGHTED ? j.val[e] : 1.0);
-                    }
-                }
+            uint32_t total;
+            if (single) {
+                __syncthreads(); // table complete (the batch is already in bt)
+                total = total0;
+            } else {
+                total = setup_batch(p0, m);
             }
-            uint32_t total = 0;
-            const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
-            if (threadIdx.x < kBatch)
-                bt.prefix[threadIdx.x] = before;
-            if (threadIdx.x == 0)
-                bt.prefix[kBatch] = total;
-            __syncthreads();
             // Group g takes the contiguous chunk range [g*per, (g+1)*per) and
             // walks the neighbours forward, so the owner is searched once.
-            const int group = threadIdx.x / kGroup;
-            const int gl = threadIdx.x % kGroup;
             const uint32_t per = (total + kGroups - 1) / kGroups;
             const uint32_t c_begin = group * per;
             const uint32_t c_end = (c_begin + per < total) ? c_begin + per : total;
             if (c_begin < c_end) {
-                int r = 0, hi = kBatch;
-                while (hi - r > 1) {
-                    const int mid = (r + hi) >> 1;
-                    if (bt.prefix[mid] <= c_begin)
-                        r = mid;
-                    else
-                        hi = mid;
-                }
+                int r = owner(c_begin);
                 uint32_t next = bt.prefix[r + 1];
                 uint32_t len = bt.len[r];
                 int64_t base = int64_t(bt.start[r]);

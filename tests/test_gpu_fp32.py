@@ -86,3 +86,43 @@ def test_fp32_against_oracle_on_sampled_rows():
     pos = {int(r): i for i, r in enumerate(rows)}
     d_s = np.array([d32[pos[int(r)]] for r in sample])
     check_bound(d_s, od["d"], np.full(sample.size, c[0]), K, "diag vs oracle")
+
+
+@pytest.mark.timeout(900)
+def test_ba_four_million_full_size():
+    # The Barabasi-Albert configuration at full size: n = 4,000,000, m = 8
+    # (64M stored entries), exp(A/d_max), K = 40, N = 256; the full action and
+    # the diagonal on 1% of the rows, FP32 walk weights against FP64.  The
+    # FP32 paths equal the FP64 paths, every FP32 output is within the stated
+    # bound of its FP64 output, and the FP64 oracle recomputes 1,000 sampled
+    # rows of each (FP64 within 1e-10, FP32 within the bound).
+    csr = G.barabasi_albert(4_000_000, 8, seed=0)
+    K, N = 40, 256
+    s = 1.0 / csr.d_max
+    rows = G.random_rows(csr.n, csr.n // 100, seed=0)
+    with graph(csr) as g:
+        y64, da = run(g, "action", M.MCMF_PRECISION_FP64, csr.n, N, K, s, seed=1)
+        y32, db = run(g, "action", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s, seed=1)
+        assert np.array_equal(da, db)
+        d64, ea = run(g, "diag", M.MCMF_PRECISION_FP64, csr.n, N, K, s, rows=rows, seed=1)
+        d32, eb = run(g, "diag", M.MCMF_PRECISION_FP32_WEIGHTS, csr.n, N, K, s, rows=rows, seed=1)
+        assert np.array_equal(ea, eb)
+    c = oracle.coeffs(oracle.FN_EXP, K)
+    check_bound(y32, y64, c[0] + c[1] * s * csr.deg, K, "action FP32 vs FP64")
+    check_bound(d32, d64, np.full(len(rows), c[0]), K, "diag FP32 vs FP64")
+    pick = np.random.default_rng(3).choice(len(rows), 1000, replace=False)
+    sample = np.sort(rows[pick]).astype(np.int32)
+    oa = oracle.action(csr, oracle.FN_EXP, np.ones(csr.n), N=N, K=K, scale=s, seed=1, rows=sample,
+                       want_digest=True)
+    started = oa["digest"] != 0
+    assert np.array_equal(da[started].view(np.uint64), oa["digest"][started])
+    h = c[0] + c[1] * s * csr.deg[sample]
+    mc = oa["y"] - h
+    assert np.all(np.abs(y64[sample] - oa["y"]) <= 1e-10 * np.abs(mc) + 8 * np.finfo(float).eps * oa["y"])
+    check_bound(y32[sample], oa["y"], h, K, "action FP32 vs oracle")
+    od = oracle.diag(csr, oracle.FN_EXP, N=N, K=K, scale=s, seed=1, rows=sample, assume_symmetric=True)
+    pos = {int(r): i for i, r in enumerate(rows)}
+    at = np.array([pos[int(r)] for r in sample])
+    mcd = od["d"] - c[0]
+    assert np.all(np.abs(d64[at] - od["d"]) <= 1e-10 * np.abs(mcd) + 8 * np.finfo(float).eps * od["d"])
+    check_bound(d32[at], od["d"], np.full(sample.size, c[0]), K, "diag FP32 vs oracle")

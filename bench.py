@@ -140,7 +140,11 @@ def summarize(directory, probe_bytes):
                 a[0] += float(r["Counter_Value"])
                 a[1].add(r["Dispatch_Id"])
         lines.append("")
-        lines.append("| kernel | counter | dispatches | KiB per dispatch |")
+        # FETCH_SIZE and WRITE_SIZE read in KiB; the SQ_ counters are counts.
+        if all(c in ("FETCH_SIZE", "WRITE_SIZE") for _, c in agg):
+            lines.append("| kernel | counter | dispatches | KiB per dispatch |")
+        else:
+            lines.append("| kernel | counter | dispatches | per dispatch (KiB for FETCH_SIZE, WRITE_SIZE) |")
         lines.append("|---|---|---|---|")
         for (name, ctr), (tot, disp) in sorted(agg.items()):
             if any(f in name for f in list(KERNELS) + [COPY_KERNEL]):

@@ -208,8 +208,11 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
 
 /* Per-graph choices of the walk kernels and of the diagonal gather.  They
  * change memory traffic and the order of floating-point sums only: walk paths
- * and step counts never change.  Defaults: action VALUE with cached loads,
- * diag EDGE with cached loads, automatic hub threshold.
+ * and step counts never change.  Defaults: action VALUE with cached loads;
+ * diag ROW with cached loads when the column array and row records take at
+ * most 16 MiB (4 nnz + 8 n bytes; they then stay in cache), else EDGE with
+ * cached loads; automatic hub threshold.  The batched walks (mcmf_batch and
+ * the server) always use EDGE records, or value records for actions.
  *
  * Hub rows: a graph created unweighted with MCMF_SYMMETRIC and strictly
  * increasing columns in every row keeps its (at most 32) rows of largest

@@ -14,6 +14,9 @@ namespace mcmf {
 namespace {
 
 constexpr int kThreads = 256;
+// Column array plus row records up to which the diagonal walk defaults to
+// the ROW layout.
+constexpr int64_t kRowLayoutBytes = int64_t(16) << 20;
 
 int64_t grid_for(int64_t n, int threads = kThreads, int64_t cap = 1 << 20) {
     int64_t b = (n + threads - 1) / threads;
@@ -415,6 +418,13 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     MCMF_HIP(hipMemcpyAsync(&dmax, d_dmax.ptr, sizeof dmax, hipMemcpyDeviceToHost, s));
     MCMF_HIP(hipStreamSynchronize(s));
     g->d_max = static_cast<int64_t>(dmax);
+    // Default layout of the diagonal walk: while the column array and the
+    // row records are small enough to stay in cache, the ROW step (4-byte
+    // column, then the 8-byte row record) beats the 16-byte EDGE record.  On
+    // R-MAT graphs the walk was 23% faster with ROW at 8 MB of column array
+    // and row records, 6% at 16 MB, and 16% slower at 32 MB.
+    if (!g->weighted && 4 * nnz + 8 * n <= kRowLayoutBytes)
+        g->tuning.diag_sampler = MCMF_SAMPLER_ROW;
 
     // Rows with entries (walk start rows), then rows by length bin.
     DevBuf<int32_t> tmp_active;

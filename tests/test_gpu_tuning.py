@@ -145,3 +145,25 @@ def test_value_records_action_matches_edge_and_oracle(stream):
         r = gpu_action(g, "exp", v, N, K, ws, seed=4)
         o = oracle.action(wcsr, oracle_fn("exp"), v, N=N, K=K, scale=ws, seed=4)
         assert_close(r["y"], o["y"], 1e-10)
+
+
+def test_default_diag_layout_by_size():
+    """An unweighted graph whose column array and row records take at most
+    16 MiB starts with the ROW layout for the diagonal walk; a larger or a
+    weighted graph starts with EDGE.  The layouts give the same walks."""
+    small, big = G.rmat(12, seed=4), G.rmat(18, seed=0)
+    assert 4 * small.nnz + 8 * small.n <= (16 << 20) < 4 * big.nnz + 8 * big.n
+    K, N, s = 12, 32, 1.0 / small.d_max
+    with graph(small) as g:
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_ROW
+        r_row = gpu_diag(g, "exp", N, K, s, seed=5, want_digest=True)
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.diag_sampler = M.MCMF_SAMPLER_EDGE
+        M.mcmf_graph_set_tuning(g.handle, t)
+        r_edge = gpu_diag(g, "exp", N, K, s, seed=5, want_digest=True)
+        assert np.array_equal(r_row["digest"], r_edge["digest"])
+        assert_close(r_row["d"], r_edge["d"], 1e-12)
+    with graph(G.with_random_weights(small, seed=1)) as g:
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
+    with graph(big) as g:
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE

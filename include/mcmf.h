@@ -73,7 +73,7 @@ typedef enum {
     MCMF_E_NOT_SYMMETRIC = 3, /* diag needs A = A^T (C_i = R_i) */
     MCMF_E_NOMEM = 4,         /* device memory or the byte budget exhausted */
     MCMF_E_DEVICE = 5,        /* HIP runtime error or no usable device */
-    MCMF_E_UNSUPPORTED = 6    /* valid request outside what this build handles */
+    MCMF_E_UNSUPPORTED = 6    /* valid request outside what the library handles */
 } mcmf_status;
 
 /* Function family: coefficients c_k of f(x) = sum_k c_k x^k (Eq. power_series). */

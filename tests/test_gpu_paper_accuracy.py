@@ -55,6 +55,7 @@ def exact_diag_exp(csr, gamma):
 
 
 def test_smallworld19_diag_error_matches_paper_table():
+    """Error of the mean of 10 runs at N_s = 1e8, and the N_s^(-1/2) slope."""
     fx = load_fixture()
     n = int(fx["nodes"])
     csr = G.watts_strogatz(n, int(fx["neighbours"]), fx["rewire"], seed=0)
@@ -74,6 +75,17 @@ def test_smallworld19_diag_error_matches_paper_table():
             d = out.cpu().numpy()
             single.append(np.max(np.abs(d - ref)) / np.max(np.abs(ref)))
             acc += d
+        # Section 4.1: the error falls as N_s^(-1/2) (accuracy figure, slope
+        # about -0.5 in log-log).
+        sizes, errs = [], []
+        for ns in (10 ** 6, 10 ** 7):
+            opts = M.make_opts(seed=1, stream=s, weight_cutoff=fx["W_c"], allocation=M.MCMF_ALLOC_NORM)
+            M.mcmf_diag(g.handle, M.make_fn(M.MCMF_FN_EXP, gamma), None, 0, ns, 40, opts, out)
+            torch.cuda.synchronize()
+            sizes.append(ns)
+            errs.append(np.max(np.abs(out.cpu().numpy() - ref)) / np.max(np.abs(ref)))
+        sizes.append(int(fx["N_s"]))
+        errs.append(float(np.mean(single)))
     mean = acc / runs
     eps = np.max(np.abs(mean - ref)) / np.max(np.abs(ref))
     print(f"eps_r of the mean of {runs} runs {eps:.3e} (paper {fx['eps_r']:.2e}); "
@@ -81,3 +93,6 @@ def test_smallworld19_diag_error_matches_paper_table():
     # The max over 2^19 rows varies by a few percent between seed sets; the
     # other reading (error of a single run) would give about 3.2x the value.
     assert 0.8 * fx["eps_r"] <= eps <= 1.25 * fx["eps_r"]
+    slope = np.polyfit(np.log(sizes), np.log(errs), 1)[0]
+    print(f"error against N_s: {dict(zip(sizes, errs))}, slope {slope:.3f}")
+    assert -0.6 <= slope <= -0.4

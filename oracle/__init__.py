@@ -88,7 +88,7 @@ def _open(path: str):
     lib.oracle_diag.argtypes = [i64, P, P, P, P, cint, f64, i64, u64, u32, f64, P, i64, cint,
                                 cint, P, P, P, P]
     lib.oracle_diag.restype = cint
-    lib.oracle_allocation.argtypes = [i64, P, P, P, cint, P, i64, i64, P]
+    lib.oracle_allocation.argtypes = [i64, P, P, P, cint, P, i64, i64, cint, P]
     lib.oracle_allocation.restype = cint
     return lib
 
@@ -170,14 +170,15 @@ def _walks_array(walks, n):
     return w
 
 
-def allocation(g, Ns: int, starts, symmetric: bool = True):
+def allocation(g, Ns: int, starts, symmetric: bool = True, min_one: bool = False):
     """Walks per start row with p_k proportional to ||C_k||_2 (Eq.
-    initial_prob): N_k = max(1, round(Ns p_k)); int64[n], 0 off the starts."""
+    initial_prob): N_k = round(Ns p_k), which may be 0 (Algorithms 2-3), or
+    max(1, round(Ns p_k)) with ``min_one``; int64[n], 0 off the starts."""
     row_ptr, col, val = _csr_arrays(g)
     st = np.ascontiguousarray(starts, dtype=np.int32)
     out = np.zeros(max(g.n, 1), dtype=np.int64)
     _check(_load().oracle_allocation(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), 1 if symmetric else 0,
-                                     _ptr(st), st.size, int(Ns), _ptr(out)))
+                                     _ptr(st), st.size, int(Ns), 1 if min_one else 0, _ptr(out)))
     return out[:g.n]
 
 
@@ -189,7 +190,8 @@ def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request:
     ``fn``: FN_EXP, FN_RESOLVENT or an explicit coefficient array c_0..c_K.
     ``rows``: output rows (default all); walks start only where needed.
     ``expect``: exact expectation of the estimator instead of sampling.
-    ``walks``: walks per start row (int64[n]) instead of N for every row.
+    ``walks``: walks per start row (int64[n]) instead of N for every row; a
+    row given 0 starts no walk.
     """
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
@@ -215,7 +217,8 @@ def diag(g, fn, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int 
          cutoff: float = 0.0, rows=None, expect: bool = False, assume_symmetric: bool = False,
          want_digest: bool = False, walks=None):
     """RandFunmDiag.  Returns dict(d, digest, steps).  ``walks``: walks per
-    start row (int64[n]) instead of N for every row."""
+    start row (int64[n]) instead of N for every row; a row given 0 starts no
+    walk."""
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
     r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)

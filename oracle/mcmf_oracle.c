@@ -29,8 +29,11 @@
  *     (K-1 states, K-2 transitions), so that the expectation is exactly
  *     sum_{k<=K} c_k B^k.  W_0 = 1 and the 1/N of Algorithms 2-3 is applied
  *     once, at the end.
- *   - Every start row k with deg(k) > 0 gets exactly N walks (the paper's
- *     N_i ~ p_i N_s allocation is replaced by a fixed count per row).
+ *   - By default every start row k with deg(k) > 0 gets exactly N walks.
+ *     With an allocation (oracle_allocation) start row k gets N_k walks,
+ *     N_k = N_s P(l0 = k) rounded to the nearest integer as in Algorithms
+ *     2-3; a row with N_k = 0 starts no walk and adds nothing to Q or q, so
+ *     an output whose neighbourhood got no walks is exactly H (Section 4.1).
  *   - SelectNextState: a uniform 64-bit word u drives it.  An unweighted row
  *     (all stored values 1) takes index j = floor(u * deg / 2^64).  A
  *     weighted row takes the first j with u53 * rowabs < cum_j, where
@@ -402,14 +405,17 @@ int oracle_action(int64_t n, const int64_t *row_ptr, const int32_t *col, const d
         if (!start[k])
             continue;
         if (mode == 0) {
-            /* N walks from every start row, or walks[k] (Eq. initial_prob). */
+            /* N walks from every start row, or walks[k] (Eq. initial_prob);
+             * a row allocated no walk contributes q_k = 0. */
             const int64_t Nk = walks ? walks[k] : N;
             double sum = 0.0;
             uint32_t w;
-            if (Nk < 1) {
+            if (Nk < 0) {
                 rc = ORC_E_ARG;
                 goto done;
             }
+            if (Nk == 0)
+                continue;
             for (w = 0; w < (uint32_t)Nk; ++w) {
                 int cnt = walk(&g, &p, k, w, st, wt, &dg), t;
                 double a = 0.0;
@@ -587,10 +593,12 @@ int oracle_diag(int64_t n, const int64_t *row_ptr, const int32_t *col, const dou
         if (mode == 0) {
             uint32_t w;
             Nk = walks ? walks[k] : N;
-            if (Nk < 1) {
+            if (Nk < 0) {
                 rc = ORC_E_ARG;
                 goto done;
             }
+            if (Nk == 0)
+                continue; /* no walks: Q_k = 0 adds nothing */
             for (w = 0; w < (uint32_t)Nk; ++w) {
                 int cnt = walk(&g, &p, k, w, st, wt, &dg), t;
                 for (t = 0; t < cnt; ++t) {
@@ -652,17 +660,19 @@ done:
 
 /*
  * Walk allocation of Definition 1 (i) (Eq. initial_prob) with N_i = N_s p_i
- * as in Algorithms 2-3: p_k = ||C_k||_2 / sum over the start rows of ||C||_2,
- * and N_k = max(1, round(N_s p_k)) for every start row (one walk at least, so
- * each start row's term stays defined).  The column norms are summed in
- * column order: for symmetric A, C_k = R_k is summed along row k; otherwise
+ * as in Algorithms 2-3: p_k = ||C_k||_2 / sum over the start rows of ||C||_2
+ * and N_k = round(N_s p_k), half away from zero.  N_k may be 0: Algorithms
+ * 2-3 then run no walk from k (the regime of small N_s in Section 4.1).
+ * min_one != 0 instead gives every start row at least one walk (a variant of
+ * this library, not the paper's).  The column norms are summed in column
+ * order: for symmetric A, C_k = R_k is summed along row k; otherwise
  * (unweighted only) ||C_k||^2 is the number of entries in column k.  The
  * total runs over starts[] in the order given.  walks_out[k] (length n) is
  * set for the start rows and 0 elsewhere.
  */
 int oracle_allocation(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
                       int symmetric, const int32_t *starts, int64_t n_start, int64_t Ns,
-                      int64_t *walks_out)
+                      int min_one, int64_t *walks_out)
 {
     double *norm = NULL, total = 0.0;
     int64_t i, e;
@@ -699,8 +709,10 @@ int oracle_allocation(int64_t n, const int64_t *row_ptr, const int32_t *col, con
     }
     for (i = 0; i < n_start; ++i) {
         const int64_t k = starts[i];
-        int64_t w = total > 0.0 ? llround((double)Ns * (norm[k] / total)) : 1;
-        walks_out[k] = w < 1 ? 1 : w;
+        int64_t w = total > 0.0 ? llround((double)Ns * (norm[k] / total)) : 0;
+        if (min_one && w < 1)
+            w = 1;
+        walks_out[k] = w;
     }
     free(norm);
     return ORC_OK;

@@ -46,9 +46,14 @@ MUTATIONS = {
     "allocation by squared norms": ("norm[i] = sqrt(sq);", "norm[i] = sq;"),
     "allocation truncates": ("llround((double)Ns * (norm[k] / total))",
                              "(int64_t)((double)Ns * (norm[k] / total))"),
+    "allocation floors at one walk": ("if (min_one && w < 1)", "if (w < 1)"),
+    "philox multiplier of word 0": ("0xD2511F53u, 0xCD9E8D57u", "0xD2511F55u, 0xCD9E8D57u"),
+    "philox multiplier of word 2": ("0xD2511F53u, 0xCD9E8D57u", "0xD2511F53u, 0xCD9E8D59u"),
+    "philox multipliers swapped": ("0xD2511F53u, 0xCD9E8D57u", "0xCD9E8D57u, 0xD2511F53u"),
 }
 
 PINS = [
+    lambda orc: R.test_philox4x32_known_answers(orc),
     lambda orc: R.test_philox4x64_matches_numpy(orc),
     lambda orc: R.test_weighted_sampler_frequencies(orc),
     lambda orc: R.test_uniform_index_histogram(orc),
@@ -60,7 +65,8 @@ PINS = [
     lambda orc: P.test_unbiased(orc, "rmat"),
     lambda orc: P.test_complete_graph_exp_diag_closed_form(orc),
     lambda orc: P.test_error_decays_as_inverse_sqrt_N(orc),
-    lambda orc: P.test_allocation_follows_column_norms(orc, "weighted"),
+    lambda orc: P.test_allocation_follows_column_norms(orc, "weighted", False),
+    lambda orc: P.test_rows_without_walks_keep_only_H(orc),
 ]
 
 

@@ -348,9 +348,10 @@ def test_argument_errors(orc):
 # ------------------------------------------------------------------ walk allocation
 
 
-def _allocation_by_formula(A, starts, Ns):
-    """N_k = max(1, round-half-up(Ns ||C_k|| / sum over starts of ||C||)), with
-    column norms from the dense matrix (Eq. initial_prob)."""
+def _allocation_by_formula(A, starts, Ns, min_one=False):
+    """N_k = round-half-up(Ns ||C_k|| / sum over starts of ||C||), with column
+    norms from the dense matrix (Eq. initial_prob; Algorithms 2-3 use
+    N_i = N_s P(l0 = i), which may round to 0); max(1, .) with min_one."""
     import math
     norms = np.sqrt((np.asarray(A) ** 2).sum(axis=0))
     total = 0.0
@@ -358,12 +359,14 @@ def _allocation_by_formula(A, starts, Ns):
         total += norms[k]
     out = np.zeros(A.shape[0], dtype=np.int64)
     for k in starts:
-        out[k] = max(1, int(math.floor(Ns * (norms[k] / total) + 0.5)))
+        w = int(math.floor(Ns * (norms[k] / total) + 0.5))
+        out[k] = max(1, w) if min_one else w
     return out
 
 
+@pytest.mark.parametrize("min_one", [False, True])
 @pytest.mark.parametrize("which", ["weighted", "rmat", "directed"])
-def test_allocation_follows_column_norms(orc, which):
+def test_allocation_follows_column_norms(orc, which, min_one):
     if which == "weighted":
         g = G.with_random_weights(G.erdos_renyi_dense(60, 0.1, seed=4), seed=5, negative_fraction=0.4)
         sym = True
@@ -378,13 +381,57 @@ def test_allocation_follows_column_norms(orc, which):
         sym = False
     starts = np.nonzero(g.deg > 0)[0].astype(np.int32)
     for Ns in (1, 50, 5000, 123457):
-        got = orc.allocation(g, Ns, starts, symmetric=sym)
-        want = _allocation_by_formula(g.dense(), starts, Ns)
+        got = orc.allocation(g, Ns, starts, symmetric=sym, min_one=min_one)
+        want = _allocation_by_formula(g.dense(), starts, Ns, min_one)
         assert np.array_equal(got, want), (which, Ns)
-    # Every start row gets a walk, the rest none; the total is Ns up to rounding.
-    got = orc.allocation(g, 5000, starts, symmetric=sym)
-    assert np.all(got[starts] >= 1) and got.sum() - got[starts].sum() == 0
+    # Rows off the start list get none; the total is Ns up to one rounding
+    # per start row (plus the forced walks with min_one).
+    got = orc.allocation(g, 5000, starts, symmetric=sym, min_one=min_one)
+    assert got.sum() - got[starts].sum() == 0
     assert abs(int(got.sum()) - 5000) <= starts.size
+    small = orc.allocation(g, starts.size // 4, starts, symmetric=sym, min_one=min_one)
+    if min_one:
+        assert np.all(small[starts] >= 1)
+    else:
+        assert np.any(small[starts] == 0)  # N_s below the row count: some rows get none
+
+
+def _two_components():
+    """K_50 on nodes 0..49 next to the pair 50-51, node 50 with a self-loop."""
+    src, dst = np.triu_indices(50, k=1)
+    src = np.concatenate([src, [50, 50]])
+    dst = np.concatenate([dst, [51, 50]])
+    return G.from_edges(52, src, dst, keep_loops=True)
+
+
+def test_rows_without_walks_keep_only_H(orc):
+    # Section 4.1: with few walks a node whose neighbours started none keeps
+    # only the exact terms, SC(i) = c0 + c1 s a_ii and TC(i) = c0 v_i + c1 (sAv)_i.
+    # K_50 rows have norm 7, the pair's rows sqrt(2) and 1: with N_s = 100 the
+    # pair is allocated round(0.40) = round(0.28) = 0 walks, each K_50 row 2.
+    g = _two_components()
+    K, s = 8, 0.05
+    c = orc.coeffs(orc.FN_EXP, K)
+    starts = np.nonzero(g.deg > 0)[0].astype(np.int32)
+    walks = orc.allocation(g, 100, starts)
+    assert walks[50] == 0 and walks[51] == 0 and np.all(walks[:50] == 2)
+    d = orc.diag(g, c, N=1, K=K, scale=s, seed=2, walks=walks, want_digest=True)
+    assert d["d"][50] == c[0] + c[1] * (s * 1.0)
+    assert d["d"][51] == c[0]
+    assert np.all(d["d"][:50] > c[0])  # the K_50 rows did get walks
+    assert d["digest"][50] == 0 and d["digest"][51] == 0
+    assert d["steps"] == 50 * 2 * (K - 1)
+    v = np.linspace(0.5, 1.5, g.n)
+    y = orc.action(g, c, v, N=1, K=K, scale=s, seed=2, walks=walks, want_q=True)
+    for i, nb in ((50, v[50] + v[51]), (51, v[50])):
+        assert y["y"][i] == c[0] * v[i] + c[1] * (s * nb)
+    assert y["q"][50] == 0.0 and y["q"][51] == 0.0
+    # With one walk at least (min_one) the pair's rows get Monte Carlo terms.
+    w1 = orc.allocation(g, 100, starts, min_one=True)
+    assert w1[50] == 1 and w1[51] == 1
+    d1 = orc.diag(g, c, N=1, K=K, scale=s, seed=2, walks=w1)
+    assert d1["d"][50] > c[0] + c[1] * s and d1["d"][51] > c[0]
+    assert np.array_equal(d1["d"][:50], d["d"][:50])
 
 
 def test_per_row_walk_counts(orc):
@@ -414,5 +461,10 @@ def test_per_row_walk_counts(orc):
     assert r["steps"] == int(walks.sum()) * (K - 1)
     with pytest.raises(orc.OracleError):
         bad = walks.copy()
-        bad[starts[0]] = 0
+        bad[starts[0]] = -1
         orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, walks=bad)
+    # A row given no walk leaves q_k = 0 and starts nothing.
+    none = walks.copy()
+    none[starts[0]] = 0
+    r0 = orc.action(g, c, np.ones(g.n), N=1, K=K, scale=s, seed=11, walks=none, want_q=True)
+    assert r0["q"][starts[0]] == 0.0 and r0["steps"] == int(none.sum()) * (K - 1)

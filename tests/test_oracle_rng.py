@@ -6,9 +6,12 @@ the output permutation, the key schedule, the number of rounds) is pinned
 by instantiating the same round function at W = 64 and comparing with
 numpy's independent Philox4x64-10.  The Weyl key-schedule constants are
 pinned by their definitions (fractional parts of the golden ratio and of
-sqrt(3)).  The 32-bit variant used by the walks is then checked for
-uniformity and avalanche behaviour.
+sqrt(3)).  The 32-bit instance used by the walks, its two round multipliers
+included, is pinned by the published known-answer vectors of Philox4x32-10
+(tests/golden/philox4x32_10_kat.txt), and checked for uniformity and
+avalanche behaviour.
 """
+import os
 from decimal import Decimal, getcontext
 
 import numpy as np
@@ -26,6 +29,27 @@ def test_philox4x64_matches_numpy(orc):
         bg = np.random.Philox(counter=[int(ctr[0]) - 1, int(ctr[1]), int(ctr[2]), int(ctr[3])],
                               key=[int(key[0]), int(key[1])])
         assert np.array_equal(orc.philox4x64_10(ctr, key), bg.random_raw(4))
+
+
+KAT_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "philox4x32_10_kat.txt")
+
+
+def philox_kat_vectors():
+    """(counter, key, expected output) triples of the known-answer file."""
+    out = []
+    for line in open(KAT_FILE):
+        if line.strip() and not line.startswith("#"):
+            w = [int(x, 16) for x in line.split()]
+            out.append((w[0:4], w[4:6], w[6:10]))
+    return out
+
+
+def test_philox4x32_known_answers(orc):
+    kats = philox_kat_vectors()
+    assert len(kats) == 3
+    for ctr, key, want in kats:
+        got = [int(x) for x in orc.philox4x32_10(ctr, key)]
+        assert got == want, (ctr, key, [hex(x) for x in got])
 
 
 def _frac_bits(x: Decimal, bits: int) -> int:

@@ -61,22 +61,37 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_bytes(kind, st, K):
-    """Bytes each kernel must move:
-    action walk: 16 B edge record per transition + 8 B r per recorded state
-                 + 16 B per start row (row record, r, q out);
-    diag walk:   16 B edge record per transition + 12 B visit record written per state
-                 + 8 B per start row;
-    gather:      12 B visit record read per state + 4 B column entry per probe."""
+def algorithmic_bytes(kind, st, atomics=0):
+    """Bytes the method itself must move through HBM, per kernel (the
+    per-unit figures of the measurement plan):
+    action walk: 12 B per transition (the current row's record, 8 B, and the
+                 picked column, 4 B) + 8 B per recorded state (r at that state);
+    diag walk:   12 B per transition (Q_k itself accumulates on chip);
+    gather:      4 B per probed column entry + 8 B per FP64 atomic into d
+                 (one per requested neighbour of each start row)."""
     steps = st["walk_steps"]
     transitions = steps - st["walks"]
     if kind == "action_walk":
-        return 16 * transitions + 8 * steps + 16 * st["start_rows"]
+        return 12 * transitions + 8 * steps
     if kind == "diag_walk":
-        return 16 * transitions + 12 * steps + 8 * st["start_rows"]
+        return 12 * transitions
     if kind == "diag_gather":
-        return 12 * steps + 4 * st["gather_probes"]
+        return 4 * st["gather_probes"] + 8 * atomics
     raise ValueError(kind)
+
+
+def layout_bytes(kind, st):
+    """Bytes this implementation's data layout moves beyond the algorithmic
+    ones: the diagonal's visit records (12 B per recorded state, written by
+    the walk and read back by the gather) and the 4 B more of a 16-byte edge
+    record than the 12 B of row record and column per transition."""
+    steps = st["walk_steps"]
+    transitions = steps - st["walks"]
+    if kind == "diag_walk":
+        return 12 * steps + 4 * transitions
+    if kind == "diag_gather":
+        return 12 * steps
+    return 0
 
 
 # Kernel name fragment -> (roofline name, source file whose hash tags counter data).
@@ -198,11 +213,29 @@ def load_traffic(kernel):
     return None
 
 
+def host_cpu():
+    """Model name of the host CPU (lscpu), and the logical CPUs this process may use."""
+    import subprocess
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return model, len(os.sched_getaffinity(0)), os.cpu_count()
+
+
 def cpu_baseline(csr, queries, target_steps, K, N):
-    """The oracle, single-threaded, on a bounded sample: each query evaluated at
-    random non-isolated output rows (its walks start from their
-    neighbourhoods), rows added until one query's walks make about
-    `target_steps` steps.  Returns walk steps per second."""
+    """The oracle, single-threaded and pinned to one core, on a bounded
+    sample: each query evaluated at random non-isolated output rows (its walks
+    start from their neighbourhoods), rows added until one query's walks make
+    about `target_steps` steps.  Then the Erdos-Renyi G(1000, 0.01) workload
+    (exp(A), K = 30, N = 1000, full diagonal and full action) end to end.
+    Returns walk steps per second and the details."""
+    import graphgen as G
     import oracle
     rng = np.random.default_rng(123)
     cand = rng.permutation(np.nonzero(csr.deg > 0)[0])
@@ -218,19 +251,34 @@ def cpu_baseline(csr, queries, target_steps, K, N):
         if len(starts) * per_start >= target_steps:
             break
     sample = np.sort(np.array(picked, dtype=np.int32))
-    total_steps, total_s = 0, 0.0
-    for kind, fn, scale in queries:
+    before = os.sched_getaffinity(0)
+    core = min(before)
+    os.sched_setaffinity(0, {core})  # one core for the oracle (single thread)
+    try:
+        total_steps, total_s = 0, 0.0
+        for kind, fn, scale in queries:
+            t0 = time.perf_counter()
+            if kind == "action":
+                r = oracle.action(csr, fn, np.ones(csr.n), N=N, K=K, scale=scale, seed=1, rows=sample)
+            else:
+                r = oracle.diag(csr, fn, N=N, K=K, scale=scale, seed=1, rows=sample,
+                                assume_symmetric=True)
+            dt = time.perf_counter() - t0
+            total_steps += r["steps"]
+            total_s += dt
+            log(f"oracle {kind} fn={fn}: {r['steps']} steps in {dt:.2f} s")
+        er = G.erdos_renyi_dense(1000, 0.01, seed=0)
         t0 = time.perf_counter()
-        if kind == "action":
-            r = oracle.action(csr, fn, np.ones(csr.n), N=N, K=K, scale=scale, seed=1, rows=sample)
-        else:
-            r = oracle.diag(csr, fn, N=N, K=K, scale=scale, seed=1, rows=sample,
-                            assume_symmetric=True)
-        dt = time.perf_counter() - t0
-        total_steps += r["steps"]
-        total_s += dt
-        log(f"oracle {kind} fn={fn}: {r['steps']} steps in {dt:.2f} s")
-    return total_steps / total_s, total_steps, total_s, sample.size
+        ra = oracle.action(er, oracle.FN_EXP, np.ones(er.n), N=1000, K=30, scale=1.0, seed=1)
+        t1 = time.perf_counter()
+        rd = oracle.diag(er, oracle.FN_EXP, N=1000, K=30, scale=1.0, seed=1, assume_symmetric=True)
+        t2 = time.perf_counter()
+        log(f"oracle ER(1000, 0.01): action {t1 - t0:.2f} s, diag {t2 - t1:.2f} s")
+    finally:
+        os.sched_setaffinity(0, before)
+    er1000 = {"action_s": t1 - t0, "diag_s": t2 - t1,
+              "walk_steps_per_query": ra["steps"], "walk_steps_per_s": (ra["steps"] + rd["steps"]) / (t2 - t0)}
+    return total_steps / total_s, total_steps, total_s, sample.size, core, er1000
 
 
 # ------------------------------------------------------------------ batch / serve
@@ -525,6 +573,10 @@ def main():
     import graphgen as G
     from paper_2308_01037_amd import mcmf as M
 
+    def oracle_fn_kind(fname):
+        import oracle
+        return oracle.FN_EXP if fname == "exp" else oracle.FN_RESOLVENT
+
     assert torch.cuda.is_available(), "needs a GPU"
     K, N = args.K, args.walks
     t0 = time.time()
@@ -582,25 +634,9 @@ def main():
     total_steps = sum(r[2]["walk_steps"] for r in records)
     value = total_steps / elapsed
     lat = np.array([r[3] for r in records]) * 1e3
-    # Per-kernel device time and algorithmic bytes over the timed region.
-    kernels = {}
-    for what, fname, st, _ in records:
-        parts = [("action_walk", st["ms_walk"])] if what == "action" else \
-            [("diag_walk", st["ms_walk"]), ("diag_gather", st["ms_gather"])]
-        for kind, ms in parts:
-            k = kernels.setdefault(kind, {"ms": 0.0, "bytes": 0})
-            k["ms"] += ms
-            k["bytes"] += algorithmic_bytes(kind, st, K)
-    for kind, k in kernels.items():
-        k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
-        log(f"{kind}: {k['ms'] / args.steps:.1f} ms/step, {k['gbs']:.1f} GB/s algorithmic")
-    dominant = max(kernels, key=lambda kk: kernels[kk]["ms"])
-    dk = kernels[dominant]
-    alg_total = sum(k["bytes"] for k in kernels.values())
-    # Launches of the dominant kernel in the timed region (one per action query;
-    # one walk and one gather launch per visit-buffer chunk of a diagonal query).
-    # The library's visit buffer: MCMF_DIAG_CHUNK_BYTES, else 1/32 of device
-    # memory within [256 MiB, 8 GiB].
+    # Launches per query: one action walk; per diagonal query one walk and one
+    # gather launch per visit-buffer chunk.  The library's visit buffer:
+    # MCMF_DIAG_CHUNK_BYTES, else 1/32 of device memory within [256 MiB, 8 GiB].
     chunk_bytes = int(os.environ.get("MCMF_DIAG_CHUNK_BYTES", "0")) or min(
         8 << 30, max(256 << 20, torch.cuda.get_device_properties(0).total_memory // 32))
 
@@ -609,17 +645,30 @@ def main():
             return 1
         rows_per_chunk = max(1, (chunk_bytes // 12) // (N * (K - 1)))
         return -(-st["start_rows"] // rows_per_chunk)
-    def launches_of_kernel(kind):
-        return sum(launches_of(what, st) for what, _, st, _ in records
-                   if (what == "action") == (kind == "action_walk"))
-    launches = launches_of_kernel(dominant)
-    traffic = load_traffic(dominant)
-    # Fabric bytes per launch from the committed counters (while the sources
-    # match), over this run's time per launch: the walks' real traffic.
+
+    # Per-kernel device time (HIP events on the call's stream, summed by the
+    # library), launches and bytes over the timed region.  A full diagonal
+    # makes one FP64 atomic per requested neighbour of each start row: nnz.
+    kernels = {}
+    for what, fname, st, _ in records:
+        parts = [("action_walk", st["ms_walk"])] if what == "action" else \
+            [("diag_walk", st["ms_walk"]), ("diag_gather", st["ms_gather"])]
+        for kind, ms in parts:
+            k = kernels.setdefault(kind, {"ms": 0.0, "bytes": 0, "layout": 0, "launches": 0})
+            k["ms"] += ms
+            k["bytes"] += algorithmic_bytes(kind, st, atomics=csr.nnz)
+            k["layout"] += layout_bytes(kind, st)
+            k["launches"] += launches_of(what, st)
     for kind, k in kernels.items():
-        t = load_traffic(kind)
-        n_l = launches_of_kernel(kind)
-        k["gbs_counter"] = t / (k["ms"] / n_l * 1e-3) / 1e9 if t and n_l and k["ms"] > 0 else None
+        k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+        k["traffic"] = load_traffic(kind)  # counter bytes per launch, None if stale
+        k["per_launch"] = k["bytes"] / k["launches"]
+        k["ms_per_launch"] = k["ms"] / k["launches"]
+        log(f"{kind}: {k['ms'] / args.steps:.1f} ms/step, {k['launches']} launches, "
+            f"{k['gbs']:.1f} GB/s algorithmic ({k['gbs'] / HBM_PEAK_GBS:.3f} of peak)")
+    dominant = max(kernels, key=lambda kk: kernels[kk]["ms"])
+    dk = kernels[dominant]
+    alg_total = sum(k["bytes"] for k in kernels.values())
     if args.copy_probe_bytes:
         src = torch.ones(args.copy_probe_bytes // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -629,14 +678,19 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        oq = [(what, oracle.FN_EXP if fname == "exp" else oracle.FN_RESOLVENT,
-               beta if fname == "exp" else gamma) for what, fname, _, _ in queries]
-        rate, steps_c, secs, nrows = cpu_baseline(csr, oq, args.cpu_steps, K, N)
+        oq = [(what, oracle_fn_kind(fname), beta if fname == "exp" else gamma)
+              for what, fname, _, _ in queries]
+        rate, steps_c, secs, nrows, core, er1000 = cpu_baseline(csr, oq, args.cpu_steps, K, N)
+        model, allowed, logical = host_cpu()
         cpu = {"value": rate, "unit": "walk-steps/s", "cores": 1, "kind": "oracle",
                "sample": f"each of the {len(oq)} queries evaluated at {nrows} random non-isolated "
                          f"rows (walks from their neighbourhoods): {steps_c} walk steps in "
-                         f"{secs:.1f} s, single thread"}
+                         f"{secs:.1f} s, single thread pinned to logical CPU {core}",
+               "host_cpu": model, "host_logical_cpus": logical, "cpus_allowed": allowed,
+               "er1000_end_to_end": er1000}
+
+    def frac(k):
+        return k["gbs"] / HBM_PEAK_GBS
 
     result = {
         "metric": METRIC,
@@ -660,8 +714,15 @@ def main():
         "queries_per_s": len(records) / elapsed,
         "query_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "hbm_gbs_algorithmic": alg_total / elapsed / 1e9,
-        "kernels": {k: {"ms_per_step": v_["ms"] / args.steps, "gbs_algorithmic": v_["gbs"],
-                        "gbs_counter": v_["gbs_counter"]}
+        "kernels": {k: {"ms_per_step": v_["ms"] / args.steps,
+                        "launches_per_step": v_["launches"] / args.steps,
+                        "ms_per_launch": v_["ms_per_launch"],
+                        "algorithmic_bytes_per_launch": v_["per_launch"],
+                        "layout_bytes_per_launch": v_["layout"] / v_["launches"],
+                        "gbs_algorithmic": v_["gbs"], "frac": frac(v_),
+                        "traffic_bytes_per_launch": v_["traffic"],
+                        "traffic_over_algorithmic": (v_["traffic"] / v_["per_launch"]
+                                                     if v_["traffic"] else None)}
                     for k, v_ in kernels.items()},
         "roofline": {
             "kernel": dominant,
@@ -669,10 +730,11 @@ def main():
             "achieved": dk["gbs"],
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": dk["gbs"] / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "bytes_per_launch": dk["bytes"] / launches,
-            "ms_per_launch": dk["ms"] / launches,
+            "frac": frac(dk),
+            "traffic": dk["traffic"],
+            "bytes_per_launch": dk["per_launch"],
+            "ms_per_launch": dk["ms_per_launch"],
+            "launches": dk["launches"],
         },
         "cpu_baseline": cpu,
     }

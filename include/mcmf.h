@@ -115,15 +115,21 @@ typedef struct {
 /* Allocation of walks over the start rows.  MCMF_ALLOC_PER_ROW: n_walks
  * walks from every start row.  MCMF_ALLOC_NORM (Definition 1 (i), Eq.
  * initial_prob, with N_i = N_s P(l0 = i) of Algorithms 2-3): n_walks is the
- * total N_s; start row k gets N_k = max(1, round(N_s ||C_k||_2 / sum over the
- * start rows of ||C||_2)) walks, rounding half away from zero (one walk at
- * least keeps every start row's term defined).  Column norms: for a graph
- * created with MCMF_SYMMETRIC, ||C_k|| = ||R_k|| summed along row k in stored
- * order; otherwise (unweighted graphs only) ||C_k||^2 is the number of
- * entries in column k.  The total is summed over the start rows in ascending
- * order.  mcmf_diag and mcmf_action only (not mcmf_batch). */
+ * total N_s; start row k gets N_k = round(N_s ||C_k||_2 / sum over the start
+ * rows of ||C||_2) walks, rounding half away from zero.  N_k may be 0: such a
+ * row starts no walk and adds nothing to Q (diag) or q (action), so an output
+ * row whose whole neighbourhood got no walk is exactly c0 + c1 s a_ii (diag)
+ * or c0 v_i + c1 (sAv)_i (action), the small-N_s regime of Section 4.1.
+ * MCMF_ALLOC_NORM_MIN1 is the same with at least one walk per start row (a
+ * variant of this library, not the paper's: every start row's term is then
+ * estimated).  Column norms: for a graph created with MCMF_SYMMETRIC,
+ * ||C_k|| = ||R_k|| summed along row k in stored order; otherwise
+ * (unweighted graphs only) ||C_k||^2 is the number of entries in column k.
+ * The total is summed over the start rows in ascending order, on the host.
+ * mcmf_diag and mcmf_action only (not mcmf_batch). */
 #define MCMF_ALLOC_PER_ROW 0
 #define MCMF_ALLOC_NORM 1
+#define MCMF_ALLOC_NORM_MIN1 2
 
 typedef struct {
     uint64_t seed;          /* RNG key */
@@ -302,7 +308,11 @@ mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64
  * Errors: MCMF_E_ARG (null g/f/out, K out of range, n_walks < 1 with K >= 2,
  * n_rows < 0, a row outside [0, n), non-finite scale or coefficients,
  * n_coeffs < K+1, non-zero reserved words), MCMF_E_NOT_SYMMETRIC,
- * MCMF_E_NOMEM, MCMF_E_DEVICE.
+ * MCMF_E_NOMEM, MCMF_E_DEVICE.  MCMF_E_DEVICE also reports a lost insert
+ * into a Q_k table (an internal sizing error that the table plan rules
+ * out): a synchronising call reports its own; an asynchronous call records
+ * it on the graph, and the next synchronising mcmf_diag on that graph whose
+ * stream has passed the failing work returns it (and clears the record).
  */
 mcmf_status mcmf_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int64_t n_rows,
                       int64_t n_walks, int32_t K, const mcmf_opts *opts, double *out,

@@ -157,9 +157,10 @@ Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int3
             return fail(MCMF_E_ARG, "unknown precision %d", o->precision);
         if (!(o->weight_cutoff >= 0.0) || !std::isfinite(o->weight_cutoff))
             return fail(MCMF_E_ARG, "weight_cutoff must be finite and >= 0");
-        if (o->allocation != MCMF_ALLOC_PER_ROW && o->allocation != MCMF_ALLOC_NORM)
+        if (o->allocation != MCMF_ALLOC_PER_ROW && o->allocation != MCMF_ALLOC_NORM &&
+            o->allocation != MCMF_ALLOC_NORM_MIN1)
             return fail(MCMF_E_ARG, "unknown allocation %d", o->allocation);
-        if (o->allocation == MCMF_ALLOC_NORM && !g->symmetric && g->weighted)
+        if (o->allocation != MCMF_ALLOC_PER_ROW && !g->symmetric && g->weighted)
             return fail(MCMF_E_UNSUPPORTED,
                         "MCMF_ALLOC_NORM on a weighted graph needs one created with MCMF_SYMMETRIC");
     }
@@ -199,9 +200,11 @@ __global__ void k_start_norms(const int32_t *__restrict__ starts, int64_t n_star
 } // namespace
 
 Status allocate_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t Ns, int K,
-                      Allocation &A, hipStream_t s) {
-    A.host_walks.assign(static_cast<size_t>(n_start), 0);
-    A.host_rec.assign(static_cast<size_t>(n_start + 1), 0);
+                      bool min_one, Allocation &A, hipStream_t s) {
+    A.host_starts.clear();
+    A.host_walks.clear();
+    A.host_rec.assign(1, 0);
+    A.n_start = 0;
     A.total = 0;
     A.max_walks = 0;
     if (n_start == 0)
@@ -222,47 +225,64 @@ Status allocate_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_star
                        starts, n_start, g->node, g->val, g->symmetric ? nullptr : cnt.ptr, norms.ptr);
     MCMF_HIP(hipGetLastError());
     std::vector<double> hn(static_cast<size_t>(n_start));
+    std::vector<int32_t> hs(static_cast<size_t>(n_start));
     MCMF_HIP(hipMemcpyAsync(hn.data(), norms.ptr, sizeof(double) * n_start, hipMemcpyDeviceToHost, s));
+    MCMF_HIP(hipMemcpyAsync(hs.data(), starts, sizeof(int32_t) * n_start, hipMemcpyDeviceToHost, s));
     MCMF_HIP(hipStreamSynchronize(s));
     double total = 0.0;
     for (double x : hn)
         total = total + x;
+    // N_k = N_s p_k rounded half away from zero (Algorithms 2-3); a row
+    // rounded to 0 starts no walk and leaves the list.
     int64_t rec = 0;
     for (int64_t i = 0; i < n_start; ++i) {
-        int64_t w = total > 0.0 ? std::llround(static_cast<double>(Ns) * (hn[i] / total)) : 1;
-        w = std::max<int64_t>(w, 1);
+        int64_t w = total > 0.0 ? std::llround(static_cast<double>(Ns) * (hn[i] / total)) : 0;
+        if (min_one)
+            w = std::max<int64_t>(w, 1);
         if (w > (int64_t(1) << 31) - 1)
             return fail(MCMF_E_ARG, "MCMF_ALLOC_NORM gives a row %lld walks, above 2^31 - 1",
                         static_cast<long long>(w));
-        A.host_walks[i] = static_cast<int32_t>(w);
-        A.host_rec[i] = rec;
+        if (w <= 0)
+            continue;
+        A.host_starts.push_back(hs[i]);
+        A.host_walks.push_back(static_cast<int32_t>(w));
         rec += w * (K - 1);
+        A.host_rec.push_back(rec);
         A.total += w;
         A.max_walks = std::max(A.max_walks, w);
     }
-    A.host_rec[n_start] = rec;
-    MCMF_TRY(A.walks.alloc(n_start, s));
-    MCMF_TRY(A.rec.alloc(n_start + 1, s));
-    MCMF_HIP(hipMemcpyAsync(A.walks.ptr, A.host_walks.data(), sizeof(int32_t) * n_start,
+    A.n_start = static_cast<int64_t>(A.host_starts.size());
+    if (A.n_start == 0)
+        return {};
+    MCMF_TRY(A.starts.alloc(A.n_start, s));
+    MCMF_TRY(A.walks.alloc(A.n_start, s));
+    MCMF_TRY(A.rec.alloc(A.n_start + 1, s));
+    MCMF_HIP(hipMemcpyAsync(A.starts.ptr, A.host_starts.data(), sizeof(int32_t) * A.n_start,
                             hipMemcpyHostToDevice, s));
-    MCMF_HIP(hipMemcpyAsync(A.rec.ptr, A.host_rec.data(), sizeof(int64_t) * (n_start + 1),
+    MCMF_HIP(hipMemcpyAsync(A.walks.ptr, A.host_walks.data(), sizeof(int32_t) * A.n_start,
+                            hipMemcpyHostToDevice, s));
+    MCMF_HIP(hipMemcpyAsync(A.rec.ptr, A.host_rec.data(), sizeof(int64_t) * (A.n_start + 1),
                             hipMemcpyHostToDevice, s));
     // The host vectors must outlive the asynchronous copies.
     MCMF_HIP(hipStreamSynchronize(s));
     return {};
 }
 
-// walks_out: the walks per row (0 off the start rows).
+// walks_out: the walks per row (0 off the start rows).  Without an
+// allocation every row of starts[0..n_start) got N_uniform walks.
 Status write_walks_out(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t N_uniform,
                        const Allocation *A, int32_t *walks_out, hipStream_t s) {
-    std::vector<int32_t> hs(static_cast<size_t>(n_start));
-    if (n_start > 0) {
+    std::vector<int32_t> w(static_cast<size_t>(g->n), 0);
+    if (A) {
+        for (size_t i = 0; i < A->host_starts.size(); ++i)
+            w[static_cast<size_t>(A->host_starts[i])] = A->host_walks[i];
+    } else if (n_start > 0) {
+        std::vector<int32_t> hs(static_cast<size_t>(n_start));
         MCMF_HIP(hipMemcpyAsync(hs.data(), starts, sizeof(int32_t) * n_start, hipMemcpyDeviceToHost, s));
         MCMF_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < n_start; ++i)
+            w[static_cast<size_t>(hs[i])] = static_cast<int32_t>(N_uniform);
     }
-    std::vector<int32_t> w(static_cast<size_t>(g->n), 0);
-    for (int64_t i = 0; i < n_start; ++i)
-        w[static_cast<size_t>(hs[i])] = A ? A->host_walks[i] : static_cast<int32_t>(N_uniform);
     if (classify(walks_out) == Mem::Device) {
         if (g->n)
             MCMF_HIP(hipMemcpyAsync(walks_out, w.data(), sizeof(int32_t) * g->n, hipMemcpyHostToDevice, s));
@@ -367,19 +387,24 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
     MCMF_TRY(tm.mark(1));
     MCMF_TRY(spmv_r(g, vin.ptr, f->scale, rec.ptr, s));
     MCMF_TRY(tm.mark(2));
-    const bool by_norm = o && o->allocation == MCMF_ALLOC_NORM && K >= 2;
+    const bool by_norm = o && o->allocation != MCMF_ALLOC_PER_ROW && K >= 2;
     Allocation alloc;
-    if (by_norm)
-        MCMF_TRY(allocate_walks(g, g->active, g->n_active, N, K, alloc, s));
+    const int32_t *starts = g->active;
+    int64_t n_start = K >= 2 ? g->n_active : 0;
+    if (by_norm) {
+        MCMF_TRY(allocate_walks(g, g->active, g->n_active, N, K, o->allocation == MCMF_ALLOC_NORM_MIN1,
+                                alloc, s));
+        starts = alloc.starts.ptr;
+        n_start = alloc.n_start;
+    }
     if (K >= 2) {
         WalkParams p = walk_params(o, coef.ptr, K, f->scale, N);
         if (by_norm)
             p.row_walks = alloc.walks.ptr;
-        MCMF_TRY(action_walks(g, rec.ptr, g->active, g->n_active, p, qptr, dig.ptr, steps.ptr, s));
+        MCMF_TRY(action_walks(g, rec.ptr, starts, n_start, p, qptr, dig.ptr, steps.ptr, s));
     }
     if (o && o->walks_out)
-        MCMF_TRY(write_walks_out(g, g->active, K >= 2 ? g->n_active : 0, N, by_norm ? &alloc : nullptr,
-                                 o->walks_out, s));
+        MCMF_TRY(write_walks_out(g, starts, n_start, N, by_norm ? &alloc : nullptr, o->walks_out, s));
     MCMF_TRY(tm.mark(3));
     MCMF_TRY(spmv_assemble(g, vin.ptr, rec.ptr, K >= 2 ? qptr : nullptr, c[0], K >= 1 ? c[1] : 0.0,
                            f->scale, yout.ptr, s));
@@ -406,7 +431,7 @@ Status run_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_
         MCMF_HIP(hipStreamSynchronize(s));
     if (stats) {
         memset(stats, 0, sizeof *stats);
-        stats->start_rows = K >= 2 ? static_cast<uint64_t>(g->n_active) : 0;
+        stats->start_rows = static_cast<uint64_t>(n_start);
         stats->walks = by_norm ? static_cast<uint64_t>(alloc.total)
                                : stats->start_rows * static_cast<uint64_t>(K >= 2 ? N : 0);
         stats->walk_steps = nsteps;
@@ -490,10 +515,18 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         }
         starts = start_list.ptr;
     }
+    // Walks per start row by column norm: rows allocated none leave the list.
+    const bool by_norm = o && o->allocation != MCMF_ALLOC_PER_ROW && K >= 2;
+    Allocation alloc;
+    if (by_norm) {
+        MCMF_TRY(allocate_walks(g, starts, n_start, N, K, o->allocation == MCMF_ALLOC_NORM_MIN1, alloc, s));
+        starts = alloc.starts.ptr;
+        n_start = alloc.n_start;
+    }
     // Work items of the gather over the start list.
     DevBuf<int64_t> item_buf;
     const int64_t *item_off = g->active_items;
-    if (!all && K >= 2 && n_start > 0) {
+    if ((!all || by_norm) && K >= 2 && n_start > 0) {
         MCMF_TRY(item_buf.alloc(n_start + 1, s));
         MCMF_TRY(gather_items(g, starts, n_start, item_buf.ptr, s));
         item_off = item_buf.ptr;
@@ -508,10 +541,10 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     MCMF_TRY(tm.mark(1));
     float ms_walk = 0.f, ms_gather = 0.f;
     EventList chunk_events;
-    const bool by_norm = o && o->allocation == MCMF_ALLOC_NORM && K >= 2;
-    Allocation alloc;
-    if (by_norm)
-        MCMF_TRY(allocate_walks(g, starts, n_start, N, K, alloc, s));
+    // A call that returns before its work is done records a Q_k table
+    // overflow (a planning error) on the graph, for the next synchronising
+    // call to report; a synchronising call checks its own counter.
+    const bool sync = !(o && o->stream) || stats || dout.host || (digest && dig.host) || rv.host;
     if (o && o->walks_out)
         MCMF_TRY(write_walks_out(g, starts, K >= 2 ? n_start : 0, N, by_norm ? &alloc : nullptr,
                                  o->walks_out, s));
@@ -584,7 +617,7 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
                 MCMF_HIP(hipEventRecord(chunk_events[2 * ci + 1], s));
             MCMF_TRY(diag_gather(g, starts, item_off, c0, c0 + rows_here, p, vstate.ptr, vx.ptr,
                                  all ? nullptr : in_set.ptr, dacc.ptr, counters.ptr + 1,
-                                 counters.ptr + 2, queues.ptr + ci, s));
+                                 sync ? counters.ptr + 2 : g->async_overflow, queues.ptr + ci, s));
         }
         if (stats)
             MCMF_HIP(hipEventRecord(chunk_events.back(), s));
@@ -600,14 +633,21 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
     MCMF_TRY(dout.copy_back(out, count, s));
     if (digest)
         MCMF_TRY(dig.copy_back(digest, n, s));
-    unsigned long long hc[3] = {0, 0, 0};
-    const bool sync = !(o && o->stream) || stats || dout.host || (digest && dig.host) || rv.host;
-    if (sync)
+    unsigned long long hc[3] = {0, 0, 0}, earlier = 0;
+    if (sync) {
         MCMF_HIP(hipMemcpyAsync(hc, counters.ptr, sizeof hc, hipMemcpyDeviceToHost, s));
-    if (sync)
+        MCMF_HIP(hipMemcpyAsync(&earlier, g->async_overflow, sizeof earlier, hipMemcpyDeviceToHost, s));
         MCMF_HIP(hipStreamSynchronize(s));
+    }
     if (hc[2] != 0)
         return fail(MCMF_E_DEVICE, "internal error: a Q_k table overflowed (%llu inserts lost)", hc[2]);
+    if (earlier != 0) {
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(g->async_overflow), 0, 1, s));
+        MCMF_HIP(hipStreamSynchronize(s));
+        return fail(MCMF_E_DEVICE,
+                    "internal error: a Q_k table of an earlier asynchronous mcmf_diag on this graph "
+                    "overflowed (%llu inserts lost)", earlier);
+    }
     if (stats) {
         for (size_t e = 0; e + 1 < chunk_events.size(); ++e) {
             float t = 0.f;

@@ -184,5 +184,7 @@ struct mcmf_graph {
     int32_t *hub_rows = nullptr; // [kMaxHubs]
     uint32_t *hubmask = nullptr; // [n]
     uint8_t *hub_of = nullptr;   // [n]
-
+    // Q_k table overflows (lost inserts) of asynchronous diagonal calls on
+    // this graph; checked and cleared by its next synchronising call.
+    unsigned long long *async_overflow = nullptr; // [1]
 };

@@ -49,9 +49,6 @@ constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
 constexpr int kGroups = kGatherThreads / kGroup;
 constexpr int kSlots = 8;                  // slots per bucket
 constexpr int kVisits = 4;                 // visit records per thread in flight (table build)
-// A one-batch item keeps only its column entries in the table when its
-// column chunks hold at most visits * kRestrictDen / kRestrictNum entries.
-constexpr uint64_t kRestrictNum = 2, kRestrictDen = 1;
 constexpr int32_t kEmpty = -1;
 
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {

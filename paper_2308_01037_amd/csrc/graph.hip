@@ -269,6 +269,7 @@ void free_graph(mcmf_graph *g) {
     dev_free_sync(g->hubmask, sizeof(uint32_t) * g->n);
     dev_free_sync(g->hub_of, sizeof(uint8_t) * g->n);
     dev_free_sync(g->hub_rows, sizeof(int32_t) * kMaxHubs);
+    dev_free_sync(g->async_overflow, sizeof(unsigned long long));
     if (g->stream)
         (void)hipStreamDestroy(g->stream);
     delete g;
@@ -359,6 +360,8 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->node), sizeof(uint2) * n));
     MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->edge), sizeof(uint4) * nnz));
     MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->bin_rows), sizeof(int32_t) * n));
+    MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->async_overflow), sizeof(unsigned long long)));
+    MCMF_TRY(fill_impl<unsigned long long>(g->async_overflow, 0ull, 1, s));
 
     MCMF_TRY(copy_in(d_rp.ptr, row_ptr, sizeof(int64_t) * (n + 1), m_rp, s));
     MCMF_TRY(copy_in(g->col, col, sizeof(int32_t) * nnz, m_col, s));

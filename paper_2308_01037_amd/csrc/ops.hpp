@@ -103,17 +103,21 @@ Status diag_finish(const mcmf_graph *g, const int32_t *rows, int64_t count, int 
 Status check_common(const mcmf_graph *g, const mcmf_fn *f, int64_t n_walks, int32_t K,
                     const mcmf_opts *o);
 
-// Walks per start row of MCMF_ALLOC_NORM (device arrays for the kernels,
-// host copies for chunking and statistics).
+// Walks per start row of MCMF_ALLOC_NORM / MCMF_ALLOC_NORM_MIN1 (device
+// arrays for the kernels, host copies for chunking and statistics).  Only the
+// rows allocated at least one walk stay in the start list.
 struct Allocation {
-    DevBuf<int32_t> walks;          // per start row
-    DevBuf<int64_t> rec;            // first visit record per start row, n_start + 1
-    std::vector<int32_t> host_walks;
+    DevBuf<int32_t> starts;         // start rows with at least one walk, ascending
+    int64_t n_start = 0;
+    DevBuf<int32_t> walks;          // per row of that list
+    DevBuf<int64_t> rec;            // first visit record per row of the list, n_start + 1
+    std::vector<int32_t> host_starts, host_walks;
     std::vector<int64_t> host_rec;
     int64_t total = 0, max_walks = 0;
 };
+// N_k = round(Ns p_k) over starts[0..n_start) (min_one: at least 1 each).
 Status allocate_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t Ns, int K,
-                      Allocation &A, hipStream_t s);
+                      bool min_one, Allocation &A, hipStream_t s);
 Status write_walks_out(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t N_uniform,
                        const Allocation *A, int32_t *walks_out, hipStream_t s);
 WalkParams walk_params(const mcmf_opts *o, const double *coef, int K, double scale, int64_t N);

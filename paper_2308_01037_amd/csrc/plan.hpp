@@ -7,6 +7,12 @@
 
 namespace mcmf {
 
+// A one-batch gather item keeps only its column entries in the table when
+// its column chunks hold at most visits * kRestrictDen / kRestrictNum
+// entries; it then claims at most that many keys (and at most n), which the
+// plan's capacity covers whenever the whole row's walks fit one pass.
+constexpr uint64_t kRestrictNum = 2, kRestrictDen = 1;
+
 struct GatherPlan {
     int64_t cap;            // table slots (multiple of slots_per_bucket)
     int64_t walks_per_pass; // walks whose visits share one table fill

@@ -55,6 +55,7 @@ MCMF_PRECISION_FP32_WEIGHTS = 1
 
 MCMF_ALLOC_PER_ROW = 0
 MCMF_ALLOC_NORM = 1
+MCMF_ALLOC_NORM_MIN1 = 2
 
 MCMF_SAMPLER_EDGE = 0
 MCMF_SAMPLER_ROW = 1

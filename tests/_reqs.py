@@ -53,18 +53,19 @@ class Req:
         return {"x": out.cpu().numpy()[:self.count], "digest": dig.cpu().numpy().view(np.uint64),
                 "steps": st.walk_steps}
 
-    def make(self, host=False):
-        """The mcmf_request plus the buffers it writes."""
+    def make(self, host=False, digest=True):
+        """The mcmf_request plus the buffers it writes.  Without a path digest
+        an action on an unweighted graph walks over value records."""
         n = self.csr.n
         if host:
             vt = None if self.v is None else self.v.copy()
             rt = None if self.rows is None else np.asarray(self.rows, np.int32)
             out = np.full(max(self.count, 1), np.nan)
-            dig = np.zeros(n, dtype=np.uint64)
+            dig = np.zeros(n, dtype=np.uint64) if digest else None
         else:
             vt, rt = self._dev()
             out = torch.full((max(self.count, 1),), float("nan"), dtype=torch.float64, device="cuda")
-            dig = torch.zeros(n, dtype=torch.int64, device="cuda")
+            dig = torch.zeros(n, dtype=torch.int64, device="cuda") if digest else None
         r = M.make_request(self.kind, self.g.handle, fn_struct(self.fn, self.scale), self.K, self.N,
                            out, rows=rt, v=vt, seed=self.seed, request_id=self.request,
                            precision=self.precision, weight_cutoff=self.cutoff, path_digest=dig)
@@ -73,8 +74,19 @@ class Req:
     @staticmethod
     def fetch(out, dig, count):
         if isinstance(out, np.ndarray):
-            return {"x": out[:count].copy(), "digest": dig.copy()}
-        return {"x": out.cpu().numpy()[:count], "digest": dig.cpu().numpy().view(np.uint64)}
+            return {"x": out[:count].copy(), "digest": None if dig is None else dig.copy()}
+        return {"x": out.cpu().numpy()[:count],
+                "digest": None if dig is None else dig.cpu().numpy().view(np.uint64)}
+
+    def oracle(self):
+        """The oracle's result for this request (FP64, with path digests)."""
+        if self.kind == M.MCMF_REQ_ACTION:
+            o = oracle.action(self.csr, oracle_fn(self.fn), self.v, N=self.N, K=self.K, scale=self.scale,
+                              seed=self.seed, request=self.request, cutoff=self.cutoff, want_digest=True)
+            return {"x": o["y"], "digest": o["digest"], "steps": o["steps"]}
+        o = oracle.diag(self.csr, oracle_fn(self.fn), N=self.N, K=self.K, scale=self.scale, seed=self.seed,
+                        request=self.request, cutoff=self.cutoff, rows=self.rows, want_digest=True)
+        return {"x": o["d"], "digest": o["digest"], "steps": o["steps"]}
 
     def h(self):
         """The deterministic part c0 + c1 s a_ii (diag) or c0 v + c1 s A v (action)."""
@@ -89,8 +101,8 @@ class Req:
         return h if self.rows is None else h[np.asarray(self.rows)]
 
 
-def run_batch(reqs, host=False, use_graph=False, stream=True):
-    made = [q.make(host) for q in reqs]
+def run_batch(reqs, host=False, use_graph=False, stream=True, digest=True):
+    made = [q.make(host, digest) for q in reqs]
     o = M.mcmf_batch_opts()
     o.use_graph = 1 if use_graph else 0
     o.stream = torch.cuda.current_stream().cuda_stream if stream else None
@@ -115,6 +127,27 @@ def check_same(q, got, want, what):
     assert_close(got["x"], want["x"], RTOL, atol=1e-13 * np.max(np.abs(want["x"]), initial=0.0),
                  what=what)
     assert_mc_part_close(got["x"], want["x"], h, RTOL, what=what)
+
+
+def check_oracle(q, got, what=""):
+    """A request's result against the oracle: paths (when a digest was taken)
+    and step counts exact, FP64 estimates within 1e-10 relative (full value
+    and Monte Carlo part), FP32-weight estimates within the stated bound
+    2 K 2^-24 sum|terms| (sum|terms| is the Monte Carlo part on the
+    non-negative inputs these requests use)."""
+    o = q.oracle()
+    if got.get("digest") is not None:
+        assert np.array_equal(got["digest"], o["digest"]), f"{what}: walk paths differ"
+    if "steps" in got:
+        assert got["steps"] == o["steps"], what
+    h = q.h()
+    if q.precision == M.MCMF_PRECISION_FP32_WEIGHTS:
+        mc = np.abs(o["x"] - h)
+        bound = 2 * q.K * 2.0 ** -24 * mc + 4 * np.finfo(np.float64).eps * np.abs(o["x"]) + 1e-30
+        assert np.all(np.abs(got["x"] - o["x"]) <= bound), what
+        return
+    assert_close(got["x"], o["x"], RTOL, atol=1e-13 * np.max(np.abs(o["x"]), initial=0.0), what=what)
+    assert_mc_part_close(got["x"], o["x"], h, RTOL, what=what)
 
 
 def make_graphs():

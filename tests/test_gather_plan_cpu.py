@@ -1,7 +1,8 @@
 """The diagonal gather's table plan (csrc/plan.hpp), checked on the CPU over
 a sweep of graph sizes, walk counts, series lengths and LDS budgets: every
 pass must leave at least one empty slot (the probe sequences end at an empty
-slot) and fit the budget."""
+slot) and fit the budget, also for the restricted tables of small items,
+whose keys are column entries rather than visited states."""
 import os
 import subprocess
 
@@ -29,6 +30,14 @@ int main() {
         }
         long long v = p.walks_per_pass * (long long)(K - 1);
         long long d = v < n ? v : n;
+        // A restricted table (only when all N walks fit one pass) claims at
+        // most visits * Den / Num column entries as keys, and at most n.
+        if (p.walks_per_pass >= N) {
+            long long keys = (N * (long long)(K - 1) * (long long)mcmf::kRestrictDen) /
+                             (long long)mcmf::kRestrictNum;
+            if (keys > n) keys = n;
+            if (keys >= p.cap) { printf("FAIL restricted n=%lld N=%lld K=%d\n", n, N, K); return 1; }
+        }
         if (p.cap % 8 || p.cap <= p.distinct_max || d != p.distinct_max || p.walks_per_pass < 1 ||
             p.walks_per_pass > N || p.lds_bytes > b) {
             printf("FAIL n=%lld N=%lld K=%d b=%zu cap=%lld wpp=%lld d=%lld lds=%zu\n", n, N, K, b,

@@ -11,7 +11,6 @@ import numpy as np
 import pytest
 
 import graphgen as G
-import oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -19,8 +18,8 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from _gpu import assert_close, assert_mc_part_close, fn_struct, graph, oracle_fn  # noqa: E402
-from _reqs import RTOL, Req, check_same, close_graphs, make_graphs, run_batch  # noqa: E402
+from _gpu import fn_struct, graph  # noqa: E402
+from _reqs import Req, check_oracle, check_same, close_graphs, make_graphs, run_batch  # noqa: E402
 from _reqs import mixed_requests as _mixed  # noqa: E402
 from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
@@ -49,27 +48,24 @@ def test_mixed_batch_host_buffers_and_library_stream(graphs):
         check_same(q, g, w, f"request {i}")
 
 
-def test_batch_against_oracle(graphs):
+@pytest.mark.parametrize("digest", [True, False])
+def test_batch_against_oracle(graphs, digest):
+    # With digests the batched walks read edge records; without, the action
+    # requests on unweighted graphs walk over value records.
     g1, c1 = graphs["rmat11"]
     g4, c4 = graphs["weighted"]
     A, D = M.MCMF_REQ_ACTION, M.MCMF_REQ_DIAG
     reqs = [Req(g1, c1, D, "exp", 1.0 / c1.d_max, 40, 10, seed=9, request=2),
             Req(g4, c4, A, "resolvent", 0.1, 50, 9, seed=9, request=3),
-            Req(g1, c1, A, "exp", 1.0 / c1.d_max, 40, 10, seed=9, request=4, cutoff=1e-4)]
-    got, _ = run_batch(reqs)
-    for q, r in zip(reqs, got):
-        if q.kind == A:
-            o = oracle.action(q.csr, oracle_fn(q.fn), q.v, N=q.N, K=q.K, scale=q.scale, seed=q.seed,
-                              request=q.request, cutoff=q.cutoff, want_digest=True)
-            x = o["y"]
-        else:
-            o = oracle.diag(q.csr, oracle_fn(q.fn), N=q.N, K=q.K, scale=q.scale, seed=q.seed,
-                            request=q.request, cutoff=q.cutoff, rows=q.rows, want_digest=True)
-            x = o["d"]
-        assert np.array_equal(r["digest"], o["digest"])
-        assert r["steps"] == o["steps"]
-        assert_close(r["x"], x, RTOL, atol=1e-13 * np.max(np.abs(x)))
-        assert_mc_part_close(r["x"], x, q.h(), RTOL)
+            Req(g1, c1, A, "exp", 1.0 / c1.d_max, 40, 10, seed=9, request=4, cutoff=1e-4),
+            Req(g1, c1, A, "exp", 1.0 / c1.d_max, 256, 40, seed=9, request=5),
+            Req(g1, c1, A, "resolvent", 0.5 / c1.d_max, 193, 30, seed=9, request=6,
+                v=np.random.default_rng(4).random(c1.n)),
+            Req(g1, c1, A, "exp", 1.0 / c1.d_max, 256, 40, seed=9, request=7,
+                precision=M.MCMF_PRECISION_FP32_WEIGHTS)]
+    got, _ = run_batch(reqs, digest=digest)
+    for i, (q, r) in enumerate(zip(reqs, got)):
+        check_oracle(q, r, f"request {i}")
 
 
 def test_small_visit_chunks(graphs, monkeypatch):

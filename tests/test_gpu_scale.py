@@ -5,10 +5,14 @@
   of 20000 entries per row (the diagonal is the closed form on every walk).
 * The R-MAT scale-20 workload in the launch configuration the benchmark
   times: full diagonal and full action for exp(beta A), beta = 1/d_max, and
-  the resolvent with gamma = 0.85/lambda_max, K = 40, N = 256.  Sampled
-  output rows are recomputed by the oracle (it replays only the walks those
-  rows need) and must match to 1e-10 with bit-exact path digests; every
-  output must also satisfy x >= h (all terms are non-negative).  The sample
+  the resolvent with gamma = 0.85/lambda_max, K = 40, N = 256, without path
+  digests (so the action walks over value records and the diagonal runs the
+  digest-free walk kernel, as benchmarked).  Sampled output rows are
+  recomputed by the oracle (it replays only the walks those rows need) and
+  must match to 1e-10, on the full value and on the Monte Carlo part.  A
+  second pair of calls with path digests (edge-record kernels) must give
+  bit-exact paths against the oracle and the same estimates.  Every output
+  must also satisfy x >= h (all terms are non-negative).  The sample
   includes a hub row, whose diagonal the walk kernel sums.
 """
 import numpy as np
@@ -23,7 +27,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from _gpu import assert_close, gpu_action, gpu_diag, graph  # noqa: E402
+from _gpu import assert_close, assert_mc_part_close, gpu_action, gpu_diag, graph  # noqa: E402
 
 
 def test_torus_million_nodes_exact():
@@ -86,8 +90,12 @@ def test_rmat20_bench_configuration(rmat20, fn):
     scale = 1.0 / csr.d_max if fn == "exp" else 0.85 / lam
     rows = _sample_rows(csr, seed=5 if fn == "exp" else 6)
     with graph(csr) as g:
-        ra = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, want_digest=True, stats=True)
-        rd = gpu_diag(g, fn, N, K, scale, seed=1, want_digest=True, stats=True)
+        # As benchmarked: no digest (value-record action walk, digest-free diag walk).
+        ra = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, stats=True)
+        rd = gpu_diag(g, fn, N, K, scale, seed=1, stats=True)
+        # With path digests (edge-record walks).
+        ra_d = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, want_digest=True)
+        rd_d = gpu_diag(g, fn, N, K, scale, seed=1, want_digest=True)
     active = int(np.count_nonzero(csr.deg))
     assert ra["stats"]["walk_steps"] == active * N * (K - 1)
     assert rd["stats"]["walk_steps"] == active * N * (K - 1)
@@ -97,13 +105,20 @@ def test_rmat20_bench_configuration(rmat20, fn):
     od = oracle.diag(csr, ofn, N=N, K=K, scale=scale, seed=1, rows=rows, assume_symmetric=True,
                      want_digest=True)
     started = oa["digest"] != 0
-    assert np.array_equal(ra["digest"][started], oa["digest"][started])
+    assert np.array_equal(ra_d["digest"][started], oa["digest"][started])
     started = od["digest"] != 0
-    assert np.array_equal(rd["digest"][started], od["digest"][started])
-    assert_close(ra["y"][rows], oa["y"], 1e-10, what="action sample")
-    assert_close(rd["d"][rows], od["d"], 1e-10, what="diag sample")
-    # Every term of the series is non-negative here: x >= h = c0 v + c1 s A v.
+    assert np.array_equal(rd_d["digest"][started], od["digest"][started])
     c = oracle.coeffs(ofn, K)
     h_action = c[0] + c[1] * scale * csr.deg
+    for y, what in ((ra["y"], "action (value records)"), (ra_d["y"], "action (edge records)")):
+        assert_close(y[rows], oa["y"], 1e-10, what=what)
+        assert_mc_part_close(y[rows], oa["y"], h_action[rows], 1e-10, what=what)
+    for d, what in ((rd["d"], "diag"), (rd_d["d"], "diag (digest)")):
+        assert_close(d[rows], od["d"], 1e-10, what=what)
+        assert_mc_part_close(d[rows], od["d"], np.full(rows.size, c[0]), 1e-10, what=what)
+    # The two kernels of each query agree on every output.
+    assert_close(ra["y"], ra_d["y"], 1e-12, what="action kernels")
+    assert_close(rd["d"], rd_d["d"], 1e-12, what="diag kernels")
+    # Every term of the series is non-negative here: x >= h = c0 v + c1 s A v.
     assert np.all(np.isfinite(ra["y"])) and np.all(ra["y"] >= h_action * (1 - 1e-15))
     assert np.all(np.isfinite(rd["d"])) and np.all(rd["d"] >= c[0])

@@ -20,7 +20,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from _gpu import fn_struct, graph  # noqa: E402
-from _reqs import Req, check_same, close_graphs, make_graphs, mixed_requests  # noqa: E402
+from _reqs import Req, check_oracle, check_same, close_graphs, make_graphs, mixed_requests  # noqa: E402
 from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
 
@@ -38,10 +38,10 @@ def server(**kw):
     return M.mcmf_server_create(o)
 
 
-def serve(srv, reqs, threads=1, host=False):
+def serve(srv, reqs, threads=1, host=False, digest=True):
     """Submits reqs (from `threads` host threads), waits for all; returns the
     results in request order and the ticket infos."""
-    made = [q.make(host) for q in reqs]
+    made = [q.make(host, digest) for q in reqs]
     tickets = [None] * len(reqs)
 
     def submit(idx):
@@ -79,6 +79,31 @@ def test_served_mix_equals_single_calls(graphs):
     assert st["submitted"] == st["completed"] == len(reqs)
     assert st["largest_batch"] <= 5
     assert all(1 <= inf.batch_size <= 5 and inf.queue_ms >= 0 and inf.run_ms > 0 for inf in infos)
+
+
+@pytest.mark.parametrize("digest", [True, False])
+def test_served_requests_against_oracle(graphs, digest):
+    # Served diagonal (full and row subset) and action requests, in batches
+    # of up to three over two streams, against the oracle directly.  Without
+    # digests the actions walk over value records.
+    g1, c1 = graphs["rmat11"]
+    g2, c2 = graphs["er"]
+    A, D = M.MCMF_REQ_ACTION, M.MCMF_REQ_DIAG
+    rng = np.random.default_rng(8)
+    reqs = [Req(g1, c1, D, "exp", 1.0 / c1.d_max, 64, 20, seed=11, request=1),
+            Req(g1, c1, A, "exp", 1.0 / c1.d_max, 256, 40, seed=11, request=2),
+            Req(g2, c2, D, "resolvent", 0.05, 100, 15, seed=11, request=3,
+                rows=rng.choice(c2.n, 60, replace=False)),
+            Req(g2, c2, A, "resolvent", 0.05, 193, 15, seed=11, request=4, v=rng.random(c2.n)),
+            Req(g1, c1, D, "resolvent", 0.5 / c1.d_max, 32, 12, seed=11, request=5,
+                rows=np.arange(0, c1.n, 5), precision=M.MCMF_PRECISION_FP32_WEIGHTS)]
+    srv = server(n_streams=2, max_batch=3)
+    try:
+        got, infos = serve(srv, reqs, threads=2, digest=digest)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, r) in enumerate(zip(reqs, got)):
+        check_oracle(q, r, f"served request {i}")
 
 
 def test_host_buffers_and_hipgraph_batches(graphs):

@@ -339,6 +339,39 @@ mcmf_status mcmf_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows
 mcmf_status mcmf_action(const mcmf_graph *g, const mcmf_fn *f, const double *v, int64_t n_walks,
                         int32_t K, const mcmf_opts *opts, double *out, mcmf_stats *stats);
 
+/*
+ * mcmf_action_noalloc -- mcmf_action for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, and hosts that
+ * forbid allocation during a request.  It computes what mcmf_action computes
+ * (same walks, same estimate up to the order of floating-point additions)
+ * and calls no hipMalloc, hipFree or other allocating routine.
+ *
+ * Its temporaries (r = sAv, q, the coefficients: 16 n bytes + 32 KiB) live in
+ * one 64 MiB device array of the library, one copy per device, held until
+ * the process ends; its address is looked up once per device on the first
+ * call there.  Every call on a device shares that device's array and leaves
+ * its contents behind (each call writes what it reads first): calls that
+ * overlap on one device, on any streams or threads, race and give wrong
+ * results.  Order them on one stream or serialise them.
+ *
+ *   g, f, n_walks, K   as for mcmf_action; g has n <= MCMF_NOALLOC_MAX_ROWS
+ *   v, out             double[n] in device memory of the graph's device
+ *   opts               may be NULL; allocation must be MCMF_ALLOC_PER_ROW and
+ *                      walks_out NULL; path_digest and q_out, if given, in
+ *                      device memory.  stream NULL: the graph's stream, and
+ *                      the call returns when out is complete; otherwise the
+ *                      call is asynchronous on that stream.
+ *
+ * Walks use the graph's EDGE or ROW records (a VALUE tuning runs EDGE).
+ *
+ * Errors: those of mcmf_action; MCMF_E_ARG also when v, out, path_digest or
+ * q_out is host memory; MCMF_E_UNSUPPORTED when n exceeds
+ * MCMF_NOALLOC_MAX_ROWS, for another allocation mode or a walks_out array.
+ */
+#define MCMF_NOALLOC_MAX_ROWS 4192256LL /* (64 MiB - 32 KiB) / 16 */
+mcmf_status mcmf_action_noalloc(const mcmf_graph *g, const mcmf_fn *f, const double *v,
+                                int64_t n_walks, int32_t K, const mcmf_opts *opts, double *out);
+
 /* ------------------------------------------------------------------ */
 /* Batched execution                                                   */
 /* ------------------------------------------------------------------ */

@@ -19,7 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmcmf.so")
 
-SOURCES = ["runtime.hip", "graph.hip", "walk.hip", "action.hip", "gather.hip", "api.hip", "batch.hip", "server.hip", "tune.hip"]
+SOURCES = ["runtime.hip", "graph.hip", "walk.hip", "action.hip", "gather.hip", "api.hip", "batch.hip",
+           "server.hip", "tune.hip", "noalloc.hip"]
 HEADERS = ["common.hpp", "device.hpp", "ops.hpp", "plan.hpp", "walk_core.hpp", "gather_core.hpp"]
 
 ARCH = "gfx950"

@@ -161,6 +161,9 @@ _lib.mcmf_diag.restype = ctypes.c_int
 _lib.mcmf_action.argtypes = [_P, ctypes.POINTER(mcmf_fn), _P, ctypes.c_int64, ctypes.c_int32,
                              ctypes.POINTER(mcmf_opts), _P, ctypes.POINTER(mcmf_stats)]
 _lib.mcmf_action.restype = ctypes.c_int
+_lib.mcmf_action_noalloc.argtypes = [_P, ctypes.POINTER(mcmf_fn), _P, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.POINTER(mcmf_opts), _P]
+_lib.mcmf_action_noalloc.restype = ctypes.c_int
 _lib.mcmf_batch.argtypes = [ctypes.POINTER(mcmf_request), ctypes.c_int64,
                             ctypes.POINTER(mcmf_batch_opts), ctypes.POINTER(mcmf_stats)]
 _lib.mcmf_batch.restype = ctypes.c_int
@@ -187,7 +190,8 @@ _lib.mcmf_last_error.argtypes = []
 _lib.mcmf_last_error.restype = ctypes.c_char_p
 
 EXPORTED = ["mcmf_graph_create", "mcmf_graph_destroy", "mcmf_graph_info", "mcmf_diag",
-            "mcmf_action", "mcmf_batch", "mcmf_server_create", "mcmf_server_submit",
+            "mcmf_action", "mcmf_action_noalloc", "mcmf_batch", "mcmf_server_create",
+            "mcmf_server_submit",
             "mcmf_server_wait", "mcmf_server_query", "mcmf_server_destroy",
             "mcmf_graph_set_tuning", "mcmf_graph_get_tuning", "mcmf_tune",
             "mcmf_status_string", "mcmf_last_error"]
@@ -322,6 +326,17 @@ def mcmf_action(g: int, f: mcmf_fn, v, n_walks: int, K: int, opts: Optional[mcmf
     _raise(_lib.mcmf_action(g, ctypes.byref(f), _addr(v), n_walks, K,
                             ctypes.byref(opts) if opts is not None else None, _addr(out),
                             ctypes.byref(stats) if stats is not None else None))
+
+
+MCMF_NOALLOC_MAX_ROWS = 4192256
+
+
+def mcmf_action_noalloc(g: int, f: mcmf_fn, v, n_walks: int, K: int, opts: Optional[mcmf_opts],
+                        out) -> None:
+    _check_dtype(v, np.float64, "v")
+    _check_dtype(out, np.float64, "out")
+    _raise(_lib.mcmf_action_noalloc(g, ctypes.byref(f), _addr(v), n_walks, K,
+                                    ctypes.byref(opts) if opts is not None else None, _addr(out)))
 
 
 def make_request(kind: int, graph: int, fn: mcmf_fn, K: int, n_walks: int, out, *, rows=None,

@@ -1,0 +1,131 @@
+"""mcmf_action_noalloc against mcmf_action, through the C ABI.
+
+Two calls in a row share the library's scratch array, the second on a
+smaller graph; each must give mcmf_action's estimate (within 1e-10 relative
+on the value and on the Monte Carlo part), its q and its walks (bit-exact
+path digests).  Every library allocation is made to fail during the
+no-allocation calls (MCMF_TEST_FAIL_ALLOC=1), so an allocation would show as
+MCMF_E_NOMEM.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from _gpu import assert_close, assert_mc_part_close, fn_struct, graph  # noqa: E402
+from paper_2308_01037_amd import mcmf as M  # noqa: E402
+
+RTOL = 1e-10
+
+
+class _NoAlloc:
+    def __enter__(self):
+        self.old = os.environ.get("MCMF_TEST_FAIL_ALLOC")
+        os.environ["MCMF_TEST_FAIL_ALLOC"] = "1"
+
+    def __exit__(self, *exc):
+        if self.old is None:
+            del os.environ["MCMF_TEST_FAIL_ALLOC"]
+        else:
+            os.environ["MCMF_TEST_FAIL_ALLOC"] = self.old
+
+
+def _both(csr, fn, s, N, K, seed, request, digest):
+    """(noalloc, mcmf_action) results on the same arguments."""
+    n = csr.n
+    v = torch.as_tensor(G.uniform_vector(n, seed=seed + 1), device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = []
+    with graph(csr) as g:
+        for noalloc in (True, False):
+            out = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+            q = torch.full((n,), np.nan, dtype=torch.float64, device="cuda")
+            dig = torch.zeros(n, dtype=torch.int64, device="cuda") if digest else None
+            opts = M.make_opts(seed=seed, request_id=request, stream=stream, q_out=q, path_digest=dig)
+            f = fn_struct(fn, s)
+            if noalloc:
+                with _NoAlloc():
+                    M.mcmf_action_noalloc(g.handle, f, v, N, K, opts, out)
+            else:
+                M.mcmf_action(g.handle, f, v, N, K, opts, out)
+            torch.cuda.synchronize()
+            res.append({"y": out.cpu().numpy(), "q": q.cpu().numpy(),
+                        "digest": dig.cpu().numpy() if digest else None})
+        # c0 v + c1 s A v: the exact part, for the Monte Carlo comparison.
+        h = _exact_part(csr, fn, s, v.cpu().numpy())
+    return res, h
+
+
+def _exact_part(csr, fn, s, v):
+    c0, c1 = (1.0, 1.0)
+    if not isinstance(fn, str):
+        c0, c1 = float(fn[0]), float(fn[1])
+    av = np.zeros(csr.n)
+    for i in range(csr.n):
+        a, b = csr.row_ptr[i], csr.row_ptr[i + 1]
+        av[i] = v[csr.col[a:b]].sum()
+    return c0 * v + c1 * s * av
+
+
+def _check(res, h, what):
+    na, ref = res
+    assert np.all(np.isfinite(na["y"])), what
+    assert_close(na["y"], ref["y"], RTOL, what=f"{what}: y")
+    assert_mc_part_close(na["y"], ref["y"], h, RTOL, what=f"{what}: MC part")
+    assert_close(na["q"], ref["q"], RTOL, atol=1e-300, what=f"{what}: q")
+    if na["digest"] is not None:
+        assert np.array_equal(na["digest"], ref["digest"]), f"{what}: walks differ"
+
+
+def test_two_calls_second_smaller():
+    big = G.rmat(13, seed=5)
+    small = G.erdos_renyi_gnm(700, 3000, seed=6)
+    assert small.n < big.n
+    for csr, fn, s, N, K, digest, what in (
+            (big, "exp", 1.0 / big.d_max, 256, 40, False, "R-MAT 13, exp, value tuning"),
+            (small, "resolvent", 0.5 / small.d_max, 193, 21, True, "ER 700, resolvent, digest")):
+        res, h = _both(csr, fn, s, N, K, seed=11, request=2, digest=digest)
+        _check(res, h, what)
+
+
+def test_errors_and_small_K():
+    csr = G.rmat(8, seed=2)
+    n = csr.n
+    v = torch.ones(n, dtype=torch.float64, device="cuda")
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    with graph(csr) as g:
+        f = M.make_fn(M.MCMF_FN_EXP, 1.0 / csr.d_max)
+        with pytest.raises(M.MCMFError) as e:
+            M.mcmf_action_noalloc(g.handle, f, v.cpu(), 64, 10, None, out)
+        assert e.value.status == M.MCMF_E_ARG
+        with pytest.raises(M.MCMFError) as e:
+            M.mcmf_action_noalloc(g.handle, f, v, 64, 10, M.make_opts(allocation=M.MCMF_ALLOC_NORM), out)
+        assert e.value.status == M.MCMF_E_UNSUPPORTED
+        # K < 2: no walks; y = c0 v + c1 s A v exactly as mcmf_action gives it.
+        for K in (0, 1):
+            ref = torch.empty_like(out)
+            M.mcmf_action(g.handle, f, v, 64, K, None, ref)
+            with _NoAlloc():
+                M.mcmf_action_noalloc(g.handle, f, v, 64, K, None, out)
+            assert torch.equal(out, ref), K
+    # A graph above the limit is refused before any device work.
+    n_big = M.MCMF_NOALLOC_MAX_ROWS + 1
+    row_ptr = np.zeros(n_big + 1, dtype=np.int64)
+    col = np.zeros(0, dtype=np.int32)
+    h = M.mcmf_graph_create(n_big, row_ptr, col, None, M.MCMF_SYMMETRIC)
+    try:
+        vb = torch.ones(n_big, dtype=torch.float64, device="cuda")
+        ob = torch.empty_like(vb)
+        with pytest.raises(M.MCMFError) as e:
+            M.mcmf_action_noalloc(h, M.make_fn(M.MCMF_FN_EXP, 1.0), vb, 16, 10, None, ob)
+        assert e.value.status == M.MCMF_E_UNSUPPORTED
+    finally:
+        M.mcmf_graph_destroy(h)

@@ -55,6 +55,13 @@ def parse():
     ap.add_argument("--qps", type=float, default=0.0,
                     help="serve: arrival rate (0: the sequential path's measured capacity)")
     ap.add_argument("--seed", type=int, default=7, help="batch/serve: workload seed")
+    ap.add_argument("--batch-n-max", type=int, default=1024,
+                    help="batch: largest walks per start row the pilot may choose (the pilot asks "
+                         "up to 65536 for the grid and ER requests)")
+    ap.add_argument("--serve-scales", default="19,20,21,22,23,24,25,26",
+                    help="serve: R-MAT scales of the resident graphs (native generator)")
+    ap.add_argument("--no-compact", action="store_true",
+                    help="hotpath: skip the compact batched/served legs")
     ap.add_argument("--tune", metavar="CACHE",
                     help="hotpath: autotune the walk kernels first (mcmf_tune, outside the timed "
                          "region), caching the choice in the JSON file CACHE")
@@ -315,10 +322,11 @@ class Query:
                         self.N, self.K, opts, self.out)
 
 
-def pick_walks(M, torch, queries, n0=16, n_max=1024):
+def pick_walks(M, torch, queries, n0=16, n_min=32, n_max=65536):
     """Walks per start row from a pilot: two independent estimates with n0
-    walks give the estimator's spread se0 (relative to the estimate's rms);
-    N = n0 (se0 / target)^2, at most n_max."""
+    walks each (32 pilot walks per start row in all, on request ids apart from
+    the production ones) give the estimator's spread se0 (relative to the
+    estimate's rms); N = n0 (se0 / target)^2, clamped to [n_min, n_max]."""
     for q in queries:
         q.N = n0
     outs = [[torch.empty_like(q.out) for q in queries] for _ in range(2)]
@@ -330,7 +338,8 @@ def pick_walks(M, torch, queries, n0=16, n_max=1024):
         b = outs[1][i][:q.count].cpu().numpy()
         rms = float(np.sqrt(np.mean(a ** 2))) if q.count else 0.0
         se0 = float(np.sqrt(np.mean((a - b) ** 2) / 2.0)) / rms if rms > 0 else 0.0
-        q.N = int(min(n_max, max(1, np.ceil(n0 * (se0 / TARGET_SE) ** 2))))
+        q.N_pilot = int(max(n_min, np.ceil(n0 * (se0 / TARGET_SE) ** 2)))
+        q.N = int(min(n_max, q.N_pilot))
 
 
 def bench_batch(args):
@@ -367,7 +376,7 @@ def bench_batch(args):
         else:
             queries.append(Query(M, torch, g, csr, M.MCMF_REQ_ACTION, fn, scale, args.K,
                                  v=rng.random(csr.n), seed=args.seed, rid=i))
-    pick_walks(M, torch, queries)
+    pick_walks(M, torch, queries, n_max=args.batch_n_max)
     log("walks per row: " + " ".join(str(q.N) for q in queries))
     stream = torch.cuda.current_stream().cuda_stream
     reqs = [q.request() for q in queries]
@@ -389,11 +398,13 @@ def bench_batch(args):
     for name, fn in (("plain", plain), ("batched", lambda: batched(False)),
                      ("batched_graph", lambda: batched(True))):
         fn()  # warm-up
+        log(f"{name}: warm-up done")
         ts = []
         for _ in range(max(1, args.steps)):
             t = time.perf_counter()
             fn()
             ts.append(time.perf_counter() - t)
+            log(f"{name}: {ts[-1] * 1e3:.1f} ms")
         times[name] = float(np.median(ts))
         results[name] = [q.out[:q.count].cpu().numpy().copy() for q in queries]
         log(f"{name}: {times[name] * 1e3:.1f} ms for {n_req} requests")
@@ -410,7 +421,9 @@ def bench_batch(args):
                                "exp(A/d_max) or (I-0.85A/lambda_max)^-1, over ER (avg degree 10) "
                                "n=1e4/1e5/1e6, R-MAT 14/17/20 (ef 16), grid 1000x1000; "
                                f"K={args.K}; N per request from a pilot for std error {TARGET_SE}",
-                   "walks_per_row": [q.N for q in queries]},
+                   "walks_per_row": [q.N for q in queries],
+                   "walks_per_row_asked_by_pilot": [q.N_pilot for q in queries],
+                   "walks_per_row_cap": args.batch_n_max},
         "queries_per_s": {k: n_req / v for k, v in times.items()},
         "ms": {k: v * 1e3 for k, v in times.items()},
         "speedup_vs_plain": times["plain"] / times["batched_graph"],
@@ -419,58 +432,80 @@ def bench_batch(args):
     }
 
 
-def bench_serve(args):
-    """Resident R-MAT graphs, Poisson arrivals of diag requests whose row
-    counts are log-uniform in [1, 1e5]: the server (continuous batching,
-    budget admission) against one request at a time in arrival order."""
-    import threading
-    import torch
-    import graphgen as G
-    from paper_2308_01037_amd import mcmf as M
-    rng = np.random.default_rng(args.seed)
-    t0 = time.time()
-    scales = [17, 18, 18, 19, 19, 20, 20, 21]
-    graphs = []
-    csr_bytes = 0
-    for i, sc in enumerate(scales):
-        csr = G.rmat(sc, seed=100 + i)
-        csr_bytes += csr.nnz * 4 + (csr.n + 1) * 8
-        graphs.append((f"rmat{sc}", csr, M.Graph.from_csr(csr), G.lambda_max(csr, 30)))
-    log(f"{len(graphs)} graphs resident ({csr_bytes / 2**30:.2f} GiB of CSR, {time.time() - t0:.1f} s)")
-    n_req = args.requests or 200
-    N = 64
-    queries = []
+def lambda_max_device(M, torch, g, n, iters=50):
+    """Largest eigenvalue by power iteration from 1/sqrt(n) * 1, every product
+    A x taken by the library itself (mcmf_action with K = 1 and coefficients
+    (0, 1) returns A x): x <- A x / ||A x|| for iters - 1 steps, then
+    lambda = ||A x||_2."""
+    stream = torch.cuda.current_stream().cuda_stream
+    coeffs = np.array([0.0, 1.0])
+    f = M.make_fn(M.MCMF_FN_COEFFS, 1.0, coeffs=coeffs)
+    opts = M.make_opts(stream=stream)
+    x = torch.full((n,), 1.0 / np.sqrt(n), dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(iters - 1):
+        M.mcmf_action(g.handle, f, x, 1, 1, opts, y)
+        x = y / torch.linalg.norm(y)
+    M.mcmf_action(g.handle, f, x, 1, 1, opts, y)
+    return float(torch.linalg.norm(y))
+
+
+class GraphInfo:
+    """A resident graph of the serve workload: its handle and sizes (the host
+    CSR is dropped once the library holds its copy)."""
+
+    def __init__(self, name, scale, csr, g, lam):
+        self.name, self.scale, self.g, self.lam = name, scale, g, lam
+        self.n, self.nnz, self.d_max = csr.n, csr.nnz, csr.d_max
+
+
+def serve_requests(M, torch, graphs, n_req, rng, K, N, seed):
+    """The serve workload's request stream.  Each request is, with
+    probability 0.8, the diagonal on a row subset of a uniformly chosen graph
+    (row count log-uniform in [1, 1e5], rows uniform without repetition);
+    0.1, f(A)v with v ~ U(0,1) on a graph of scale <= 21; 0.1, the full
+    diagonal of a graph of scale <= 20.  f is exp(A/d_max) or
+    (I - 0.85 A/lambda_max)^-1 with probability 1/2 each."""
+    import types
+    full_ok = [g for g in graphs if g.scale <= 20] or graphs[:1]
+    act_ok = [g for g in graphs if g.scale <= 21] or graphs[:1]
+    queries, kinds = [], []
     for i in range(n_req):
-        name, csr, g, lam = graphs[rng.integers(len(graphs))]
+        u = rng.random()
+        pool = full_ok if u < 0.1 else (act_ok if u < 0.2 else graphs)
+        gi = pool[rng.integers(len(pool))]
         fn = M.MCMF_FN_EXP if rng.random() < 0.5 else M.MCMF_FN_RESOLVENT
-        scale = 1.0 / csr.d_max if fn == M.MCMF_FN_EXP else 0.85 / lam
-        count = int(min(csr.n, np.floor(np.exp(rng.uniform(0.0, np.log(1e5))))))
-        rows = np.sort(rng.choice(csr.n, max(1, count), replace=False))
-        q = Query(M, torch, g, csr, M.MCMF_REQ_DIAG, fn, scale, args.K, rows=rows, seed=args.seed, rid=i)
+        scale = 1.0 / gi.d_max if fn == M.MCMF_FN_EXP else 0.85 / gi.lam
+        shape = types.SimpleNamespace(n=gi.n)
+        if u < 0.1:
+            q = Query(M, torch, gi.g, shape, M.MCMF_REQ_DIAG, fn, scale, K, seed=seed, rid=i)
+            kinds.append(f"full diag rmat{gi.scale}")
+        elif u < 0.2:
+            q = Query(M, torch, gi.g, shape, M.MCMF_REQ_ACTION, fn, scale, K, v=rng.random(gi.n),
+                      seed=seed, rid=i)
+            kinds.append(f"f(A)v rmat{gi.scale}")
+        else:
+            count = int(min(gi.n, np.floor(np.exp(rng.uniform(0.0, np.log(1e5))))))
+            rows = np.sort(rng.choice(gi.n, max(1, count), replace=False))
+            q = Query(M, torch, gi.g, shape, M.MCMF_REQ_DIAG, fn, scale, K, rows=rows, seed=seed,
+                      rid=i)
+            kinds.append(f"{len(rows)} rows rmat{gi.scale}")
         q.N = N
         queries.append(q)
+    return queries, kinds
+
+
+def serve_run(M, torch, queries, loads, rng, opts):
+    """Each offered load: Poisson arrivals; the requests one at a time in
+    arrival order (plain), then the same arrivals through the server.
+    Latency is arrival to result; both paths run the same walks."""
+    import threading
+    n_req = len(queries)
     stream = torch.cuda.current_stream().cuda_stream
-    # Service times one at a time (also the warm-up), then the arrival rates.
-    svc = []
-    for q in queries:
-        t = time.perf_counter()
-        q.single(stream)
-        torch.cuda.synchronize()
-        svc.append(time.perf_counter() - t)
-    mean_svc = float(np.mean(svc))
-    log(f"mean sequential service {mean_svc * 1e3:.1f} ms")
-    loads = [args.qps] if args.qps else [1.0 / mean_svc, 2.0 / mean_svc]
     pct = lambda xs, p: float(np.percentile(xs, p) * 1e3)
-    o = M.mcmf_server_opts()
-    o.n_streams = 4
-    o.max_batch = 32
-    o.hbm_budget_bytes = 64 << 30
-    o.visit_chunk_bytes = 1 << 30
-    runs = []
-    worst = 0.0
+    runs, worst = [], 0.0
     for qps in loads:
         arrivals = np.cumsum(rng.exponential(1.0 / qps, n_req))
-        # Plain: one request at a time in arrival order.
         lat_plain = []
         start = time.perf_counter()
         for q, a in zip(queries, arrivals):
@@ -480,10 +515,11 @@ def bench_serve(args):
             q.single(stream)
             torch.cuda.synchronize()
             lat_plain.append(time.perf_counter() - start - a)
+            if len(lat_plain) % 20 == 0:
+                log(f"plain at {qps:.2f}/s: {len(lat_plain)}/{n_req} requests")
         span_plain = time.perf_counter() - start
         plain_out = [q.out[:q.count].cpu().numpy().copy() for q in queries]
-        # Served: submissions at the arrival times, completions waited in order.
-        srv = M.mcmf_server_create(o)
+        srv = M.mcmf_server_create(opts)
         reqs = [q.request() for q in queries]
         tickets = [None] * n_req
         submitted = [0.0] * n_req
@@ -495,6 +531,8 @@ def bench_serve(args):
                 while tickets[i] is None:
                     time.sleep(0.0002)
                 infos[i] = M.mcmf_server_wait(srv, tickets[i])
+                if (i + 1) % 20 == 0:
+                    log(f"served at {qps:.2f}/s: {i + 1}/{n_req} requests")
 
         th = threading.Thread(target=waiter)
         th.start()
@@ -509,8 +547,8 @@ def bench_serve(args):
         st = M.mcmf_server_query(srv)
         M.mcmf_server_destroy(srv)
         torch.cuda.synchronize()
-        # Latency of each request: arrival -> end of its batch (the server's
-        # own clock from submission on), whatever order completions are waited in.
+        # Served latency: arrival -> end of the request's batch (the server's
+        # own clock from submission on).
         lat_srv = [(sub - a) + (inf.queue_ms + inf.run_ms) * 1e-3
                    for sub, a, inf in zip(submitted, arrivals, infos)]
         for q, p in zip(queries, plain_out):
@@ -525,26 +563,162 @@ def bench_serve(args):
                           "peak_bytes_in_flight": st["peak_bytes_in_flight"]},
                "plain": {"requests_per_s": n_req / span_plain, "p50_ms": pct(lat_plain, 50),
                          "p99_ms": pct(lat_plain, 99)}}
-        log(f"offered {qps:.1f}/s: served {run['served']['requests_per_s']:.1f}/s p50 "
+        log(f"offered {qps:.2f}/s: served {run['served']['requests_per_s']:.2f}/s p50 "
             f"{run['served']['p50_ms']:.0f} ms p99 {run['served']['p99_ms']:.0f} ms | plain "
-            f"{run['plain']['requests_per_s']:.1f}/s p50 {run['plain']['p50_ms']:.0f} ms p99 "
+            f"{run['plain']['requests_per_s']:.2f}/s p50 {run['plain']['p50_ms']:.0f} ms p99 "
             f"{run['plain']['p99_ms']:.0f} ms")
         runs.append(run)
-    top = runs[-1]
+    return runs, worst
+
+
+def server_opts(M, torch, reserve_bytes=0):
+    o = M.mcmf_server_opts()
+    o.n_streams = 4
+    o.max_batch = 32
+    free_b, _ = torch.cuda.mem_get_info()
+    o.hbm_budget_bytes = int(max(1 << 30, (free_b - reserve_bytes) * 0.6))
+    o.visit_chunk_bytes = 1 << 30
+    return o
+
+
+def mean_service(torch, queries):
+    """Each request alone (also the warm-up); mean seconds per request."""
+    stream = torch.cuda.current_stream().cuda_stream
+    svc = []
+    for i, q in enumerate(queries):
+        t = time.perf_counter()
+        q.single(stream)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - t)
+        if (i + 1) % 10 == 0:
+            log(f"service times: {i + 1}/{len(queries)} requests")
+    return float(np.mean(svc)), svc
+
+
+def bench_serve(args):
+    """Resident R-MAT graphs (scales 19..26 by default), Poisson arrivals of
+    mixed requests (serve_requests), offered at 0.25 / 0.5 / 0.75 / 0.9 of
+    the plain path's capacity: the server (continuous batching, budget
+    admission) against one request at a time in arrival order."""
+    import torch
+    import graphgen as G
+    from paper_2308_01037_amd import mcmf as M
+    rng = np.random.default_rng(args.seed)
+    scales = [int(x) for x in args.serve_scales.split(",")]
+    graphs, csr_bytes = [], 0
+    t0 = time.time()
+    for i, sc in enumerate(scales):
+        t1 = time.time()
+        csr = G.rmat_native(sc, seed=100 + i)
+        gen_s = time.time() - t1
+        g = M.Graph.from_csr(csr, device=False)
+        lam = lambda_max_device(M, torch, g, csr.n)
+        csr_bytes += csr.nnz * 4 + (csr.n + 1) * 8
+        graphs.append(GraphInfo(f"rmat{sc}", sc, csr, g, lam))
+        log(f"rmat{sc}: n={csr.n} nnz={csr.nnz} d_max={csr.d_max} lambda_max={lam:.1f} "
+            f"(generated in {gen_s:.1f} s, resident after {time.time() - t1:.1f} s)")
+        del csr
+    free_b, total_b = torch.cuda.mem_get_info()
+    log(f"{len(graphs)} graphs resident: {csr_bytes / 2**30:.1f} GiB of CSR (int64 row_ptr, int32 col), "
+        f"{(total_b - free_b) / 2**30:.1f} GiB of device memory in use ({time.time() - t0:.0f} s)")
+    K, N = args.K, args.walks
+    n_req = args.requests or 80
+    queries, kinds = serve_requests(M, torch, graphs, n_req, rng, K, N, args.seed)
+    mean_svc, svc = mean_service(torch, queries)
+    cap = 1.0 / mean_svc
+    log(f"plain capacity {cap:.2f} requests/s (mean service {mean_svc * 1e3:.1f} ms, "
+        f"p50 {np.percentile(svc, 50) * 1e3:.1f} ms, max {max(svc) * 1e3:.0f} ms)")
+    fracs = [0.25, 0.5, 0.75, 0.9, 2.0] if not args.qps else [args.qps / cap]
+    o = server_opts(M, torch)
+    runs, worst = serve_run(M, torch, queries, [f * cap for f in fracs], rng, o)
+    for run, f in zip(runs, fracs):
+        run["offered_fraction_of_capacity"] = f
+    for gi in graphs:
+        gi.g.close()
     return {
         "metric": "served requests/s and p50/p99 latency vs plain sequential, equal walks per request",
-        "value": top["served"]["requests_per_s"], "unit": "requests/s", "n_gpus": 1,
+        "value": max(r["served"]["requests_per_s"] for r in runs), "unit": "requests/s", "n_gpus": 1,
         "higher_is_better": True, "data": "synthetic", "dtype": "f64",
         "config": {"workload": f"{len(scales)} resident R-MAT graphs (scales {scales}, ef 16, "
-                               f"{csr_bytes / 2**30:.2f} GiB CSR); {n_req} diag requests, rows "
-                               "log-uniform in [1, 1e5], exp(A/d_max) or (I-0.85A/lambda_max)^-1, "
-                               f"K={args.K}, N={N}; Poisson arrivals",
-                   "mean_sequential_service_ms": mean_svc * 1e3,
+                               f"{csr_bytes / 2**30:.1f} GiB CSR); {n_req} requests: 80% diag on "
+                               "row subsets (log-uniform in [1, 1e5] rows), 10% f(A)v (scale <= 21), "
+                               "10% full diag (scale <= 20); exp(A/d_max) or (I-0.85A/lambda_max)^-1; "
+                               f"K={K}, N={N}; Poisson arrivals",
+                   "request_kinds": kinds,
+                   "plain_capacity_rps": cap, "mean_sequential_service_ms": mean_svc * 1e3,
                    "server": {"n_streams": o.n_streams, "max_batch": o.max_batch,
                               "hbm_budget_bytes": o.hbm_budget_bytes,
                               "visit_chunk_bytes": o.visit_chunk_bytes}},
         "runs": runs,
         "max_rel_diff_served_vs_plain": worst,
+    }
+
+
+def compact_batch_and_serve(M, torch, G, g20, csr20, lam20, K, N, seed):
+    """The batched and served paths against the plain one, at a size that fits
+    the default run: 16 requests batched (one launch, hipGraph) vs one call
+    each; 48 requests served at 0.75 of the plain capacity vs one at a time.
+    The graphs: R-MAT 16, 17 and 18 (numpy generator, seeds 100..102) and the
+    R-MAT 20 graph of the main workload; N and K as there."""
+    rng = np.random.default_rng(seed)
+    graphs = []
+    for i, sc in enumerate((16, 17, 18)):
+        csr = G.rmat(sc, seed=100 + i)
+        g = M.Graph.from_csr(csr)
+        graphs.append(GraphInfo(f"rmat{sc}", sc, csr, g, G.lambda_max(csr, 50)))
+    graphs.append(GraphInfo("rmat20", 20, csr20, g20, lam20))
+    stream = torch.cuda.current_stream().cuda_stream
+    # Batched vs plain, 16 requests of the serve mix.
+    bq, _ = serve_requests(M, torch, graphs, 16, rng, K, N, seed)
+    reqs = [q.request() for q in bq]
+
+    def plain():
+        for q in bq:
+            q.single(stream)
+        torch.cuda.synchronize()
+
+    def batched():
+        o = M.mcmf_batch_opts()
+        o.stream = stream
+        o.use_graph = 1
+        M.mcmf_batch(reqs, o)
+        torch.cuda.synchronize()
+
+    bt = {}
+    outs = {}
+    for name, fn in (("plain", plain), ("batched", batched)):
+        fn()
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t)
+        bt[name] = float(np.median(ts))
+        outs[name] = [q.out[:q.count].cpu().numpy().copy() for q in bq]
+    bdiff = max((float(np.max(np.abs(a - b) / np.maximum(np.abs(a), 1e-300)))
+                 for a, b in zip(outs["plain"], outs["batched"]) if a.size), default=0.0)
+    log(f"compact batch: plain {bt['plain'] * 1e3:.0f} ms, batched {bt['batched'] * 1e3:.0f} ms")
+    # Served vs plain at 0.75 of the plain capacity.
+    sq, _ = serve_requests(M, torch, graphs, 48, rng, K, N, seed)
+    mean_svc, _ = mean_service(torch, sq)
+    runs, sdiff = serve_run(M, torch, sq, [0.75 / mean_svc], rng, server_opts(M, torch))
+    for gi in graphs[:3]:
+        gi.g.close()
+    r = runs[0]
+    return {
+        "batched": {"workload": "16 requests (80% diag on row subsets of 1..1e5 rows, 10% f(A)v, 10% "
+                                "full diag) over R-MAT 16/17/18/20, one hipGraph-launched batch vs one "
+                                "call per request, equal walks",
+                    "queries_per_s": 16 / bt["batched"], "plain_queries_per_s": 16 / bt["plain"],
+                    "speedup_vs_plain": bt["plain"] / bt["batched"], "max_rel_diff_vs_plain": bdiff},
+        "served": {"workload": "48 requests of the same mix, Poisson arrivals at 0.75 of the plain "
+                               "capacity, server (4 streams, budget admission) vs one at a time",
+                   "offered_qps": r["offered_qps"],
+                   "queries_per_s": r["served"]["requests_per_s"], "p50_ms": r["served"]["p50_ms"],
+                   "p99_ms": r["served"]["p99_ms"],
+                   "plain_queries_per_s": r["plain"]["requests_per_s"],
+                   "plain_p50_ms": r["plain"]["p50_ms"], "plain_p99_ms": r["plain"]["p99_ms"],
+                   "max_rel_diff_vs_plain": sdiff},
     }
 
 
@@ -676,6 +850,12 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.copy_probe_bytes} bytes done")
 
+    compact = None
+    if not args.no_compact and args.only == "all" and not args.copy_probe_bytes:
+        t_c = time.time()
+        compact = compact_batch_and_serve(M, torch, G, g, csr, lam, K, N, args.seed)
+        log(f"compact batched/served legs: {time.time() - t_c:.1f} s")
+
     cpu = None
     if not args.no_cpu_baseline:
         oq = [(what, oracle_fn_kind(fname), beta if fname == "exp" else gamma)
@@ -738,6 +918,8 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if compact is not None:
+        result.update(compact)
     if tuned is not None:
         result["tuning"] = tuned
     g.close()

@@ -33,7 +33,7 @@ __all__ = [
     "CSR", "from_edges", "erdos_renyi_dense", "erdos_renyi_gnm", "rmat",
     "grid2d", "torus2d", "complete", "complete_bipartite", "star", "path",
     "cycle", "circulant", "hypercube", "watts_strogatz", "with_random_weights",
-    "lambda_max", "ones", "uniform_vector", "random_rows", "barabasi_albert",
+    "lambda_max", "ones", "uniform_vector", "random_rows", "barabasi_albert", "rmat_native",
 ]
 
 
@@ -288,6 +288,13 @@ def uniform_vector(n: int, seed: int = 0) -> np.ndarray:
 def random_rows(n: int, count: int, seed: int = 0, replace: bool = False) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return rng.choice(n, size=count, replace=replace).astype(np.int32)
+
+
+def rmat_native(scale: int, edge_factor: int = 16, a: float = 0.57, b: float = 0.19,
+                c: float = 0.19, seed: int = 0, permute: bool = True) -> CSR:
+    """R-MAT by the multithreaded C generator (see :mod:`graphgen.rmatgen`)."""
+    from .rmatgen import rmat_native as _rmat_native
+    return _rmat_native(scale, edge_factor, a, b, c, seed, permute)
 
 
 def barabasi_albert(n: int, m: int = 8, seed: int = 0) -> CSR:

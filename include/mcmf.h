@@ -456,8 +456,9 @@ mcmf_status mcmf_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts
  * overlap on the device.  A batch completes as a unit, so requests join one
  * only while its estimated walk steps stay within max_batch_steps: a large
  * request runs on its own stream while small ones keep flowing on the
- * others.  Requests that arrive while batches run join the
- * next batch as slots and memory free up.  Results equal those of the
+ * others, and at most max_large_in_flight large requests share the device
+ * (so that large requests do not slow each other down).  Requests that
+ * arrive while batches run join the next batch as slots and memory free up.  Results equal those of the
  * request's own mcmf_diag / mcmf_action call up to the order of
  * floating-point additions (keyed walks).
  */
@@ -475,7 +476,11 @@ typedef struct {
     uint64_t max_batch_steps;   /* a batch takes further requests only while its estimated
                                    walk steps stay within this; a request above it runs
                                    alone; 0: 2^28 */
-    uint32_t reserved[6];       /* must be zero */
+    int32_t max_large_in_flight; /* most requests above max_batch_steps running at once,
+                                   1..n_streams; 0: 1.  A large request that would exceed
+                                   it waits, and the smaller requests queued behind it
+                                   are dispatched past it in arrival order */
+    uint32_t reserved[5];       /* must be zero */
 } mcmf_server_opts;
 
 typedef struct {
@@ -494,7 +499,8 @@ typedef struct {
     uint64_t peak_bytes_in_flight;  /* largest admission total so far */
     uint64_t peak_batches_in_flight;
     uint64_t largest_batch;
-    uint32_t reserved[8];
+    uint64_t peak_large_in_flight;  /* most requests above max_batch_steps run at once */
+    uint32_t reserved[6];
 } mcmf_server_stats;
 
 /*

@@ -2,10 +2,12 @@
 // memory budget, continuous batching over several streams.
 //
 // Threads: one dispatcher and one worker per stream slot.  The dispatcher
-// forms a batch from the head of the arrival queue whenever a slot is idle:
-// requests join while the batch's admission estimate fits the budget left
-// by the batches in flight (arrival order is kept; a request larger than the
-// whole budget runs alone once nothing else is in flight).  The slot's
+// forms a batch from the arrival queue whenever a slot is idle: requests join
+// while the batch's admission estimate fits the budget left by the batches
+// in flight (arrival order is kept; a request larger than the whole budget
+// runs alone once nothing else is in flight).  A request above
+// max_batch_steps runs alone, and while max_large_in_flight such requests
+// run, further large ones wait while the requests behind them go ahead.  The slot's
 // worker runs the batch with mcmf_batch on its own stream, then releases
 // the estimate and completes the tickets.  If a batch fails as a whole, its
 // requests are run again one at a time so that one failure stays with its
@@ -100,6 +102,7 @@ struct mcmf_server {
     uint64_t in_flight = 0;
     mcmf_server_stats stats = {};
     uint64_t batches_in_flight = 0;
+    int32_t large_in_flight = 0;
 
     struct Slot {
         hipStream_t stream = nullptr;
@@ -107,6 +110,7 @@ struct mcmf_server {
         std::vector<std::shared_ptr<mcmf::Ticket>> batch;
         uint64_t est = 0;
         bool busy = false;
+        bool large = false; // its batch is one request above max_batch_steps
     };
     std::vector<std::unique_ptr<Slot>> slots;
     std::condition_variable cv_slot; // a slot received a batch
@@ -191,9 +195,12 @@ void run_slot(mcmf_server *S, mcmf_server::Slot *slot) {
             S->stats.completed += batch.size();
             S->stats.bytes_in_flight = S->in_flight;
             --S->batches_in_flight;
+            if (slot->large)
+                --S->large_in_flight;
             slot->batch.clear();
             slot->est = 0;
             slot->busy = false;
+            slot->large = false;
         }
         S->cv_done.notify_all();
         S->cv_dispatch.notify_all();
@@ -217,11 +224,24 @@ void run_dispatcher(mcmf_server *S) {
             S->cv_dispatch.wait(lock);
             continue;
         }
-        // Form a batch from the head of the queue.
+        // Form a batch from the queue in arrival order.  A large request (above
+        // max_batch_steps: it runs alone) while max_large_in_flight of them
+        // already run is passed over, and so is everything when the head does
+        // not fit the memory budget; smaller requests behind a passed-over
+        // large one may go first.
         std::vector<std::shared_ptr<Ticket>> batch;
         uint64_t est = 0;
-        while (!S->queue.empty() && static_cast<int32_t>(batch.size()) < S->opts.max_batch) {
-            batch.push_back(S->queue.front());
+        bool large = false;
+        for (auto it = S->queue.begin(); it != S->queue.end() &&
+                                         static_cast<int32_t>(batch.size()) < S->opts.max_batch;) {
+            const bool big = (*it)->steps > S->opts.max_batch_steps;
+            if (big && (!batch.empty() || S->large_in_flight >= S->opts.max_large_in_flight)) {
+                if (!batch.empty())
+                    break; // a large request ends the batch (it runs alone)
+                ++it;
+                continue;
+            }
+            batch.push_back(*it);
             const uint64_t e = batch_estimate(batch, chunk);
             const bool fits = budget == 0 || S->in_flight + e <= budget;
             const bool alone = batch.size() == 1 && S->in_flight == 0;
@@ -233,12 +253,21 @@ void run_dispatcher(mcmf_server *S) {
                 break;
             }
             est = e;
-            S->queue.pop_front();
+            it = S->queue.erase(it);
+            if (big) {
+                large = true;
+                break;
+            }
         }
         if (batch.empty()) {
-            // The head does not fit next to the batches in flight: wait for one to end.
+            // Nothing can start next to the batches in flight: wait for one to end.
             S->cv_dispatch.wait(lock);
             continue;
+        }
+        if (large) {
+            ++S->large_in_flight;
+            S->stats.peak_large_in_flight =
+                std::max<uint64_t>(S->stats.peak_large_in_flight, static_cast<uint64_t>(S->large_in_flight));
         }
         S->in_flight += est;
         ++S->batches_in_flight;
@@ -250,6 +279,7 @@ void run_dispatcher(mcmf_server *S) {
         free_slot->batch = std::move(batch);
         free_slot->est = est;
         free_slot->busy = true;
+        free_slot->large = large;
         S->cv_slot.notify_all();
     }
     // Wake the workers so that they see the stop.
@@ -293,8 +323,12 @@ Status create_server(const mcmf_server_opts *o, mcmf_server **out) {
         op.visit_chunk_bytes = uint64_t(256) << 20;
     if (op.max_batch_steps == 0)
         op.max_batch_steps = uint64_t(1) << 28;
+    if (op.max_large_in_flight == 0)
+        op.max_large_in_flight = 1;
     if (op.n_streams < 1 || op.n_streams > 16)
         return fail(MCMF_E_ARG, "n_streams = %d outside 1..16", op.n_streams);
+    if (op.max_large_in_flight < 1 || op.max_large_in_flight > op.n_streams)
+        return fail(MCMF_E_ARG, "max_large_in_flight = %d outside 1..n_streams", op.max_large_in_flight);
     if (op.max_batch < 1)
         return fail(MCMF_E_ARG, "max_batch = %d is below 1", op.max_batch);
     if (op.use_graph != 0 && op.use_graph != 1)

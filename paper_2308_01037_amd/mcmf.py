@@ -125,7 +125,8 @@ class mcmf_server_opts(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("visit_chunk_bytes", ctypes.c_uint64),
                 ("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("device", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("max_batch_steps", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 6)]
+                ("max_batch_steps", ctypes.c_uint64), ("max_large_in_flight", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32 * 5)]
 
 
 class mcmf_ticket_info(ctypes.Structure):
@@ -142,7 +143,7 @@ class mcmf_server_stats(ctypes.Structure):
                 ("batches", ctypes.c_uint64), ("bytes_in_flight", ctypes.c_uint64),
                 ("peak_bytes_in_flight", ctypes.c_uint64),
                 ("peak_batches_in_flight", ctypes.c_uint64), ("largest_batch", ctypes.c_uint64),
-                ("reserved", ctypes.c_uint32 * 8)]
+                ("peak_large_in_flight", ctypes.c_uint64), ("reserved", ctypes.c_uint32 * 6)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}

@@ -151,6 +151,10 @@ def test_server_argument_errors_need_no_device():
     assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
     assert "n_streams" in M.mcmf_last_error()
     o = M.mcmf_server_opts()
+    o.n_streams, o.max_large_in_flight = 2, 3
+    assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
+    assert "max_large_in_flight" in M.mcmf_last_error()
+    o = M.mcmf_server_opts()
     o.max_batch = -1
     assert lib.mcmf_server_create(ctypes.byref(o), ctypes.byref(out)) == M.MCMF_E_ARG
     t = ctypes.c_uint64()

@@ -211,3 +211,23 @@ def test_batches_stay_small_and_step_bounds_hold(graphs):
             assert inf.est_steps >= r.walk_steps, (i, inf.est_steps, r.walk_steps)
         if inf.est_steps > 1:
             assert inf.batch_size == 1
+
+
+@pytest.mark.parametrize("limit", [1, 2])
+def test_large_requests_in_flight_are_limited(graphs, limit):
+    # With a one-step batch limit every request that walks is large and runs
+    # alone; at most `limit` of them run at once on the three streams, the
+    # small ones (K <= 1: no walk steps) pass the waiting large ones, and
+    # every result equals its single call.
+    reqs = mixed_requests(graphs)
+    want = [q.single() for q in reqs]
+    srv = server(n_streams=3, max_batch=4, max_batch_steps=1, max_large_in_flight=limit)
+    try:
+        got, infos = serve(srv, reqs * 2, threads=3)
+        st = M.mcmf_server_query(srv)
+    finally:
+        M.mcmf_server_destroy(srv)
+    for i, (q, g, w) in enumerate(zip(reqs * 2, got, want * 2)):
+        check_same(q, g, w, f"request {i}")
+    assert 1 <= st["peak_large_in_flight"] <= limit
+    assert st["completed"] == 2 * len(reqs)

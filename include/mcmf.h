@@ -62,7 +62,7 @@ extern "C" {
 #endif
 
 #define MCMF_VERSION_MAJOR 1
-#define MCMF_VERSION_MINOR 0
+#define MCMF_VERSION_MINOR 1
 
 typedef struct mcmf_graph mcmf_graph; /* opaque; owns its device copy of A */
 
@@ -249,6 +249,19 @@ typedef struct {
                                 ignored on input */
     double action_value_ms[2]; /* mcmf_tune only: ms of the VALUE action walk, index stream
                                   (0 when the graph cannot use it) */
+    int32_t walk_threads;    /* lanes per start row of the mcmf_diag / mcmf_action walks,
+                                64, 128 or 256 (each lane runs every walk_threads-th
+                                walk of the row); 0 = automatic, the walk count rounded
+                                up to 64 lanes, at most 256 */
+    int32_t gather_item;     /* neighbours of a start row per diagonal-gather work item
+                                (every item rebuilds Q_k, so larger items rebuild less
+                                and spread a high-degree row over fewer workgroups),
+                                64..4096; 0 = 256 */
+    double walk_threads_ms[3]; /* mcmf_tune only: ms of the diag walk at 64/128/256 lanes */
+    double gather_item_ms[4];  /* mcmf_tune only: ms of the diagonal gather at items of
+                                  128/256/512/1024 neighbours */
+    double hub_ms[2];          /* mcmf_tune only: ms of diag walk + gather with hub sums at
+                                  the automatic threshold / off (0 without hubs) */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the
@@ -257,12 +270,16 @@ mcmf_status mcmf_graph_set_tuning(mcmf_graph *g, const mcmf_tuning *t);
 mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t);
 
 /*
- * mcmf_tune -- the autotuner: times every sampler layout and load policy of
- * the action and diagonal walk kernels on a sample of the graph's rows (rows
- * with entries taken at an even stride, about 2^28 walk steps in all, with
- * the function, n_walks and K of the intended requests), keeps the fastest of
- * each and stores it in the graph (mcmf_graph_set_tuning).  out receives the
- * choice and the measured times.  The caller may cache the result by a
+ * mcmf_tune -- the autotuner.  On a sample of the graph's rows (rows with
+ * entries taken at an even stride, about 2^28 walk steps in all, with the
+ * function, n_walks and K of the intended requests) it times, in turn:
+ * every sampler layout and load policy of the action and diagonal walk
+ * kernels; the diagonal walk at 64, 128 and 256 lanes per start row; the
+ * diagonal gather (every neighbour of the sampled rows requested) at work
+ * items of 128, 256, 512 and 1024 neighbours; and, on graphs with hub rows,
+ * diagonal walk plus gather with hub sums at the automatic threshold and
+ * off.  It keeps the fastest of each and stores it in the graph
+ * (mcmf_graph_set_tuning).  out receives the choice and the measured times.  The caller may cache the result by a
  * fingerprint of the graph and reapply it with mcmf_graph_set_tuning.
  * Errors: as mcmf_action (K >= 2, n_walks >= 1 required), MCMF_E_NOMEM,
  * MCMF_E_DEVICE.

@@ -58,6 +58,7 @@ struct BReq {
     const uint4 *rec;          // action, value mode: this request's value records
     const uint8_t *hub_of;     // diag: hub index per node
     uint32_t hub_act;          // diag: hubs the walks sum (a.hub_act), left out of the probes
+    uint32_t item;             // diag: neighbours per gather work item (the graph's tuning)
 };
 
 // A run of one request's start rows inside a walk launch.  A task is one
@@ -333,8 +334,8 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         const uint2 rk = R.g.node[job.k];
         job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
                             static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
-        job.p_begin = part * kItem;
-        job.p_end = job.rk.y - job.p_begin < kItem ? job.rk.y : job.p_begin + kItem;
+        job.p_begin = part * R.item;
+        job.p_end = job.rk.y - job.p_begin < R.item ? job.rk.y : job.p_begin + R.item;
         job.st = vstate + sg.slot_base + rel * span;
         job.N = R.a.N;
         job.K = R.a.K;
@@ -560,6 +561,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.in_set = P.all ? nullptr : P.in_set.ptr;
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
+        B.item = gather_item(q.graph);
         if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kHubMinWalks) {
             // Hub rows: the walks sum them, the gather leaves them out.
             B.hub_of = q.graph->hub_of;

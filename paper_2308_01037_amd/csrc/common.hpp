@@ -130,6 +130,9 @@ int64_t default_visit_chunk_bytes();
 // Total memory of the current device (cached; 64 GiB if it cannot be read).
 uint64_t device_memory_bytes();
 
+// Neighbours per diagonal-gather work item when the tuning leaves it open.
+constexpr int32_t kDefaultGatherItem = 256;
+
 // Hub rows of the diagonal gather: at most one per bit of a 32-bit mask.
 constexpr int kMaxHubs = 32;
 constexpr uint8_t kNoHub = 0xFF;
@@ -172,7 +175,8 @@ struct mcmf_graph {
     int64_t bin_offset[3] = {0, 0, 0};
     size_t bytes = 0;
     // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
-    mcmf_tuning tuning = {MCMF_SAMPLER_VALUE, 0, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {0, 0}};
+    mcmf_tuning tuning = {MCMF_SAMPLER_VALUE, 0, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {0, 0},
+                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}};
     // Hub rows (unweighted symmetric graphs with strictly increasing rows):
     // the rows of largest degree, at most kMaxHubs.  hubmask[j] has bit h set
     // when j is a column of row hub_rows[h] (by symmetry: when j is adjacent

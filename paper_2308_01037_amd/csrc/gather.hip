@@ -13,10 +13,10 @@ namespace {
 using namespace gather;
 
 __global__ void k_item_counts(const int32_t *__restrict__ starts, int64_t n,
-                              const uint2 *__restrict__ node, uint32_t *__restrict__ cnt) {
+                              const uint2 *__restrict__ node, uint32_t item, uint32_t *__restrict__ cnt) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n)
-        cnt[i] = items_of(node[starts[i]].y);
+        cnt[i] = items_of(node[starts[i]].y, item);
 }
 
 // Exclusive prefix sums of cnt[0..n) into off[0..n], one workgroup of 1024
@@ -76,6 +76,7 @@ struct GatherArgs {
     unsigned long long *queue;
     const uint8_t *hub_of;
     uint32_t hub_act; // hubs the walks summed: left out of the probes
+    uint32_t item;    // neighbours per work item
 };
 
 template <bool WEIGHTED, class VT>
@@ -113,8 +114,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
         const uint2 rk = a.node[job.k];
         job.rk = make_uint2(static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.x))),
                             static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(rk.y))));
-        job.p_begin = part * kItem;
-        job.p_end = job.rk.y - job.p_begin < kItem ? job.rk.y : job.p_begin + kItem;
+        job.p_begin = part * a.item;
+        job.p_end = job.rk.y - job.p_begin < a.item ? job.rk.y : job.p_begin + a.item;
         int64_t rec = (kk - a.row_begin) * span;
         if (a.row_walks) {
             job.N = dev::uniform(static_cast<int64_t>(a.row_walks[kk]));
@@ -132,8 +133,19 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
 
 } // namespace
 
+uint32_t gather_item(const mcmf_graph *g) {
+    return static_cast<uint32_t>(g->tuning.gather_item > 0 ? g->tuning.gather_item : kDefaultGatherItem);
+}
+
+Status refresh_active_items(mcmf_graph *g) {
+    MCMF_HIP(hipSetDevice(g->device));
+    MCMF_TRY(gather_items(g, g->active, g->n_active, g->active_items, g->stream));
+    MCMF_HIP(hipStreamSynchronize(g->stream));
+    return {};
+}
+
 Status gather_items(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t *off,
-                    hipStream_t s) {
+                    hipStream_t s, uint32_t item) {
     if (n_start < 0)
         return fail(MCMF_E_ARG, "negative start-row count");
     DevBuf<uint32_t> cnt;
@@ -141,7 +153,7 @@ Status gather_items(const mcmf_graph *g, const int32_t *starts, int64_t n_start,
     if (n_start > 0) {
         const int64_t blocks = (n_start + 255) / 256;
         hipLaunchKernelGGL(k_item_counts, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, starts,
-                           n_start, g->node, cnt.ptr);
+                           n_start, g->node, item ? item : gather_item(g), cnt.ptr);
         MCMF_HIP(hipGetLastError());
     }
     hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(kScanThreads), 0, s, cnt.ptr, n_start, off);
@@ -176,6 +188,7 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.queue = queue;
     a.hub_of = g->hub_of;
     a.hub_act = p.hub_act;
+    a.item = p.gather_item ? p.gather_item : gather_item(g);
     const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, kMaxTableLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);
     if (!plan.ok)

@@ -42,7 +42,6 @@ constexpr int kWaves = kGatherThreads / 64;
 constexpr uint32_t kFilterLog2Words = 11; // 2048 words = 8 KiB
 constexpr uint32_t kFilterWords = 1u << kFilterLog2Words;
 constexpr int kBatch = 256;                // neighbours per batch
-constexpr uint32_t kItem = 256;            // neighbours per work item (a multiple of kBatch)
 constexpr int kGroup = 16;                 // lanes per chunk
 constexpr int kPerLane = 8;                // entries per lane per chunk
 constexpr int kChunk = kGroup * kPerLane;  // entries per chunk
@@ -542,12 +541,13 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
     }
 }
 
-// Work items.  A start row with d neighbours is cut into ceil(d / kItem)
-// items of at most kItem neighbours each; every item builds Q_k itself, so
-// the items of a high-degree row run on many workgroups at once.
-// item_off[kk] = first item of start row kk (exclusive prefix sums).
-__device__ __forceinline__ uint32_t items_of(uint32_t deg) {
-    return (deg + kItem - 1) / kItem;
+// Work items.  A start row with d neighbours is cut into ceil(d / item)
+// items of at most `item` neighbours each (the graph's tuning); every item
+// builds Q_k itself, so the items of a high-degree row run on many
+// workgroups at once.  item_off[kk] = first item of start row kk (exclusive
+// prefix sums).
+__device__ __forceinline__ uint32_t items_of(uint32_t deg, uint32_t item) {
+    return (deg + item - 1) / item;
 }
 
 // Start row kk in [lo, hi) with off[kk] <= item < off[kk + 1].

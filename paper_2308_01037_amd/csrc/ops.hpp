@@ -35,9 +35,12 @@ struct WalkParams {
     uint32_t request;
     double cutoff; // 0 = off
     int precision; // MCMF_PRECISION_*
-    // Sampler layout and load policy: -1 = the graph's tuning.
+    // Sampler layout, load policy and lanes per start row: -1 = the graph's tuning.
     int sampler = -1;
     int stream = -1;
+    int threads = -1;
+    // Neighbours per diagonal-gather work item: 0 = the graph's tuning.
+    uint32_t gather_item = 0;
     // Walks per start row (device, indexed like the start list passed to the
     // walk launcher) and the first visit record of each of those rows
     // (prefix sums of walks * (K-1)); null: n_walks for every row.
@@ -77,11 +80,18 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
                   int32_t *state, void *x, uint64_t *digest, unsigned long long *steps,
                   hipStream_t s);
 
+// Neighbours per diagonal-gather work item of the graph (its tuning).
+uint32_t gather_item(const mcmf_graph *g);
+
+// Recomputes the graph's work items of a full diagonal (after its tuning's
+// gather_item changed); synchronises the graph's stream.
+Status refresh_active_items(mcmf_graph *g);
+
 // Work items of the diag gather: off[kk] = first item of start row kk
-// (ceil(row length / 256) items per row), off[n_start] = total.  off has
-// n_start + 1 entries.
+// (ceil(row length / gather_item(g)) items per row), off[n_start] = total.
+// off has n_start + 1 entries.
 Status gather_items(const mcmf_graph *g, const int32_t *starts, int64_t n_start, int64_t *off,
-                    hipStream_t s);
+                    hipStream_t s, uint32_t item = 0);
 
 // Diag gather for start rows starts[row_begin..row_end) of a start list with
 // item offsets item_off (gather_items), whose visit records begin at

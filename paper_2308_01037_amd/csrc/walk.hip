@@ -160,10 +160,13 @@ __global__ void k_value_records(const uint4 *__restrict__ edge, int64_t nnz, con
     }
 }
 
-int walk_block(int64_t N) {
-    if (N >= 256)
-        return 256;
-    return static_cast<int>(((N + 63) / 64) * 64);
+// Lanes per start row: the walk count rounded up to whole wavefronts, at most
+// 256, or fewer when the tuning (or the call) asks for fewer.
+int walk_block(int64_t N, int threads) {
+    int b = N >= 256 ? 256 : static_cast<int>(((N + 63) / 64) * 64);
+    if (threads > 0 && threads < b)
+        b = threads;
+    return b;
 }
 
 // Workgroups loop over start rows, so the grid stays within the 32-bit
@@ -196,7 +199,8 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
         return {};
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
-    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks));
+    const int threads = p.threads >= 0 ? p.threads : g->tuning.walk_threads;
+    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks, threads));
     const int sampler = p.sampler >= 0 ? p.sampler : g->tuning.action_sampler;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.action_stream) != 0;
     if (sampler == MCMF_SAMPLER_VALUE && !g->weighted && !digest && value_records_fit(g)) {
@@ -238,7 +242,8 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
         return {};
     const WalkArgs a = walk::to_args(p);
     const GraphView gv = walk::view(g);
-    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks));
+    const int threads = p.threads >= 0 ? p.threads : g->tuning.walk_threads;
+    const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks, threads));
     const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_EDGE;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.diag_stream) != 0;
     walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,

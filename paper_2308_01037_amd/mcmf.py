@@ -91,14 +91,20 @@ class mcmf_tuning(ctypes.Structure):
                 ("diag_sampler", ctypes.c_int32), ("diag_stream", ctypes.c_int32),
                 ("action_ms", ctypes.c_double * 4), ("diag_ms", ctypes.c_double * 4),
                 ("sample_rows", ctypes.c_int64), ("hub_min_degree", ctypes.c_int32),
-                ("hub_count", ctypes.c_int32), ("action_value_ms", ctypes.c_double * 2)]
+                ("hub_count", ctypes.c_int32), ("action_value_ms", ctypes.c_double * 2),
+                ("walk_threads", ctypes.c_int32), ("gather_item", ctypes.c_int32),
+                ("walk_threads_ms", ctypes.c_double * 3), ("gather_item_ms", ctypes.c_double * 4),
+                ("hub_ms", ctypes.c_double * 2)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
                 "diag_sampler": self.diag_sampler, "diag_stream": self.diag_stream,
                 "action_ms": list(self.action_ms), "diag_ms": list(self.diag_ms),
                 "sample_rows": self.sample_rows, "hub_min_degree": self.hub_min_degree,
-                "hub_count": self.hub_count, "action_value_ms": list(self.action_value_ms)}
+                "hub_count": self.hub_count, "action_value_ms": list(self.action_value_ms),
+                "walk_threads": self.walk_threads, "gather_item": self.gather_item,
+                "walk_threads_ms": list(self.walk_threads_ms),
+                "gather_item_ms": list(self.gather_item_ms), "hub_ms": list(self.hub_ms)}
 
 
 MCMF_REQ_DIAG = 0

@@ -40,8 +40,10 @@ def autotune(graph, csr, fn: M.mcmf_fn, n_walks: int, K: int, cache_path: str) -
         d = cache[key]
         t = M.mcmf_graph_get_tuning(graph.handle)  # keeps the graph's other settings
         t.hub_count = 0
-        for name in ("action_sampler", "action_stream", "diag_sampler", "diag_stream"):
-            setattr(t, name, int(d[name]))
+        for name in ("action_sampler", "action_stream", "diag_sampler", "diag_stream",
+                     "walk_threads", "gather_item", "hub_min_degree"):
+            if name in d:
+                setattr(t, name, int(d[name]))
         M.mcmf_graph_set_tuning(graph.handle, t)
         return dict(d, cached=True)
     t = M.mcmf_tune(graph.handle, fn, n_walks, K)

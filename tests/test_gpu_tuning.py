@@ -1,6 +1,7 @@
-"""Walk-kernel tuning: every sampler layout and load policy gives the same
-walks (paths bit-exact against the oracle, estimates within 1e-10), and the
-autotuner (mcmf_tune) with its JSON cache picks and reapplies a choice."""
+"""Walk and gather tuning: every sampler layout, load policy, lane count per
+start row, gather work-item size and hub setting gives the same walks (paths
+bit-exact against the oracle, estimates within 1e-10), and the autotuner
+(mcmf_tune) with its JSON cache picks and reapplies a choice."""
 import numpy as np
 import pytest
 
@@ -64,6 +65,14 @@ def test_tuning_argument_errors():
         t.action_sampler = 3
         with pytest.raises(M.MCMFError):
             M.mcmf_graph_set_tuning(g.handle, t)
+        t = M.mcmf_tuning()
+        t.walk_threads = 100
+        with pytest.raises(M.MCMFError):
+            M.mcmf_graph_set_tuning(g.handle, t)
+        t = M.mcmf_tuning()
+        t.gather_item = 32
+        with pytest.raises(M.MCMFError):
+            M.mcmf_graph_set_tuning(g.handle, t)
         with pytest.raises(M.MCMFError):
             M.mcmf_tune(g.handle, M.make_fn(M.MCMF_FN_EXP, 0.5), 16, 1)
 
@@ -73,10 +82,26 @@ def test_autotune_measures_then_caches(tmp_path):
     path = str(tmp_path / "tune.json")
     f = M.make_fn(M.MCMF_FN_EXP, 1.0 / csr.d_max)
     with graph(csr) as g:
-        a = tuning.autotune(g, csr, f, 64, 20, path)
+        a = tuning.autotune(g, csr, f, 200, 20, path)
         assert not a["cached"] and a["sample_rows"] > 0
         assert all(ms > 0 for ms in a["action_ms"]) and all(ms > 0 for ms in a["diag_ms"])
         assert all(ms > 0 for ms in a["action_value_ms"])
+        assert all(ms > 0 for ms in a["walk_threads_ms"]) and all(ms > 0 for ms in a["gather_item_ms"])
+        # A choice other than the default (256 lanes, 256 neighbours) beats the
+        # default by more than 3%; the default stays unless one does.
+        lanes, items = [64, 128, 256], [128, 256, 512, 1024]
+        wt, gi = a["walk_threads_ms"], a["gather_item_ms"]
+        if a["walk_threads"] != 256:
+            assert wt[lanes.index(a["walk_threads"])] < 0.97 * wt[2]
+        else:
+            assert min(wt[:2]) >= 0.97 * wt[2]
+        if a["gather_item"] != 256:
+            assert gi[items.index(a["gather_item"])] == min(gi) < 0.97 * gi[1]
+        else:
+            assert min(gi) >= 0.97 * gi[1]
+        if a["hub_count"] > 0:
+            assert all(ms > 0 for ms in a["hub_ms"])
+            assert a["hub_min_degree"] == (0 if a["hub_ms"][0] <= a["hub_ms"][1] else 2**31 - 1)
         # The fastest of the four EDGE/ROW variants and the two VALUE ones.
         times = list(a["action_ms"]) + list(a["action_value_ms"])
         choice = [(v >> 1, v & 1) for v in range(4)] + [(M.MCMF_SAMPLER_VALUE, 0), (M.MCMF_SAMPLER_VALUE, 1)]
@@ -84,11 +109,13 @@ def test_autotune_measures_then_caches(tmp_path):
         t = M.mcmf_graph_get_tuning(g.handle)
         assert (t.diag_sampler, t.diag_stream) == (a["diag_sampler"], a["diag_stream"])
     with graph(csr) as g2:
-        b = tuning.autotune(g2, csr, f, 64, 20, path)
+        b = tuning.autotune(g2, csr, f, 200, 20, path)
         assert b["cached"]
         t = M.mcmf_graph_get_tuning(g2.handle)
         assert (t.action_sampler, t.action_stream, t.diag_sampler, t.diag_stream) == \
             (a["action_sampler"], a["action_stream"], a["diag_sampler"], a["diag_stream"])
+        assert (t.walk_threads, t.gather_item, t.hub_min_degree) == \
+            (a["walk_threads"], a["gather_item"], a["hub_min_degree"])
         # Tuned and default walks agree exactly.
         x = gpu_diag(g2, "exp", 32, 12, 1.0 / csr.d_max, seed=9, want_digest=True)
         set_tuning(g2, M.MCMF_SAMPLER_EDGE, 0)
@@ -167,3 +194,31 @@ def test_default_diag_layout_by_size():
         assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
     with graph(big) as g:
         assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
+
+
+@pytest.mark.parametrize("lanes,item,hubs", [(64, 64, 1), (128, 512, 2**31 - 1), (256, 4096, 1),
+                                             (64, 1000, 2**31 - 1)])
+def test_lanes_items_and_hubs_match_oracle(lanes, item, hubs):
+    # Lanes per start row, gather work-item size and hub sums change the order
+    # of sums only: digests exact, full and subset diagonals and the action
+    # within 1e-10 of the oracle.  N = 200 puts 4, 2 and 1 walks on a lane; a
+    # hub threshold of 1 sums every hub row in the walk, 2^31 - 1 none.
+    csr = G.rmat(11, seed=12)
+    K, N, s = 14, 200, 1.0 / csr.d_max
+    rows = np.random.default_rng(4).choice(csr.n, 300, replace=False)
+    with graph(csr) as g:
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.walk_threads, t.gather_item, t.hub_min_degree, t.hub_count = lanes, item, hubs, 0
+        M.mcmf_graph_set_tuning(g.handle, t)
+        t = M.mcmf_graph_get_tuning(g.handle)
+        assert (t.walk_threads, t.gather_item, t.hub_min_degree) == (lanes, item, hubs)
+        for sub in (None, rows):
+            o = oracle.diag(csr, oracle_fn("exp"), N=N, K=K, scale=s, seed=6, rows=sub, want_digest=True)
+            r = gpu_diag(g, "exp", N, K, s, seed=6, rows=sub, want_digest=True)
+            assert np.array_equal(r["digest"], o["digest"])
+            assert_close(r["d"], o["d"], 1e-10)
+        v = np.random.default_rng(5).random(csr.n)
+        o = oracle.action(csr, oracle_fn("resolvent"), v, N=N, K=K, scale=0.5 * s, seed=6)
+        for want_digest in (False, True):  # value records, then edge records
+            r = gpu_action(g, "resolvent", v, N, K, 0.5 * s, seed=6, want_digest=want_digest)
+            assert_close(r["y"], o["y"], 1e-10)

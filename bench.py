@@ -221,7 +221,9 @@ def load_traffic(kernel):
 
 
 def host_cpu():
-    """Model name of the host CPU (lscpu), and the logical CPUs this process may use."""
+    """Model of the host CPU (lscpu's model name, with the family, model,
+    stepping and clock from /proc/cpuinfo, since a virtual machine may report
+    a bare vendor name), and the logical CPUs this process may use."""
     import subprocess
     model = ""
     try:
@@ -232,6 +234,22 @@ def host_cpu():
                 break
     except (OSError, subprocess.SubprocessError):
         pass
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if not line.strip():
+                    break  # the first processor's block is enough
+                key, _, value = line.partition(":")
+                info[key.strip()] = value.strip()
+    except OSError:
+        pass
+    model = model or info.get("model name", "")
+    extra = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    if "cpu MHz" in info:
+        extra.append(f"{float(info['cpu MHz']):.0f} MHz")
+    if extra:
+        model = f"{model} ({', '.join(extra)})"
     return model, len(os.sched_getaffinity(0)), os.cpu_count()
 
 

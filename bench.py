@@ -91,7 +91,9 @@ def layout_bytes(kind, st):
     """Bytes this implementation's data layout moves beyond the algorithmic
     ones: the diagonal's visit records (12 B per recorded state, written by
     the walk and read back by the gather) and the 4 B more of a 16-byte edge
-    record than the 12 B of row record and column per transition."""
+    record than the 12 B of row record and column per transition.  The wide
+    hub masks the diagonal walk reads under the WIDE layout are left out:
+    the call does not count them (the FETCH_SIZE traffic includes them)."""
     steps = st["walk_steps"]
     transitions = steps - st["walks"]
     if kind == "diag_walk":

@@ -211,6 +211,11 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
                                Costs 16 bytes per stored entry during the call; falls
                                back to EDGE with a path digest, on weighted graphs or
                                when 16 nnz exceeds 1/16 of device memory */
+#define MCMF_SAMPLER_WIDE 3  /* mcmf_diag on graphs with wide hubs only (below): EDGE
+                               records, and for each visit the state's 128-byte mask of
+                               up to 1024 hubs (the chunks a start row needs, loaded
+                               with the step's record); the walk sums <Q_k, C_h> for
+                               all those hubs as it goes and the gather skips them */
 
 /* Per-graph choices of the walk kernels and of the diagonal gather.  They
  * change memory traffic and the order of floating-point sums only: walk paths
@@ -229,11 +234,19 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
  * diagonal walk adds up as it records the visits (the mask arrives with the
  * record it loads anyway), instead of one probe of Q_k per entry of row h
  * in the gather.  The graph's hubs, and the masks, assume the symmetry that
- * MCMF_SYMMETRIC states. */
+ * MCMF_SYMMETRIC states.
+ *
+ * Wide hubs: such a graph with more than 32 rows with entries also keeps its
+ * (up to 1024) rows of largest degree as wide hubs, with a 128-byte mask per
+ * node of those adjacent to it (130 bytes per node in all), when that fits
+ * 1/32 of device memory, and then defaults diag_sampler to MCMF_SAMPLER_WIDE
+ * unless the ROW default above applies.  hub_min_degree picks the active wide
+ * hubs as it picks the 32-bit ones.  The batched walks keep the 32-bit hubs. */
 typedef struct {
     int32_t action_sampler;  /* MCMF_SAMPLER_* of mcmf_action walks */
     int32_t action_stream;   /* 1: the walk's record loads are non-temporal */
-    int32_t diag_sampler;    /* MCMF_SAMPLER_* of mcmf_diag walks */
+    int32_t diag_sampler;    /* MCMF_SAMPLER_* of mcmf_diag walks (WIDE: graphs with wide
+                                hub records only; the stream flag does not apply) */
     int32_t diag_stream;     /* 1: non-temporal record loads */
     double action_ms[4];     /* mcmf_tune only: ms of each EDGE/ROW action variant, index
                                 sampler*2+stream */
@@ -262,6 +275,8 @@ typedef struct {
                                   128/256/512/1024 neighbours */
     double hub_ms[2];          /* mcmf_tune only: ms of diag walk + gather with hub sums at
                                   the automatic threshold / off (0 without hubs) */
+    double wide_ms;            /* mcmf_tune only: ms of the same with wide hub sums
+                                  (MCMF_SAMPLER_WIDE; 0 without wide hubs) */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the
@@ -278,7 +293,7 @@ mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t);
  * diagonal gather (every neighbour of the sampled rows requested) at work
  * items of 128, 256, 512 and 1024 neighbours; and, on graphs with hub rows,
  * diagonal walk plus gather with hub sums at the automatic threshold and
- * off.  It keeps the fastest of each and stores it in the graph
+ * off, and with wide hub sums where the graph has wide hubs.  It keeps the fastest of each and stores it in the graph
  * (mcmf_graph_set_tuning).  out receives the choice and the measured times.  The caller may cache the result by a
  * fingerprint of the graph and reapply it with mcmf_graph_set_tuning.
  * Errors: as mcmf_action (K >= 2, n_walks >= 1 required), MCMF_E_NOMEM,

@@ -558,7 +558,10 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
             p.n_walks = alloc.max_walks;
         }
         // Hub rows: the walks sum them, the gather leaves them out.
-        p.hub_act = g->weighted ? 0u : active_hubs(g, p.n_walks, K);
+        if (wide_diag(g, p))
+            p.whub_act = active_wide_hubs(g, p.n_walks, K);
+        else
+            p.hub_act = g->weighted ? 0u : active_hubs(g, p.n_walks, K);
         p.in_set = all ? nullptr : in_set.ptr;
         p.dacc = dacc.ptr;
         // Visit records of a chunk of start rows: 12 bytes per visit (8 with

@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <vector>
 
 #include "mcmf.h"
 
@@ -137,6 +138,12 @@ constexpr int32_t kDefaultGatherItem = 256;
 constexpr int kMaxHubs = 32;
 constexpr uint8_t kNoHub = 0xFF;
 
+// Wide hubs: up to kMaxWideHubs hub rows, with a 128-byte mask per node
+// (kWideWords words, one 128-byte line) of the wide hubs adjacent to it.
+constexpr int kWideWords = 32;
+constexpr int kMaxWideHubs = 32 * kWideWords; // 1024
+constexpr uint16_t kNoWideHub = 0xFFFF;
+
 } // namespace mcmf
 
 // Opaque graph handle: the device copy of A and its per-row metadata.
@@ -176,7 +183,7 @@ struct mcmf_graph {
     size_t bytes = 0;
     // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
     mcmf_tuning tuning = {MCMF_SAMPLER_VALUE, 0, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {0, 0},
-                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}};
+                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}, 0};
     // Hub rows (unweighted symmetric graphs with strictly increasing rows):
     // the rows of largest degree, at most kMaxHubs.  hubmask[j] has bit h set
     // when j is a column of row hub_rows[h] (by symmetry: when j is adjacent
@@ -191,4 +198,15 @@ struct mcmf_graph {
     // Q_k table overflows (lost inserts) of asynchronous diagonal calls on
     // this graph; checked and cleared by its next synchronising call.
     unsigned long long *async_overflow = nullptr; // [1]
+    // Wide hubs (unweighted symmetric graphs with strictly increasing rows
+    // and more than kMaxHubs rows with entries): the up to kMaxWideHubs rows
+    // of largest degree (the first kMaxHubs are hub_rows), degree descending;
+    // whub_of[i] = wide hub index of row i, kNoWideHub elsewhere;
+    // wmask[i * kWideWords + w] = bits of the wide hubs 32w..32w+31 adjacent
+    // to i (128 bytes per node, line aligned).
+    int32_t n_whubs = 0;
+    std::vector<int64_t> whub_deg_host;
+    int32_t *whub_rows = nullptr; // [n_whubs]
+    uint16_t *whub_of = nullptr;  // [n]
+    uint32_t *wmask = nullptr;    // [n * kWideWords]
 };

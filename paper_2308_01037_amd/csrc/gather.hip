@@ -77,6 +77,8 @@ struct GatherArgs {
     const uint8_t *hub_of;
     uint32_t hub_act; // hubs the walks summed: left out of the probes
     uint32_t item;    // neighbours per work item
+    const uint16_t *whub_of;
+    int32_t whub_act; // wide hubs the walks summed (prefix): left out too
 };
 
 template <bool WEIGHTED, class VT>
@@ -104,6 +106,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.overflow = a.overflow;
     job.hub_of = a.hub_of;
     job.hub_act = a.hub_act;
+    job.whub_of = a.whub_of;
+    job.whub_act = a.whub_act;
     for (;;) {
         const int64_t item = dev::uniform(first + next_item(a.queue, &item_slot));
         if (item >= last)
@@ -188,6 +192,8 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.queue = queue;
     a.hub_of = g->hub_of;
     a.hub_act = p.hub_act;
+    a.whub_of = g->whub_of;
+    a.whub_act = wide_diag(g, p) ? p.whub_act : 0;
     a.item = p.gather_item ? p.gather_item : gather_item(g);
     const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, kMaxTableLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);

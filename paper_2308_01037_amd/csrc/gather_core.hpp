@@ -291,6 +291,8 @@ struct RowJob {
     unsigned long long *overflow;
     const uint8_t *hub_of;   // per node: its hub index, or kNoHub
     uint32_t hub_act;        // hubs summed by the walks, not probed here (0: none)
+    const uint16_t *whub_of; // per node: its wide hub index, or kNoWideHub
+    int32_t whub_act;        // wide hubs [0, whub_act) summed by the walks (0: none)
 };
 
 // Runs the job with all threads of the workgroup (kGatherThreads).
@@ -329,6 +331,8 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                         const uint32_t hx = j.hub_of[i];
                         take = hx == kNoHub || ((j.hub_act >> hx) & 1u) == 0u;
                     }
+                    if (take && j.whub_act > 0)
+                        take = static_cast<int32_t>(j.whub_of[i]) >= j.whub_act;
                 }
                 if (take) {
                     const uint2 ri = j.node[i];

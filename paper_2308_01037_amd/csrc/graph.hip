@@ -197,6 +197,19 @@ __global__ void k_hub_marks(const int32_t *hub_rows, const uint2 *node, const in
         hub_of[row] = static_cast<uint8_t>(h);
 }
 
+// Wide hub h (one workgroup each): its bit in the wide mask of every column
+// of its row.
+__global__ void k_whub_marks(const int32_t *whub_rows, const uint2 *node, const int32_t *col,
+                             uint32_t *wmask, uint16_t *whub_of) {
+    const int h = blockIdx.x;
+    const int32_t row = whub_rows[h];
+    const uint2 r = node[row];
+    for (uint32_t e = threadIdx.x; e < r.y; e += blockDim.x)
+        atomicOr(&wmask[int64_t(col[int64_t(r.x) + e]) * kWideWords + h / 32], 1u << (h % 32));
+    if (threadIdx.x == 0)
+        whub_of[row] = static_cast<uint16_t>(h);
+}
+
 // a_ji == a_ij for every stored a_ij (rows sorted): one wavefront per row,
 // each lane binary-searches row j for i.
 __global__ __launch_bounds__(kThreads) void k_check_symmetric(const uint2 *node, int64_t n,
@@ -269,14 +282,20 @@ void free_graph(mcmf_graph *g) {
     dev_free_sync(g->hubmask, sizeof(uint32_t) * g->n);
     dev_free_sync(g->hub_of, sizeof(uint8_t) * g->n);
     dev_free_sync(g->hub_rows, sizeof(int32_t) * kMaxHubs);
+    dev_free_sync(g->whub_rows, sizeof(int32_t) * g->n_whubs);
+    dev_free_sync(g->whub_of, sizeof(uint16_t) * g->n);
+    dev_free_sync(g->wmask, sizeof(uint32_t) * kWideWords * g->n);
     dev_free_sync(g->async_overflow, sizeof(unsigned long long));
     if (g->stream)
         (void)hipStreamDestroy(g->stream);
     delete g;
 }
 
-// The graph's hub rows: the kMaxHubs rows of largest degree (ties: lower
-// row first), chosen on the host from the row records, and their masks.
+// The graph's hub rows: the kMaxWideHubs rows of largest degree (ties:
+// lower row first), chosen on the host from the row records.  The first
+// kMaxHubs are the hubs of the 32-bit masks (every edge record's spare word);
+// when there are more, all of them get wide masks if those fit 1/32 of
+// device memory.
 Status build_hubs(mcmf_graph *g, hipStream_t s) {
     const int64_t n = g->n;
     std::vector<uint2> node(static_cast<size_t>(n));
@@ -288,14 +307,14 @@ Status build_hubs(mcmf_graph *g, hipStream_t s) {
     };
     for (int64_t i = 0; i < n; ++i) {
         const uint32_t d = node[static_cast<size_t>(i)].y;
-        if (d == 0 || (static_cast<int>(top.size()) == kMaxHubs && d <= top.back().first))
+        if (d == 0 || (static_cast<int>(top.size()) == kMaxWideHubs && d <= top.back().first))
             continue;
         const std::pair<uint32_t, int32_t> x(d, static_cast<int32_t>(i));
         top.insert(std::upper_bound(top.begin(), top.end(), x, before), x);
-        if (static_cast<int>(top.size()) > kMaxHubs)
+        if (static_cast<int>(top.size()) > kMaxWideHubs)
             top.pop_back();
     }
-    g->n_hubs = static_cast<int32_t>(top.size());
+    g->n_hubs = static_cast<int32_t>(std::min<size_t>(top.size(), kMaxHubs));
     if (g->n_hubs == 0)
         return {};
     for (int h = 0; h < g->n_hubs; ++h) {
@@ -312,6 +331,25 @@ Status build_hubs(mcmf_graph *g, hipStream_t s) {
     hipLaunchKernelGGL(k_hub_marks, dim3(g->n_hubs), dim3(kThreads), 0, s, g->hub_rows, g->node, g->col,
                        g->hubmask, g->hub_of);
     MCMF_HIP(hipGetLastError());
+    const uint64_t wide_bytes = (sizeof(uint32_t) * kWideWords + sizeof(uint16_t)) * static_cast<uint64_t>(n);
+    if (top.size() > static_cast<size_t>(kMaxHubs) && wide_bytes <= device_memory_bytes() / 32) {
+        g->n_whubs = static_cast<int32_t>(top.size());
+        g->whub_deg_host.resize(top.size());
+        std::vector<int32_t> rows(top.size());
+        for (size_t h = 0; h < top.size(); ++h) {
+            rows[h] = top[h].second;
+            g->whub_deg_host[h] = top[h].first;
+        }
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->whub_rows), sizeof(int32_t) * g->n_whubs));
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->whub_of), sizeof(uint16_t) * n));
+        MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->wmask), sizeof(uint32_t) * kWideWords * n));
+        MCMF_TRY(fill_impl<uint32_t>(g->wmask, 0u, kWideWords * n, s));
+        MCMF_TRY(fill_impl<uint16_t>(g->whub_of, kNoWideHub, n, s));
+        MCMF_HIP(hipMemcpyAsync(g->whub_rows, rows.data(), sizeof(int32_t) * g->n_whubs, hipMemcpyHostToDevice, s));
+        hipLaunchKernelGGL(k_whub_marks, dim3(g->n_whubs), dim3(kThreads), 0, s, g->whub_rows, g->node, g->col,
+                           g->wmask, g->whub_of);
+        MCMF_HIP(hipGetLastError());
+    }
     MCMF_HIP(hipStreamSynchronize(s));
     return {};
 }
@@ -450,11 +488,29 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
     g->bytes = (sizeof(int32_t) + sizeof(uint4)) * nnz + sizeof(uint2) * n + sizeof(int32_t) * (n + g->n_active) +
                sizeof(int64_t) * (g->n_active + 1) +
                (g->weighted ? sizeof(double) * (2 * nnz + n) : 0) +
-               (g->n_hubs > 0 ? (sizeof(uint32_t) + sizeof(uint8_t)) * n + sizeof(int32_t) * kMaxHubs : 0);
+               (g->n_hubs > 0 ? (sizeof(uint32_t) + sizeof(uint8_t)) * n + sizeof(int32_t) * kMaxHubs : 0) +
+               (g->n_whubs > 0 ? (sizeof(uint32_t) * kWideWords + sizeof(uint16_t)) * n + sizeof(int32_t) * g->n_whubs
+                               : 0);
+    // The diagonal walk with wide hub sums where the graph has wide hubs and
+    // is past the size at which the ROW layout pays.
+    if (g->n_whubs > 0 && g->tuning.diag_sampler != MCMF_SAMPLER_ROW)
+        g->tuning.diag_sampler = MCMF_SAMPLER_WIDE;
     return {};
 }
 
 } // namespace
+
+int32_t active_wide_hubs(const mcmf_graph *g, int64_t n_walks, int K) {
+    if (g->n_whubs == 0)
+        return 0;
+    int64_t min_deg = g->tuning.hub_min_degree;
+    if (min_deg <= 0)
+        min_deg = std::max<int64_t>(1, n_walks * (K - 1) / 4);
+    int32_t c = 0; // wide hubs are sorted by degree: the active ones are a prefix
+    while (c < g->n_whubs && g->whub_deg_host[static_cast<size_t>(c)] >= min_deg)
+        ++c;
+    return c;
+}
 
 uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K) {
     if (g->n_hubs == 0)

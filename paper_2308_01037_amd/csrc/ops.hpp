@@ -20,6 +20,11 @@ Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s);
 // row per adjacent start row); 0 without hubs.
 uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K);
 
+// Wide hubs (degree descending) whose sums the wide diagonal walk takes for
+// n_walks and K: the prefix of degree >= the same threshold; 0 without them.
+int32_t active_wide_hubs(const mcmf_graph *g, int64_t n_walks, int K);
+
+
 // Ascending indices i < n with flags[i] == match written to out; *count (host)
 // receives how many.  Synchronises the stream to read the count back.
 Status compact(const uint8_t *flags, int64_t n, uint8_t match, int32_t *out, int64_t *count,
@@ -52,7 +57,12 @@ struct WalkParams {
     uint32_t hub_act = 0;
     const uint8_t *in_set = nullptr;
     double *dacc = nullptr;
+    // Diagonal walks with wide hub sums: the active prefix of the graph's wide
+    // hubs whose sums the walk takes (0: none; then hub_act applies).
+    int32_t whub_act = 0;
 };
+// Whether diag_walks runs the wide-record kernel for these parameters.
+bool wide_diag(const mcmf_graph *g, const WalkParams &p);
 
 // r = s A v.
 Status spmv_r(const mcmf_graph *g, const double *v, double scale, double *r, hipStream_t s);

@@ -37,8 +37,8 @@ Status check_tuning(const mcmf_tuning *t) {
     auto sampler_ok = [](int32_t v) { return v == MCMF_SAMPLER_EDGE || v == MCMF_SAMPLER_ROW; };
     auto flag_ok = [](int32_t v) { return v == 0 || v == 1; };
     if (!(sampler_ok(t->action_sampler) || t->action_sampler == MCMF_SAMPLER_VALUE) ||
-        !sampler_ok(t->diag_sampler))
-        return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only)");
+        !(sampler_ok(t->diag_sampler) || t->diag_sampler == MCMF_SAMPLER_WIDE))
+        return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only, WIDE for the diagonal)");
     if (!flag_ok(t->action_stream) || !flag_ok(t->diag_stream))
         return fail(MCMF_E_ARG, "stream flags must be 0 or 1");
     if (t->hub_min_degree < 0)
@@ -72,6 +72,7 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
         x = 0.0;
     for (double &x : best.hub_ms)
         x = 0.0;
+    best.wide_ms = 0.0;
     if (g->n_active == 0) {
         *out = best;
         return {};
@@ -211,10 +212,15 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
         MCMF_TRY(items.alloc(m + 1, s));
         MCMF_TRY(counters.alloc(3, s));
         const uint32_t auto_hubs = g->weighted ? 0u : active_hubs(g, N, K);
-        auto run_diag = [&](uint32_t item, uint32_t hubs, bool walk) -> Status {
+        auto run_diag = [&](uint32_t item, uint32_t hubs, bool walk, int32_t whubs = -1) -> Status {
             WalkParams pd = p;
             pd.gather_item = item;
             pd.hub_act = hubs;
+            if (whubs >= 0) {
+                pd.sampler = MCMF_SAMPLER_WIDE;
+                pd.whub_act = whubs;
+                pd.hub_act = 0u;
+            }
             pd.in_set = nullptr;
             pd.dacc = dacc.ptr;
             MCMF_TRY(fill_f64(dacc.ptr, 0.0, n, s));
@@ -242,6 +248,20 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
             MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], auto_hubs, true); }, &best.hub_ms[0]));
             MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true); }, &best.hub_ms[1]));
             best.hub_min_degree = best.hub_ms[1] < best.hub_ms[0] ? INT32_MAX : 0;
+        }
+        // Wide hub records: walk and gather with the wide hub sums at the
+        // automatic threshold, against the better of the two above.
+        if (g->n_whubs > 0 && !g->weighted) {
+            const int32_t auto_wide = active_wide_hubs(g, N, K);
+            MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true, auto_wide); }, &best.wide_ms));
+            double other = std::min(best.hub_ms[0], best.hub_ms[1]);
+            if (auto_hubs == 0u)
+                MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true); }, &other));
+            if (best.wide_ms < other) {
+                best.diag_sampler = MCMF_SAMPLER_WIDE;
+                best.diag_stream = 0;
+                best.hub_min_degree = 0;
+            }
         }
         unsigned long long lost = 0;
         MCMF_HIP(hipMemcpyAsync(&lost, counters.ptr + 1, sizeof lost, hipMemcpyDeviceToHost, s));
@@ -273,6 +293,10 @@ extern "C" mcmf_status mcmf_graph_set_tuning(mcmf_graph *g, const mcmf_tuning *t
     mcmf::Status st = mcmf::check_tuning(t);
     if (st)
         return st.code;
+    if (t->diag_sampler == MCMF_SAMPLER_WIDE && g->n_whubs == 0) {
+        mcmf::fail(MCMF_E_ARG, "diag_sampler WIDE needs a graph with wide hubs");
+        return MCMF_E_ARG;
+    }
     g->tuning.action_sampler = t->action_sampler;
     g->tuning.action_stream = t->action_stream;
     g->tuning.diag_sampler = t->diag_sampler;

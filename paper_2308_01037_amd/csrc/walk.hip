@@ -116,6 +116,83 @@ __global__ __launch_bounds__(256) void k_diag_walk(GraphView g, const int32_t *_
     }
 }
 
+// Diagonal with wide hub sums (unweighted graphs): the visit records as
+// k_diag_walk writes them, and <Q_k, C_h> for every requested wide hub h of
+// the active prefix [0, n_act) adjacent to k summed here (the gather leaves
+// those neighbours out): dacc[h] += s a_kh * s <Q_k, C_h> / N.
+template <class WT, bool DIGEST, bool CUTOFF>
+__global__ __launch_bounds__(256) void k_diag_walk_wide(const uint2 *__restrict__ node,
+                                                        const uint4 *__restrict__ edge,
+                                                        const uint32_t *__restrict__ wmask,
+                                                        const int32_t *__restrict__ whub_rows, int32_t n_act,
+                                                        const int32_t *__restrict__ starts, int64_t n_start,
+                                                        WalkArgs a, int32_t *__restrict__ vstate,
+                                                        WT *__restrict__ vx, uint64_t *__restrict__ digest,
+                                                        unsigned long long *steps) {
+    __shared__ unsigned long long redu[4];
+    __shared__ double redd[4];
+    __shared__ double hsum[kMaxWideHubs];
+    __shared__ uint32_t hk[kWideWords];
+    for (int64_t kk = blockIdx.x; kk < n_start; kk += gridDim.x) {
+        const uint32_t k = static_cast<uint32_t>(starts[kk]);
+        const uint2 rk = node[k];
+        const int64_t N = a.row_walks ? a.row_walks[kk] : a.N;
+        const int64_t row_base = a.row_rec ? a.row_rec[kk] - a.row_rec[0] : kk * (a.K - 1) * a.N;
+        // The requested active hubs adjacent to k.
+        __syncthreads();
+        if (threadIdx.x < kWideWords)
+            hk[threadIdx.x] = 0u;
+        __syncthreads();
+        for (int hb = threadIdx.x; hb < n_act; hb += blockDim.x) {
+            const bool adj = (wmask[int64_t(k) * kWideWords + hb / 32] >> (hb % 32)) & 1u;
+            if (adj && (!a.in_set || a.in_set[whub_rows[hb]])) {
+                atomicOr(&hk[hb / 32], 1u << (hb % 32));
+                hsum[hb] = 0.0;
+            }
+        }
+        __syncthreads();
+        walk::WideRow hr;
+        hr.chunks = 0u;
+#pragma unroll
+        for (int wd = 0; wd < kWideWords; ++wd) {
+            hr.hk[wd] = static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(hk[wd])));
+            if (hr.hk[wd] != 0u)
+                hr.chunks |= 1u << (wd >> 2);
+        }
+        hr.any = hr.chunks != 0u;
+        uint64_t dig = 0;
+        unsigned long long nsteps = 0;
+        double acc0 = 0.0;
+        for (int64_t w64 = threadIdx.x; w64 < N; w64 += blockDim.x) {
+            uint64_t h = dev::kFnvBasis;
+            walk::diag_walk_wide<WT, DIGEST, CUTOFF>(edge, reinterpret_cast<const uint4 *>(wmask), a, k, rk,
+                                                     static_cast<uint32_t>(w64),
+                                                     vstate + row_base + w64, vx + row_base + w64, N, &h,
+                                                     &nsteps, hr, hsum, &acc0);
+            if (DIGEST)
+                dig += h;
+        }
+        if (hr.any) {
+            const double x0 = dev::block_sum(acc0, redd);
+            for (int hb = threadIdx.x; hb < n_act; hb += blockDim.x) {
+                if ((hk[hb / 32] >> (hb % 32)) & 1u) {
+                    const double hs = hsum[hb] + x0;
+                    if (hs != 0.0)
+                        atomicAdd(&a.dacc[whub_rows[hb]], a.scale * (a.scale * hs) * (1.0 / static_cast<double>(N)));
+                }
+            }
+        }
+        const unsigned long long st = dev::block_sum(nsteps, redu);
+        if (DIGEST) {
+            const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+            if (threadIdx.x == 0)
+                digest[k] = dg;
+        }
+        if (threadIdx.x == 0 && steps)
+            atomicAdd(steps, st);
+    }
+}
+
 // Action over value records (unweighted graphs, no path digest).
 template <class WT, bool CUTOFF, bool STREAM>
 __global__ __launch_bounds__(256) void k_action_walk_value(const uint2 *__restrict__ node,
@@ -235,6 +312,11 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     return {};
 }
 
+bool wide_diag(const mcmf_graph *g, const WalkParams &p) {
+    return g->n_whubs > 0 && !g->weighted &&
+           (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_WIDE;
+}
+
 Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,
                   int32_t *state, void *x, uint64_t *digest, unsigned long long *steps,
                   hipStream_t s) {
@@ -244,7 +326,18 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
     const GraphView gv = walk::view(g);
     const int threads = p.threads >= 0 ? p.threads : g->tuning.walk_threads;
     const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks, threads));
-    const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_EDGE;
+    if (wide_diag(g, p)) {
+        const bool fp32 = p.precision == MCMF_PRECISION_FP32_WEIGHTS;
+        walk::dispatch4(fp32, false, digest != nullptr, p.cutoff > 0.0, [&](auto wt, auto, auto d, auto c) {
+            using WT = decltype(wt);
+            hipLaunchKernelGGL((k_diag_walk_wide<WT, decltype(d)::value, decltype(c)::value>), grid, block, 0, s,
+                               g->node, g->edge, g->wmask, g->whub_rows, p.whub_act, starts, n_start, a, state,
+                               static_cast<WT *>(x), digest, steps);
+        });
+        MCMF_HIP(hipGetLastError());
+        return {};
+    }
+    const bool edge = (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) != MCMF_SAMPLER_ROW;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.diag_stream) != 0;
     walk::dispatch6(p.precision == MCMF_PRECISION_FP32_WEIGHTS, g->weighted, digest != nullptr,
                     p.cutoff > 0.0, edge, stream, [&](auto wt, auto w, auto d, auto c, auto e, auto st) {

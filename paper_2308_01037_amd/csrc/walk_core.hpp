@@ -297,6 +297,92 @@ __device__ __forceinline__ void diag_walk(const GraphView &g, const WalkArgs &a,
         vstate[int64_t(t) * stride] = -1;
 }
 
+// Requested wide hubs adjacent to a start row k (uniform over the row's
+// walks): mask word w of them, and the 16-byte chunks of a node's 128-byte
+// wide mask that hold the nonzero words.
+struct WideRow {
+    uint32_t hk[kWideWords];
+    uint32_t chunks; // bit c: words 4c..4c+3 are needed
+    bool any;
+};
+
+// Word i (0..3) of a uint4, i known at compile time after unrolling.
+__device__ __forceinline__ uint32_t word_of(const uint4 &v, int i) {
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+// One diagonal walk over edge records with wide hub sums (unweighted
+// graphs): the visit records as diag_walk writes them, and for every visit
+// (t >= 1) at a state l adjacent to one of the hubs in hr its weight added to
+// hsum[h] (LDS).  The needed chunks of l's wide mask are loaded together with
+// the record of the step out of l, so their latency hides behind it.  Step 0
+// sits at k, adjacent to every hub in hr: its weights go to *acc0, added to
+// every such hub once per start row.
+template <class WT, bool DIGEST, bool CUTOFF>
+__device__ __forceinline__ void diag_walk_wide(const uint4 *__restrict__ edge, const uint4 *__restrict__ wmask,
+                                               const WalkArgs &a, uint32_t k, uint2 rk, uint32_t w,
+                                               int32_t *__restrict__ vstate, WT *__restrict__ vx, int64_t stride,
+                                               uint64_t *h, unsigned long long *nsteps, const WideRow &hr,
+                                               double *hsum, double *acc0) {
+    const int last = a.K - 2;
+    uint32_t l = k, start = rk.x, deg = rk.y;
+    WT W = WT(1);
+    int t = 0;
+    for (; t <= last; ++t) {
+        if (CUTOFF && !(fabs(static_cast<double>(W)) > a.cutoff))
+            break;
+        const bool more = t < last && deg > 0;
+        const bool sums = hr.any && t > 0;
+        uint4 c[kWideWords / 4];
+        if (sums) {
+            const uint4 *ml = wmask + int64_t(l) * (kWideWords / 4);
+#pragma unroll
+            for (int q = 0; q < kWideWords / 4; ++q)
+                if ((hr.chunks >> q) & 1u)
+                    c[q] = ml[q];
+        }
+        uint4 nx = make_uint4(l, start, deg, 0u);
+        WT Wn = W;
+        if (more) {
+            const uint4 x = dev::philox4x32_10(make_uint4(k, w, static_cast<uint32_t>(t), a.request),
+                                               a.key0, a.key1);
+            const uint32_t j = dev::uniform_index(x.x, x.y, deg);
+            Wn = W * static_cast<WT>(a.scale * static_cast<double>(deg));
+            nx = edge[int64_t(start) + j];
+        }
+        const WT xt = static_cast<WT>(a.coef[t]) * W;
+        vstate[int64_t(t) * stride] = static_cast<int32_t>(l);
+        vx[int64_t(t) * stride] = xt;
+        if (t == 0 && hr.any)
+            *acc0 += static_cast<double>(xt);
+        if (sums) {
+#pragma unroll
+            for (int wd = 0; wd < kWideWords; ++wd) {
+                if (hr.hk[wd] == 0u)
+                    continue;
+                uint32_t m = word_of(c[wd >> 2], wd & 3) & hr.hk[wd];
+                while (m != 0u) {
+                    atomicAdd(&hsum[32 * wd + __ffs(m) - 1], static_cast<double>(xt));
+                    m &= m - 1u;
+                }
+            }
+        }
+        if (DIGEST)
+            *h = dev::fnv_step(*h, l);
+        ++*nsteps;
+        if (!more) {
+            ++t;
+            break;
+        }
+        l = nx.x;
+        start = nx.y;
+        deg = nx.z;
+        W = Wn;
+    }
+    for (; t <= last; ++t)
+        vstate[int64_t(t) * stride] = -1;
+}
+
 // Runtime flags to template arguments, sampler layout included (weighted
 // rows have one layout: the sampler flags are ignored for them).
 template <class F>

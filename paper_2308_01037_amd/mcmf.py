@@ -60,6 +60,7 @@ MCMF_ALLOC_NORM_MIN1 = 2
 MCMF_SAMPLER_EDGE = 0
 MCMF_SAMPLER_ROW = 1
 MCMF_SAMPLER_VALUE = 2
+MCMF_SAMPLER_WIDE = 3
 
 
 class mcmf_fn(ctypes.Structure):
@@ -94,7 +95,7 @@ class mcmf_tuning(ctypes.Structure):
                 ("hub_count", ctypes.c_int32), ("action_value_ms", ctypes.c_double * 2),
                 ("walk_threads", ctypes.c_int32), ("gather_item", ctypes.c_int32),
                 ("walk_threads_ms", ctypes.c_double * 3), ("gather_item_ms", ctypes.c_double * 4),
-                ("hub_ms", ctypes.c_double * 2)]
+                ("hub_ms", ctypes.c_double * 2), ("wide_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
@@ -104,7 +105,8 @@ class mcmf_tuning(ctypes.Structure):
                 "hub_count": self.hub_count, "action_value_ms": list(self.action_value_ms),
                 "walk_threads": self.walk_threads, "gather_item": self.gather_item,
                 "walk_threads_ms": list(self.walk_threads_ms),
-                "gather_item_ms": list(self.gather_item_ms), "hub_ms": list(self.hub_ms)}
+                "gather_item_ms": list(self.gather_item_ms), "hub_ms": list(self.hub_ms),
+                "wide_ms": self.wide_ms}
 
 
 MCMF_REQ_DIAG = 0

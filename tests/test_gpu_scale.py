@@ -28,6 +28,7 @@ if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
 from _gpu import assert_close, assert_mc_part_close, gpu_action, gpu_diag, graph  # noqa: E402
+from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
 
 def test_torus_million_nodes_exact():
@@ -76,10 +77,11 @@ def _sample_rows(csr, seed):
         rows.append(int(rng.choice(mid)))
     iso = np.nonzero(deg == 0)[0]
     rows.append(int(iso[0]))
-    # The smallest of the 32 hub rows: its diagonal is summed by the walks
-    # (one mask test per visit) instead of probed.
-    top = np.lexsort((np.arange(csr.n), -deg))[:32]
-    rows.append(int(top[-1]))
+    # The smallest of the 32 hub rows and two of the 1024 wide hub rows (the
+    # smallest among them too): the walks sum their diagonals (mask tests per
+    # visit) instead of the gather probing them.
+    top = np.lexsort((np.arange(csr.n), -deg))[:1024]
+    rows += [int(top[31]), int(top[400]), int(top[-1])]
     return np.array(rows, dtype=np.int32)
 
 
@@ -90,12 +92,19 @@ def test_rmat20_bench_configuration(rmat20, fn):
     scale = 1.0 / csr.d_max if fn == "exp" else 0.85 / lam
     rows = _sample_rows(csr, seed=5 if fn == "exp" else 6)
     with graph(csr) as g:
-        # As benchmarked: no digest (value-record action walk, digest-free diag walk).
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_WIDE
+        # As benchmarked: no digest (value-record action walk, digest-free
+        # diag walk with wide hub sums).
         ra = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, stats=True)
         rd = gpu_diag(g, fn, N, K, scale, seed=1, stats=True)
-        # With path digests (edge-record walks).
+        # With path digests (edge-record action walk, wide diag walk).
         ra_d = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, want_digest=True)
         rd_d = gpu_diag(g, fn, N, K, scale, seed=1, want_digest=True)
+        # The EDGE diag walk with the 32-bit hub masks: the same estimate.
+        t = M.mcmf_graph_get_tuning(g.handle)
+        t.diag_sampler, t.hub_count = M.MCMF_SAMPLER_EDGE, 0
+        M.mcmf_graph_set_tuning(g.handle, t)
+        rd_e = gpu_diag(g, fn, N, K, scale, seed=1, stats=True)
     active = int(np.count_nonzero(csr.deg))
     assert ra["stats"]["walk_steps"] == active * N * (K - 1)
     assert rd["stats"]["walk_steps"] == active * N * (K - 1)
@@ -119,6 +128,9 @@ def test_rmat20_bench_configuration(rmat20, fn):
     # The two kernels of each query agree on every output.
     assert_close(ra["y"], ra_d["y"], 1e-12, what="action kernels")
     assert_close(rd["d"], rd_d["d"], 1e-12, what="diag kernels")
+    assert_close(rd["d"], rd_e["d"], 1e-10, what="wide vs edge diag")
+    assert rd_e["stats"]["walk_steps"] == rd["stats"]["walk_steps"]
+    assert rd["stats"]["gather_probes"] < rd_e["stats"]["gather_probes"]
     # Every term of the series is non-negative here: x >= h = c0 v + c1 s A v.
     assert np.all(np.isfinite(ra["y"])) and np.all(ra["y"] >= h_action * (1 - 1e-15))
     assert np.all(np.isfinite(rd["d"])) and np.all(rd["d"] >= c[0])

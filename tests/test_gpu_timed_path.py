@@ -10,8 +10,9 @@ and compare every output with the oracle:
   full 256-lane workgroup, several walks per lane), FP64 within 1e-10 on the
   full value, on q and on the Monte Carlo part, FP32 walk weights within the
   stated bound 2 K 2^-24 sum|terms|;
-* diagonal, digest-free walk in both sampler layouts, the same N (N = 1000
-  also takes the gather through several table passes);
+* diagonal, digest-free walk in the EDGE, ROW and WIDE layouts (WIDE, with
+  its hub sums, is what large graphs default to), the same N (N = 1000 also
+  takes the gather through several table passes);
 * the first draw of walk 0 from row 0 with seed 0 and request 0 is the
   published Philox4x32-10 known answer for counter 0 and key 0, read back
   through the walk it picks on a star (independent of the oracle).
@@ -74,7 +75,7 @@ def test_value_record_action_matches_oracle(rmat10, N):
     assert not np.array_equal(y32, r["y"])  # the FP32 path really ran
 
 
-@pytest.mark.parametrize("sampler", [M.MCMF_SAMPLER_EDGE, M.MCMF_SAMPLER_ROW])
+@pytest.mark.parametrize("sampler", [M.MCMF_SAMPLER_EDGE, M.MCMF_SAMPLER_ROW, M.MCMF_SAMPLER_WIDE])
 @pytest.mark.parametrize("N", [193, 256, 1000])
 def test_digest_free_diag_matches_oracle(rmat10, N, sampler):
     csr = rmat10

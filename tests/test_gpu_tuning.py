@@ -101,6 +101,13 @@ def test_autotune_measures_then_caches(tmp_path):
             assert min(gi) >= 0.97 * gi[1]
         if a["hub_count"] > 0:
             assert all(ms > 0 for ms in a["hub_ms"])
+        # Wide hub records (this graph has them) against the better of hub
+        # sums on and off; with them the automatic threshold applies.
+        assert a["wide_ms"] > 0
+        if a["diag_sampler"] == M.MCMF_SAMPLER_WIDE:
+            assert a["wide_ms"] < min(a["hub_ms"]) and a["hub_min_degree"] == 0
+        else:
+            assert a["diag_sampler"] in (M.MCMF_SAMPLER_EDGE, M.MCMF_SAMPLER_ROW)
             assert a["hub_min_degree"] == (0 if a["hub_ms"][0] <= a["hub_ms"][1] else 2**31 - 1)
         # The fastest of the four EDGE/ROW variants and the two VALUE ones.
         times = list(a["action_ms"]) + list(a["action_value_ms"])
@@ -176,8 +183,9 @@ def test_value_records_action_matches_edge_and_oracle(stream):
 
 def test_default_diag_layout_by_size():
     """An unweighted graph whose column array and row records take at most
-    16 MiB starts with the ROW layout for the diagonal walk; a larger or a
-    weighted graph starts with EDGE.  The layouts give the same walks."""
+    16 MiB starts with the ROW layout for the diagonal walk; a larger one
+    with wide hubs starts with WIDE, a weighted graph with EDGE.  The
+    layouts give the same walks."""
     small, big = G.rmat(12, seed=4), G.rmat(18, seed=0)
     assert 4 * small.nnz + 8 * small.n <= (16 << 20) < 4 * big.nnz + 8 * big.n
     K, N, s = 12, 32, 1.0 / small.d_max
@@ -193,7 +201,7 @@ def test_default_diag_layout_by_size():
     with graph(G.with_random_weights(small, seed=1)) as g:
         assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
     with graph(big) as g:
-        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_WIDE
 
 
 @pytest.mark.parametrize("lanes,item,hubs", [(64, 64, 1), (128, 512, 2**31 - 1), (256, 4096, 1),

@@ -76,8 +76,12 @@ def _open(path: str):
     lib.oracle_philox4x64_10.restype = None
     lib.oracle_uniform_index.argtypes = [u64, i64]
     lib.oracle_uniform_index.restype = i64
-    lib.oracle_select_next.argtypes = [i64, P, P, P, i64, u64]
+    lib.oracle_select_next.argtypes = [i64, P, P, P, i64, u64, u64]
     lib.oracle_select_next.restype = i64
+    lib.oracle_set_alias.argtypes = [cint]
+    lib.oracle_set_alias.restype = None
+    lib.oracle_alias_table.argtypes = [i64, P, P, P, P, P]
+    lib.oracle_alias_table.restype = cint
     lib.oracle_is_symmetric.argtypes = [i64, P, P, P]
     lib.oracle_is_symmetric.restype = cint
     lib.oracle_coeffs.argtypes = [cint, cint, P]
@@ -131,9 +135,39 @@ def uniform_index(u: int, deg: int) -> int:
     return int(_load().oracle_uniform_index(u, deg))
 
 
-def select_next(g, row: int, u: int) -> int:
+def select_next(g, row: int, u: int, u2: int = 0, sampler: str = "cdf") -> int:
+    """Index in row ``row`` of the next state for random words u (and u2,
+    the alias method's second word)."""
     row_ptr, col, val = _csr_arrays(g)
-    return int(_load().oracle_select_next(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), row, u))
+    with _sampler(sampler):
+        return int(_load().oracle_select_next(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), row, u, u2))
+
+
+def alias_table(g):
+    """The alias method's tables of a weighted graph: (prob float64[nnz],
+    alias int64[nnz], alias given as an index inside the row)."""
+    row_ptr, col, val = _csr_arrays(g)
+    nnz = int(row_ptr[-1])
+    prob = np.zeros(max(nnz, 1), dtype=np.float64)
+    alias = np.zeros(max(nnz, 1), dtype=np.int64)
+    _check(_load().oracle_alias_table(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(prob), _ptr(alias)))
+    return prob[:nnz], alias[:nnz]
+
+
+class _sampler:
+    """Weighted rows sample by running sums ("cdf") or by alias tables
+    ("alias") inside the block; unweighted rows are not affected."""
+
+    def __init__(self, kind: str):
+        if kind not in ("cdf", "alias"):
+            raise OracleError(f"unknown sampler {kind!r}")
+        self.on = kind == "alias"
+
+    def __enter__(self):
+        _load().oracle_set_alias(1 if self.on else 0)
+
+    def __exit__(self, *exc):
+        _load().oracle_set_alias(0)
 
 
 def is_symmetric(g) -> bool:
@@ -184,7 +218,7 @@ def allocation(g, Ns: int, starts, symmetric: bool = True, min_one: bool = False
 
 def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int = 0,
            cutoff: float = 0.0, rows=None, expect: bool = False, want_q: bool = False,
-           want_digest: bool = False, walks=None):
+           want_digest: bool = False, walks=None, sampler: str = "cdf"):
     """RandFunmAction.  Returns dict(y, q, digest, steps).
 
     ``fn``: FN_EXP, FN_RESOLVENT or an explicit coefficient array c_0..c_K.
@@ -192,6 +226,7 @@ def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request:
     ``expect``: exact expectation of the estimator instead of sampling.
     ``walks``: walks per start row (int64[n]) instead of N for every row; a
     row given 0 starts no walk.
+    ``sampler``: "cdf" (running sums) or "alias" for weighted rows.
     """
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
@@ -204,21 +239,22 @@ def action(g, fn, v, N: int, K: int, scale: float = 1.0, seed: int = 0, request:
     q = np.zeros(max(g.n, 1), dtype=np.float64) if want_q else None
     dig = np.zeros(max(g.n, 1), dtype=np.uint64) if want_digest else None
     steps = ctypes.c_uint64(0)
-    _check(_load().oracle_action(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(c), K,
-                                 float(scale), int(N), int(seed), int(request), float(cutoff),
-                                 _ptr(v), _ptr(out_rows), 0 if out_rows is None else out_rows.size,
-                                 1 if expect else 0, _ptr(y), _ptr(q), _ptr(dig),
-                                 ctypes.addressof(steps), _ptr(_walks_array(walks, g.n))))
+    with _sampler(sampler):
+        _check(_load().oracle_action(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(c), K,
+                                     float(scale), int(N), int(seed), int(request), float(cutoff),
+                                     _ptr(v), _ptr(out_rows), 0 if out_rows is None else out_rows.size,
+                                     1 if expect else 0, _ptr(y), _ptr(q), _ptr(dig),
+                                     ctypes.addressof(steps), _ptr(_walks_array(walks, g.n))))
     return {"y": y[:n_out], "q": None if q is None else q[:g.n],
             "digest": None if dig is None else dig[:g.n], "steps": steps.value}
 
 
 def diag(g, fn, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int = 0,
          cutoff: float = 0.0, rows=None, expect: bool = False, assume_symmetric: bool = False,
-         want_digest: bool = False, walks=None):
+         want_digest: bool = False, walks=None, sampler: str = "cdf"):
     """RandFunmDiag.  Returns dict(d, digest, steps).  ``walks``: walks per
     start row (int64[n]) instead of N for every row; a row given 0 starts no
-    walk."""
+    walk.  ``sampler``: "cdf" (running sums) or "alias" for weighted rows."""
     row_ptr, col, val = _csr_arrays(g)
     c = _coeff_array(fn, K)
     r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int32)
@@ -226,11 +262,12 @@ def diag(g, fn, N: int, K: int, scale: float = 1.0, seed: int = 0, request: int 
     d = np.zeros(max(count, 1), dtype=np.float64)
     dig = np.zeros(max(g.n, 1), dtype=np.uint64) if want_digest else None
     steps = ctypes.c_uint64(0)
-    _check(_load().oracle_diag(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(c), K,
-                               float(scale), int(N), int(seed), int(request), float(cutoff),
-                               _ptr(r), 0 if r is None else r.size, 1 if assume_symmetric else 0,
-                               1 if expect else 0, _ptr(d), _ptr(dig), ctypes.addressof(steps),
-                               _ptr(_walks_array(walks, g.n))))
+    with _sampler(sampler):
+        _check(_load().oracle_diag(g.n, _ptr(row_ptr), _ptr(col), _ptr(val), _ptr(c), K,
+                                   float(scale), int(N), int(seed), int(request), float(cutoff),
+                                   _ptr(r), 0 if r is None else r.size, 1 if assume_symmetric else 0,
+                                   1 if expect else 0, _ptr(d), _ptr(dig), ctypes.addressof(steps),
+                                   _ptr(_walks_array(walks, g.n))))
     return {"d": d[:count], "digest": None if dig is None else dig[:g.n], "steps": steps.value}
 
 

@@ -39,6 +39,18 @@
  *     weighted row takes the first j with u53 * rowabs < cum_j, where
  *     u53 = (u >> 11) * 2^-53, rowabs = sum_j |a_lj| and cum_j the running
  *     sum of |a_lj|, both summed left to right; j is clamped to deg-1.
+ *   - Weighted rows, alias mode (oracle_set_alias): Walker's alias method
+ *     with Vose's construction (Vose, IEEE TSE 17(9), 1991).  Per row of deg
+ *     d: q_j = (|a_lj| * d) / rowabs; indices with q_j < 1 go on a "small"
+ *     stack, the others on a "large" one, pushed in ascending j; while both
+ *     are non-empty, pop s from small and g from large, set prob_s = q_s,
+ *     alias_s = g, q_g = (q_g + q_s) - 1 and push g on small if q_g < 1,
+ *     else on large; what is left on either stack gets prob 1 and itself as
+ *     alias.  A row with rowabs = 0 gets prob 1 and itself everywhere.  A
+ *     step takes i = floor(u * d / 2^64) and keeps i if u2_53 < prob_i,
+ *     else alias_i, with u2 = X3 * 2^32 + X2 of the same Philox block and
+ *     u2_53 = (u2 >> 11) * 2^-53.  P(next = j) = |a_lj| / rowabs as with
+ *     the running sums; only the map from random words to j differs.
  *   - The weight update is W <- (W * (s * rowabs(l))), negated when the chosen
  *     entry is negative (b/t = s * sign(a) * rowabs).
  *   - A walk reaching a row with no entries stops (its remaining terms are
@@ -127,7 +139,17 @@ typedef struct {
     const double *val; /* NULL: every stored entry is 1 */
     double *rowabs;    /* sum_j |a_lj|, left to right */
     double *cum;       /* running sums of |a_lj| per row (weighted only) */
+    double *aprob;     /* alias mode, weighted only: prob_j per stored entry */
+    int64_t *alias;    /* alias mode, weighted only: alias_j (index in the row) */
 } ograph;
+
+/* Alias mode for weighted rows (see the header); 0: running sums. */
+static int g_alias_mode = 0;
+
+void oracle_set_alias(int on)
+{
+    g_alias_mode = on ? 1 : 0;
+}
 
 typedef struct {
     const double *c; /* c_0 .. c_K */
@@ -144,10 +166,57 @@ static double entry(const ograph *g, int64_t e)
     return g->val ? g->val[e] : 1.0;
 }
 
+/* Vose's construction for one row (entries [b, b + d)); stack is scratch of
+ * d entries: "small" grows up from stack[0], "large" down from stack[d-1]. */
+static void alias_row(const ograph *g, int64_t b, int64_t d, double W, int64_t *stack)
+{
+    int64_t j, ns = 0, nl = 0;
+    double *q = g->aprob + b;
+    int64_t *al = g->alias + b;
+    if (!(W > 0.0)) {
+        for (j = 0; j < d; ++j) {
+            q[j] = 1.0;
+            al[j] = j;
+        }
+        return;
+    }
+    for (j = 0; j < d; ++j) {
+        q[j] = (fabs(entry(g, b + j)) * (double)d) / W;
+        if (q[j] < 1.0)
+            stack[ns++] = j;
+        else
+            stack[d - 1 - nl++] = j;
+    }
+    while (ns > 0 && nl > 0) {
+        int64_t s = stack[--ns];
+        int64_t big = stack[d - nl];
+        --nl;
+        al[s] = big; /* q[s] stays as prob_s */
+        q[big] = (q[big] + q[s]) - 1.0;
+        if (q[big] < 1.0)
+            stack[ns++] = big;
+        else
+            stack[d - 1 - nl++] = big;
+    }
+    while (nl > 0) {
+        int64_t big = stack[d - nl];
+        --nl;
+        q[big] = 1.0;
+        al[big] = big;
+    }
+    while (ns > 0) {
+        int64_t s = stack[--ns];
+        q[s] = 1.0;
+        al[s] = s;
+    }
+}
+
 static int prepare(ograph *g)
 {
     int64_t i, e;
     g->cum = NULL;
+    g->aprob = NULL;
+    g->alias = NULL;
     g->rowabs = (double *)malloc(sizeof(double) * (size_t)(g->n > 0 ? g->n : 1));
     if (!g->rowabs)
         return ORC_E_NOMEM;
@@ -165,6 +234,23 @@ static int prepare(ograph *g)
         }
         g->rowabs[i] = sum;
     }
+    if (g->val && g_alias_mode) {
+        int64_t nnz = g->row_ptr[g->n], dmax = 0;
+        int64_t *stack;
+        g->aprob = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+        g->alias = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nnz > 0 ? nnz : 1));
+        for (i = 0; i < g->n; ++i)
+            if (g->row_ptr[i + 1] - g->row_ptr[i] > dmax)
+                dmax = g->row_ptr[i + 1] - g->row_ptr[i];
+        stack = (int64_t *)malloc(sizeof(int64_t) * (size_t)(dmax > 0 ? dmax : 1));
+        if (!g->aprob || !g->alias || !stack) {
+            free(stack);
+            return ORC_E_NOMEM;
+        }
+        for (i = 0; i < g->n; ++i)
+            alias_row(g, g->row_ptr[i], g->row_ptr[i + 1] - g->row_ptr[i], g->rowabs[i], stack);
+        free(stack);
+    }
     return ORC_OK;
 }
 
@@ -172,6 +258,8 @@ static void release(ograph *g)
 {
     free(g->rowabs);
     free(g->cum);
+    free(g->aprob);
+    free(g->alias);
 }
 
 static int check_csr(int64_t n, const int64_t *row_ptr, const int32_t *col)
@@ -190,12 +278,18 @@ static int check_csr(int64_t n, const int64_t *row_ptr, const int32_t *col)
     return ORC_OK;
 }
 
-/* Index of the next state inside row l (0 <= j < deg(l)), Definition 1 (ii). */
-static int64_t select_next(const ograph *g, int64_t l, uint64_t u)
+/* Index of the next state inside row l (0 <= j < deg(l)), Definition 1 (ii).
+ * u2 is the second random word (alias mode only). */
+static int64_t select_next(const ograph *g, int64_t l, uint64_t u, uint64_t u2)
 {
     int64_t deg = g->row_ptr[l + 1] - g->row_ptr[l];
     if (!g->val)
         return oracle_uniform_index(u, deg);
+    if (g->aprob) {
+        int64_t i = oracle_uniform_index(u, deg);
+        double v53 = (double)(u2 >> 11) * 0x1p-53;
+        return v53 < g->aprob[g->row_ptr[l] + i] ? i : g->alias[g->row_ptr[l] + i];
+    }
     {
         double u53 = (double)(u >> 11) * 0x1p-53;
         double target = u53 * g->rowabs[l];
@@ -208,7 +302,7 @@ static int64_t select_next(const ograph *g, int64_t l, uint64_t u)
 }
 
 int64_t oracle_select_next(int64_t n, const int64_t *row_ptr, const int32_t *col,
-                           const double *val, int64_t l, uint64_t u)
+                           const double *val, int64_t l, uint64_t u, uint64_t u2)
 {
     ograph g;
     int64_t j;
@@ -219,9 +313,34 @@ int64_t oracle_select_next(int64_t n, const int64_t *row_ptr, const int32_t *col
         release(&g);
         return -1;
     }
-    j = select_next(&g, l, u);
+    j = select_next(&g, l, u, u2);
     release(&g);
     return j;
+}
+
+/* Alias mode's tables of a weighted CSR (prob and alias per stored entry,
+ * alias as an index inside the row).  Returns 0, or an ORC_E_* code. */
+int oracle_alias_table(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val,
+                       double *prob, int64_t *alias)
+{
+    ograph g;
+    int64_t e, nnz;
+    int rc, prev = g_alias_mode;
+    if (!val || check_csr(n, row_ptr, col) != ORC_OK)
+        return ORC_E_ARG;
+    g.n = n; g.row_ptr = row_ptr; g.col = col; g.val = val;
+    g_alias_mode = 1;
+    rc = prepare(&g);
+    g_alias_mode = prev;
+    if (rc == ORC_OK) {
+        nnz = row_ptr[n];
+        for (e = 0; e < nnz; ++e) {
+            prob[e] = g.aprob[e];
+            alias[e] = g.alias[e];
+        }
+    }
+    release(&g);
+    return rc;
 }
 
 /* One walk from start row k (walk index w).  Records the visited states and
@@ -258,7 +377,7 @@ static int walk(const ograph *g, const oparams *p, int64_t k, uint32_t w,
         key[1] = (uint32_t)(p->seed >> 32);
         oracle_philox4x32_10(ctr, key, x);
         u = ((uint64_t)x[1] << 32) | (uint64_t)x[0];
-        e = g->row_ptr[l] + select_next(g, l, u);
+        e = g->row_ptr[l] + select_next(g, l, u, ((uint64_t)x[3] << 32) | (uint64_t)x[2]);
         a = entry(g, e);
         W = W * (p->s * g->rowabs[l]);
         if (a < 0.0)

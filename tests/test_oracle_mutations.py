@@ -50,6 +50,13 @@ MUTATIONS = {
     "philox multiplier of word 0": ("0xD2511F53u, 0xCD9E8D57u", "0xD2511F55u, 0xCD9E8D57u"),
     "philox multiplier of word 2": ("0xD2511F53u, 0xCD9E8D57u", "0xD2511F53u, 0xCD9E8D59u"),
     "philox multipliers swapped": ("0xD2511F53u, 0xCD9E8D57u", "0xCD9E8D57u, 0xD2511F53u"),
+    "alias leftover mass": ("q[big] = (q[big] + q[s]) - 1.0;", "q[big] = q[big] - q[s];"),
+    "alias scaled without the row length": ("q[j] = (fabs(entry(g, b + j)) * (double)d) / W;",
+                                            "q[j] = fabs(entry(g, b + j)) / W;"),
+    "alias keep and alias swapped": ("v53 < g->aprob[g->row_ptr[l] + i] ? i : g->alias[g->row_ptr[l] + i]",
+                                     "v53 < g->aprob[g->row_ptr[l] + i] ? g->alias[g->row_ptr[l] + i] : i"),
+    "alias second word is the first": ("select_next(g, l, u, ((uint64_t)x[3] << 32) | (uint64_t)x[2])",
+                                       "select_next(g, l, u, u)"),
 }
 
 PINS = [
@@ -61,8 +68,11 @@ PINS = [
     lambda orc: P.test_complete_bipartite_diag_closed_form(orc, 3, 5),
     lambda orc: P.test_regular_graph_action_on_ones(orc, lambda: P.G.torus2d(6, 7)),
     lambda orc: P.test_expectation_mode_equals_dense_series(orc, 6),
-    lambda orc: P.test_unbiased(orc, "weighted"),
-    lambda orc: P.test_unbiased(orc, "rmat"),
+    lambda orc: P.test_unbiased(orc, "weighted", "cdf"),
+    lambda orc: R.test_alias_table_reproduces_row_distribution(orc),
+    lambda orc: R.test_alias_sampler_frequencies(orc),
+    lambda orc: P.test_unbiased(orc, "weighted", "alias"),
+    lambda orc: P.test_unbiased(orc, "rmat", "cdf"),
     lambda orc: P.test_complete_graph_exp_diag_closed_form(orc),
     lambda orc: P.test_error_decays_as_inverse_sqrt_N(orc),
     lambda orc: P.test_allocation_follows_column_norms(orc, "weighted", False),

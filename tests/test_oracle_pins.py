@@ -221,8 +221,9 @@ def _z_test(estimates, exact, tol=5.0):
     return z.max() if z.size else 0.0
 
 
-@pytest.mark.parametrize("which", ["er", "rmat", "weighted", "path"])
-def test_unbiased(orc, which):
+@pytest.mark.parametrize("which,sampler", [("er", "cdf"), ("rmat", "cdf"), ("weighted", "cdf"),
+                                           ("weighted", "alias"), ("path", "cdf")])
+def test_unbiased(orc, which, sampler):
     g = {"er": lambda: G.erdos_renyi_dense(30, 0.2, seed=11),
          "rmat": lambda: G.rmat(6, seed=3),
          "weighted": lambda: G.with_random_weights(G.erdos_renyi_dense(25, 0.25, seed=5), seed=6,
@@ -234,8 +235,8 @@ def test_unbiased(orc, which):
     dense = orc.dense_series(g.dense(), c, s)
     v = G.uniform_vector(g.n, seed=2)
     R = 40
-    ys = [orc.action(g, c, v, N=16, K=K, scale=s, seed=77, request=r)["y"] for r in range(R)]
-    ds = [orc.diag(g, c, N=16, K=K, scale=s, seed=77, request=r)["d"] for r in range(R)]
+    ys = [orc.action(g, c, v, N=16, K=K, scale=s, seed=77, request=r, sampler=sampler)["y"] for r in range(R)]
+    ds = [orc.diag(g, c, N=16, K=K, scale=s, seed=77, request=r, sampler=sampler)["d"] for r in range(R)]
     # 5 sigma over ~100 entries: a wrong term or sign fails by many sigma.
     assert _z_test(ys, dense @ v) < 5.0
     assert _z_test(ds, np.diag(dense)) < 5.0

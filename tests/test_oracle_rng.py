@@ -137,3 +137,68 @@ def test_unweighted_sampler_is_uniform_index(orc):
         assert orc.select_next(g, 0, int(u)) == orc.uniform_index(int(u), 9)
     assert orc.select_next(g, 0, 0) == 0
     assert orc.select_next(G.from_edges(3, [0], [1]), 2, 5) == -1  # no entries
+
+
+def _alias_rows():
+    """Weighted rows that stress the alias construction: random signed
+    weights, exact zeros, all-equal weights, one dominant entry, rows of one
+    entry, a row whose weights are all zero, and a long skewed row."""
+    rng = np.random.default_rng(17)
+    rows = [rng.uniform(0.1, 2.0, 7) * np.where(rng.random(7) < 0.4, -1, 1),
+            np.array([0.5, 0.0, 1.5, 0.0, 2.0]),
+            np.full(6, 0.75),
+            np.array([1e-9, 1e-9, 5.0, 1e-9]),
+            np.array([-3.0]),
+            np.array([0.0, 0.0, 0.0]),
+            rng.pareto(1.2, 300) + 1e-3]
+    n = max(len(r) for r in rows)
+    row_ptr = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64)
+    col = np.concatenate([np.arange(len(r)) for r in rows]).astype(np.int32)
+    # Rows past the last listed one are empty; column indices stay below n.
+    n = max(n, len(rows))
+    row_ptr = np.concatenate([row_ptr, np.full(n - len(rows), row_ptr[-1])]).astype(np.int64)
+    return G.CSR(n, row_ptr, col, np.concatenate(rows).astype(np.float64), "alias-rows"), rows
+
+
+def test_alias_table_reproduces_row_distribution(orc):
+    # Walker's alias method: entry j is drawn with probability
+    # (prob_j + sum over i with alias_i = j of (1 - prob_i)) / d, which must be
+    # |a_j| / sum |a| (Definition 1 (ii)); a row of zeros is drawn uniformly.
+    g, rows = _alias_rows()
+    prob, alias = orc.alias_table(g)
+    for r, w in enumerate(rows):
+        lo, d = int(g.row_ptr[r]), len(w)
+        p, a = prob[lo:lo + d], alias[lo:lo + d]
+        assert np.all((p >= 0) & (p <= 1)) and np.all((a >= 0) & (a < d))
+        implied = p.copy()
+        np.add.at(implied, a, 1.0 - p)
+        implied /= d
+        want = np.abs(w) / np.abs(w).sum() if np.abs(w).sum() > 0 else np.full(d, 1.0 / d)
+        assert np.allclose(implied, want, rtol=1e-12, atol=1e-15), r
+    # All-equal weights need no alias at all.
+    lo = int(g.row_ptr[2])
+    assert np.all(prob[lo:lo + 6] == 1.0) and np.all(alias[lo:lo + 6] == np.arange(6))
+
+
+def test_alias_sampler_frequencies(orc):
+    # Drawing through the tables with independent words (u, u2) gives the
+    # row's distribution; u2 = 0 keeps the uniform pick whenever prob > 0.
+    g = G.with_random_weights(G.complete(6), seed=3, negative_fraction=0.4)
+    row = 2
+    lo, hi = g.row_ptr[row], g.row_ptr[row + 1]
+    w = np.abs(g.val[lo:hi])
+    rng = np.random.default_rng(12)
+    us = rng.integers(0, 2**64, (20000, 2), dtype=np.uint64, endpoint=False)
+    js = np.array([orc.select_next(g, row, int(u), int(u2), sampler="alias") for u, u2 in us])
+    assert js.min() >= 0 and js.max() < hi - lo
+    hist = np.bincount(js, minlength=hi - lo)
+    exp = us.shape[0] * w / w.sum()
+    assert ((hist - exp) ** 2 / exp).sum() < 25  # 4 d.o.f.
+    prob, alias = orc.alias_table(g)
+    for u in rng.integers(0, 2**64, 50, dtype=np.uint64, endpoint=False):
+        i = orc.uniform_index(int(u), hi - lo)
+        assert orc.select_next(g, row, int(u), 0, sampler="alias") == (i if prob[lo + i] > 0 else alias[lo + i])
+        want = i if prob[lo + i] == 1.0 else alias[lo + i]
+        assert orc.select_next(g, row, int(u), 2**64 - 1, sampler="alias") == want
+    # Unweighted rows ignore the mode.
+    assert orc.select_next(G.star(9), 0, 2**63, 5, sampler="alias") == orc.uniform_index(2**63, 9)

@@ -216,14 +216,28 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
                                up to 1024 hubs (the chunks a start row needs, loaded
                                with the step's record); the walk sums <Q_k, C_h> for
                                all those hubs as it goes and the gather skips them */
+#define MCMF_SAMPLER_ALIAS 4 /* weighted graphs only, action or diagonal: Walker's alias
+                               method (Vose's construction) instead of the running sums
+                               of |a|.  Entry i = floor(u deg / 2^64) from Philox words
+                               X0:X1 is kept when the 53-bit uniform from X2:X3 is below
+                               its probability, else its alias is taken: one 16-byte
+                               record per step instead of a binary search.  Same law
+                               (Definition 1 (ii)), other paths.  The default for both
+                               walks on weighted graphs; the records (16 bytes per stored
+                               entry) are built with the graph.  EDGE or ROW select the
+                               running sums of |a| instead */
 
-/* Per-graph choices of the walk kernels and of the diagonal gather.  They
- * change memory traffic and the order of floating-point sums only: walk paths
- * and step counts never change.  Defaults: action VALUE with cached loads;
- * diag ROW with cached loads when the column array and row records take at
- * most 16 MiB (4 nnz + 8 n bytes; they then stay in cache), else EDGE with
- * cached loads; automatic hub threshold.  The batched walks (mcmf_batch and
- * the server) always use EDGE records, or value records for actions.
+/* Per-graph choices of the walk kernels and of the diagonal gather.  On
+ * unweighted graphs they change memory traffic and the order of
+ * floating-point sums only: walk paths and step counts never change.  On
+ * weighted graphs ALIAS and the running sums (EDGE, ROW) draw other paths
+ * from the same law.  Defaults: action VALUE with cached loads; diag ROW
+ * with cached loads when the column array and row records take at most
+ * 16 MiB (4 nnz + 8 n bytes; they then stay in cache), WIDE where the graph
+ * has wide hubs, else EDGE with cached loads; ALIAS for both walks on
+ * weighted graphs; automatic hub threshold.  The batched walks (mcmf_batch
+ * and the server) use EDGE records (value records for unweighted actions,
+ * alias records for weighted rows when the graph's layout is ALIAS).
  *
  * Hub rows: a graph created unweighted with MCMF_SYMMETRIC and strictly
  * increasing columns in every row keeps its (at most 32) rows of largest
@@ -277,6 +291,8 @@ typedef struct {
                                   the automatic threshold / off (0 without hubs) */
     double wide_ms;            /* mcmf_tune only: ms of the same with wide hub sums
                                   (MCMF_SAMPLER_WIDE; 0 without wide hubs) */
+    double alias_ms[2];        /* mcmf_tune only, weighted graphs: ms of the action and the
+                                  diagonal walk with MCMF_SAMPLER_ALIAS (0 otherwise) */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the
@@ -293,7 +309,8 @@ mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t);
  * diagonal gather (every neighbour of the sampled rows requested) at work
  * items of 128, 256, 512 and 1024 neighbours; and, on graphs with hub rows,
  * diagonal walk plus gather with hub sums at the automatic threshold and
- * off, and with wide hub sums where the graph has wide hubs.  It keeps the fastest of each and stores it in the graph
+ * off, and with wide hub sums where the graph has wide hubs; on weighted
+ * graphs, both walks with the running sums and with alias records.  It keeps the fastest of each and stores it in the graph
  * (mcmf_graph_set_tuning).  out receives the choice and the measured times.  The caller may cache the result by a
  * fingerprint of the graph and reapply it with mcmf_graph_set_tuning.
  * Errors: as mcmf_action (K >= 2, n_walks >= 1 required), MCMF_E_NOMEM,

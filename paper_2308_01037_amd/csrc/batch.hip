@@ -542,7 +542,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         Prep &P = *preps[i];
         BReq &B = hreq[i];
         memset(&B, 0, sizeof B);
-        B.g = walk::view(q.graph);
+        B.g = walk::view(q.graph, (q.kind == MCMF_REQ_DIAG ? q.graph->tuning.diag_sampler
+                                                            : q.graph->tuning.action_sampler) == MCMF_SAMPLER_ALIAS);
         mcmf_opts oo = {};
         oo.seed = q.seed;
         oo.request_id = q.request_id;

@@ -164,6 +164,10 @@ struct mcmf_graph {
     double *val = nullptr;      // [nnz] or null
     double *rowabs = nullptr;   // [n] sum |a| (weighted only)
     double *cum = nullptr;      // [nnz] running sums of |a| per row (weighted only)
+    // [nnz] alias records of weighted rows, built on first use of
+    // MCMF_SAMPLER_ALIAS: {col_j | sign_j << 31, col_a | sign_a << 31,
+    // prob_j low word, high word} with a = alias_j (sign: a < 0).
+    uint4 *alias_rec = nullptr;
     double *diagval = nullptr;  // [n] a_ii (only when the graph has loops)
     uint2 *node = nullptr;      // [n] {first entry, row length}
     // [nnz] per stored entry a_ij: {j, first entry of row j, length of row j,
@@ -183,7 +187,7 @@ struct mcmf_graph {
     size_t bytes = 0;
     // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
     mcmf_tuning tuning = {MCMF_SAMPLER_VALUE, 0, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {0, 0},
-                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}, 0};
+                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}, 0, {0, 0}};
     // Hub rows (unweighted symmetric graphs with strictly increasing rows):
     // the rows of largest degree, at most kMaxHubs.  hubmask[j] has bit h set
     // when j is a column of row hub_rows[h] (by symmetry: when j is adjacent

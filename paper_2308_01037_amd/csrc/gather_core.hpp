@@ -368,14 +368,6 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
 
     for (int64_t w0 = 0; w0 < j.N; w0 += j.walks_per_pass) {
         const int64_t nw = (j.N - w0 < j.walks_per_pass) ? (j.N - w0) : j.walks_per_pass;
-        __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
-            tab.keys[i] = kEmpty;
-            tab.vals[i] = 0.0;
-        }
-        for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
-            tab.filter[i] = 0u;
-        __syncthreads();
         const int64_t count = nw * (j.K - 1);
         // An item of one neighbour batch whose columns hold fewer entries than
         // half the visits: the table takes those entries as keys and the
@@ -386,9 +378,21 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
         bool restricted = false;
         if (single) {
             total0 = setup_batch(j.p_begin, j.p_end - j.p_begin);
+            // Nothing to probe (every neighbour unrequested or summed by the
+            // walk): no table either.
+            if (total0 == 0)
+                continue;
             // total0 * kChunk bounds the batch's column entries from above.
             restricted = uint64_t(total0) * kChunk * kRestrictNum <= static_cast<uint64_t>(count) * kRestrictDen;
         }
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
+            tab.keys[i] = kEmpty;
+            tab.vals[i] = 0.0;
+        }
+        for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
+            tab.filter[i] = 0u;
+        __syncthreads();
         if (restricted) {
             // (1') the column entries of the batch as keys.
             const uint32_t per = (total0 + kGroups - 1) / kGroups;

@@ -20,6 +20,9 @@ Status fill_u64(uint64_t *out, uint64_t value, int64_t n, hipStream_t s);
 // row per adjacent start row); 0 without hubs.
 uint32_t active_hubs(const mcmf_graph *g, int64_t n_walks, int K);
 
+// Builds the graph's alias records (weighted graphs; once, synchronously).
+Status ensure_alias(mcmf_graph *g);
+
 // Wide hubs (degree descending) whose sums the wide diagonal walk takes for
 // n_walks and K: the prefix of degree >= the same threshold; 0 without them.
 int32_t active_wide_hubs(const mcmf_graph *g, int64_t n_walks, int K);

@@ -36,8 +36,9 @@ Status check_tuning(const mcmf_tuning *t) {
         return fail(MCMF_E_ARG, "tuning is NULL");
     auto sampler_ok = [](int32_t v) { return v == MCMF_SAMPLER_EDGE || v == MCMF_SAMPLER_ROW; };
     auto flag_ok = [](int32_t v) { return v == 0 || v == 1; };
-    if (!(sampler_ok(t->action_sampler) || t->action_sampler == MCMF_SAMPLER_VALUE) ||
-        !(sampler_ok(t->diag_sampler) || t->diag_sampler == MCMF_SAMPLER_WIDE))
+    if (!(sampler_ok(t->action_sampler) || t->action_sampler == MCMF_SAMPLER_VALUE ||
+          t->action_sampler == MCMF_SAMPLER_ALIAS) ||
+        !(sampler_ok(t->diag_sampler) || t->diag_sampler == MCMF_SAMPLER_WIDE || t->diag_sampler == MCMF_SAMPLER_ALIAS))
         return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only, WIDE for the diagonal)");
     if (!flag_ok(t->action_stream) || !flag_ok(t->diag_stream))
         return fail(MCMF_E_ARG, "stream flags must be 0 or 1");
@@ -73,6 +74,7 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     for (double &x : best.hub_ms)
         x = 0.0;
     best.wide_ms = 0.0;
+    best.alias_ms[0] = best.alias_ms[1] = 0.0;
     if (g->n_active == 0) {
         *out = best;
         return {};
@@ -181,6 +183,26 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     }
     best.diag_sampler = bd >> 1;
     best.diag_stream = bd & 1;
+    // Weighted graphs: the running sums (any of the four above) against the
+    // alias records.
+    if (g->weighted) {
+        MCMF_TRY(ensure_alias(g));
+        p.sampler = MCMF_SAMPLER_ALIAS;
+        p.stream = 0;
+        MCMF_TRY(time_it([&]() { return action_walks(g, r.ptr, rows.ptr, m, p, q.ptr, nullptr, steps.ptr, s); },
+                         &best.alias_ms[0]));
+        MCMF_TRY(time_it([&]() {
+            return diag_walks(g, rows.ptr, m, p, vstate.ptr, vx.ptr, nullptr, steps.ptr, s);
+        }, &best.alias_ms[1]));
+        if (best.alias_ms[0] < best.action_ms[ba]) {
+            best.action_sampler = MCMF_SAMPLER_ALIAS;
+            best.action_stream = 0;
+        }
+        if (best.alias_ms[1] < best.diag_ms[bd]) {
+            best.diag_sampler = MCMF_SAMPLER_ALIAS;
+            best.diag_stream = 0;
+        }
+    }
     p.sampler = best.diag_sampler;
     p.stream = best.diag_stream;
 
@@ -296,6 +318,15 @@ extern "C" mcmf_status mcmf_graph_set_tuning(mcmf_graph *g, const mcmf_tuning *t
     if (t->diag_sampler == MCMF_SAMPLER_WIDE && g->n_whubs == 0) {
         mcmf::fail(MCMF_E_ARG, "diag_sampler WIDE needs a graph with wide hubs");
         return MCMF_E_ARG;
+    }
+    if ((t->action_sampler == MCMF_SAMPLER_ALIAS || t->diag_sampler == MCMF_SAMPLER_ALIAS) && !g->weighted) {
+        mcmf::fail(MCMF_E_ARG, "the ALIAS sampler is for weighted graphs");
+        return MCMF_E_ARG;
+    }
+    if (t->action_sampler == MCMF_SAMPLER_ALIAS || t->diag_sampler == MCMF_SAMPLER_ALIAS) {
+        st = mcmf::ensure_alias(g);
+        if (st)
+            return st.code;
     }
     g->tuning.action_sampler = t->action_sampler;
     g->tuning.action_stream = t->action_stream;

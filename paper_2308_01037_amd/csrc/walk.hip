@@ -275,10 +275,10 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
     if (n_start <= 0 || p.K < 2)
         return {};
     const WalkArgs a = walk::to_args(p);
-    const GraphView gv = walk::view(g);
+    const int sampler = p.sampler >= 0 ? p.sampler : g->tuning.action_sampler;
+    const GraphView gv = walk::view(g, sampler == MCMF_SAMPLER_ALIAS);
     const int threads = p.threads >= 0 ? p.threads : g->tuning.walk_threads;
     const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks, threads));
-    const int sampler = p.sampler >= 0 ? p.sampler : g->tuning.action_sampler;
     const bool stream = (p.stream >= 0 ? p.stream : g->tuning.action_stream) != 0;
     if (sampler == MCMF_SAMPLER_VALUE && !g->weighted && !digest && value_records_fit(g)) {
         DevBuf<uint4> rec;
@@ -323,7 +323,8 @@ Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, c
     if (n_start <= 0 || p.K < 2)
         return {};
     const WalkArgs a = walk::to_args(p);
-    const GraphView gv = walk::view(g);
+    const GraphView gv =
+        walk::view(g, (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_ALIAS);
     const int threads = p.threads >= 0 ? p.threads : g->tuning.walk_threads;
     const dim3 grid = walk_grid(n_start), block(p.row_walks ? 256 : walk_block(p.n_walks, threads));
     if (wide_diag(g, p)) {

@@ -78,9 +78,12 @@ struct GraphView {
     const double *cum;
     const uint32_t *hubmask; // per node: adjacent hubs (null: no hubs)
     const int32_t *hub_row;  // hub index -> row
+    const uint4 *alias;      // weighted rows: alias records (null: running sums)
 };
 
-inline GraphView view(const mcmf_graph *g) {
+// The graph's arrays for a walk launch; alias: weighted rows sample through
+// the alias records (built by then).
+inline GraphView view(const mcmf_graph *g, bool alias = false) {
     GraphView v;
     v.node = g->node;
     v.edge = g->edge;
@@ -90,6 +93,7 @@ inline GraphView view(const mcmf_graph *g) {
     v.cum = g->cum;
     v.hubmask = g->hubmask;
     v.hub_row = g->hub_rows;
+    v.alias = alias && g->weighted ? g->alias_rec : nullptr;
     return v;
 }
 
@@ -128,7 +132,9 @@ __device__ __forceinline__ int32_t load_col(const int32_t *c) {
 // Unweighted rows either read one edge record (EDGE: the entry carries the
 // next row's record) or the column and then the next row's record (two
 // dependent loads, but 4 + 8 bytes instead of 16 and a row-record array
-// that caches well); both pick the same entry.
+// that caches well); both pick the same entry.  Weighted rows search the
+// running sums of |a|, or read one alias record (g.alias); the two map the
+// random words to entries differently, with the same probabilities.
 template <bool WEIGHTED, class WT, bool STREAM = false, bool EDGE = true>
 __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, double scale,
                                     WT &W) {
@@ -149,6 +155,22 @@ __device__ __forceinline__ Pos step(const GraphView &g, const Pos &p, uint4 x, d
             n.deg = r.y;
             n.hm = 0u;
         }
+    } else if (g.alias) {
+        // Alias method: entry i = floor(u deg / 2^64) from X0:X1, kept when
+        // the 53-bit uniform from X2:X3 is below prob_i, else its alias.
+        const double ra = g.rowabs[p.l];
+        const uint32_t i = dev::uniform_index(x.x, x.y, p.deg);
+        const uint4 r = g.alias[int64_t(p.start) + i];
+        const double prob = __hiloint2double(static_cast<int>(r.w), static_cast<int>(r.z));
+        const uint32_t c = dev::unit53(x.z, x.w) < prob ? r.x : r.y;
+        W = W * static_cast<WT>(scale * ra);
+        if (c >> 31)
+            W = -W;
+        n.l = c & 0x7fffffffu;
+        const uint2 nr = g.node[n.l];
+        n.start = nr.x;
+        n.deg = nr.y;
+        n.hm = 0u;
     } else {
         const double ra = g.rowabs[p.l];
         const uint32_t j = cdf_search(g.cum + p.start, p.deg, dev::unit53(x.x, x.y) * ra);

@@ -61,6 +61,7 @@ MCMF_SAMPLER_EDGE = 0
 MCMF_SAMPLER_ROW = 1
 MCMF_SAMPLER_VALUE = 2
 MCMF_SAMPLER_WIDE = 3
+MCMF_SAMPLER_ALIAS = 4
 
 
 class mcmf_fn(ctypes.Structure):
@@ -95,7 +96,8 @@ class mcmf_tuning(ctypes.Structure):
                 ("hub_count", ctypes.c_int32), ("action_value_ms", ctypes.c_double * 2),
                 ("walk_threads", ctypes.c_int32), ("gather_item", ctypes.c_int32),
                 ("walk_threads_ms", ctypes.c_double * 3), ("gather_item_ms", ctypes.c_double * 4),
-                ("hub_ms", ctypes.c_double * 2), ("wide_ms", ctypes.c_double)]
+                ("hub_ms", ctypes.c_double * 2), ("wide_ms", ctypes.c_double),
+                ("alias_ms", ctypes.c_double * 2)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
@@ -106,7 +108,7 @@ class mcmf_tuning(ctypes.Structure):
                 "walk_threads": self.walk_threads, "gather_item": self.gather_item,
                 "walk_threads_ms": list(self.walk_threads_ms),
                 "gather_item_ms": list(self.gather_item_ms), "hub_ms": list(self.hub_ms),
-                "wide_ms": self.wide_ms}
+                "wide_ms": self.wide_ms, "alias_ms": list(self.alias_ms)}
 
 
 MCMF_REQ_DIAG = 0

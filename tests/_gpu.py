@@ -21,6 +21,12 @@ def oracle_fn(fn):
     return np.asarray(fn, dtype=np.float64)
 
 
+def default_sampler(csr):
+    """The oracle's sampler mode for the library's default layout: weighted
+    rows walk by the alias method, unweighted rows are not affected."""
+    return "alias" if getattr(csr, "val", None) is not None else "cdf"
+
+
 def graph(csr, flags=M.MCMF_SYMMETRIC):
     return M.Graph.from_csr(csr, flags=flags)
 

@@ -6,7 +6,7 @@ import torch
 
 import graphgen as G
 import oracle
-from _gpu import assert_close, assert_mc_part_close, fn_struct, graph, oracle_fn
+from _gpu import assert_close, assert_mc_part_close, default_sampler, fn_struct, graph, oracle_fn
 from paper_2308_01037_amd import mcmf as M
 
 RTOL = 1e-10
@@ -82,10 +82,12 @@ class Req:
         """The oracle's result for this request (FP64, with path digests)."""
         if self.kind == M.MCMF_REQ_ACTION:
             o = oracle.action(self.csr, oracle_fn(self.fn), self.v, N=self.N, K=self.K, scale=self.scale,
-                              seed=self.seed, request=self.request, cutoff=self.cutoff, want_digest=True)
+                              seed=self.seed, request=self.request, cutoff=self.cutoff, want_digest=True,
+                              sampler=default_sampler(self.csr))
             return {"x": o["y"], "digest": o["digest"], "steps": o["steps"]}
         o = oracle.diag(self.csr, oracle_fn(self.fn), N=self.N, K=self.K, scale=self.scale, seed=self.seed,
-                        request=self.request, cutoff=self.cutoff, rows=self.rows, want_digest=True)
+                        request=self.request, cutoff=self.cutoff, rows=self.rows, want_digest=True,
+                        sampler=default_sampler(self.csr))
         return {"x": o["d"], "digest": o["digest"], "steps": o["steps"]}
 
     def h(self):

@@ -19,7 +19,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from _gpu import assert_close, fn_struct, graph, oracle_fn  # noqa: E402
+from _gpu import assert_close, default_sampler, fn_struct, graph, oracle_fn  # noqa: E402
 from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
 
@@ -79,7 +79,7 @@ def test_diag_with_norm_allocation(maker, subset, per_row, alloc, min_one, monke
     assert st["walks"] == int(want_walks.sum())
     assert st["start_rows"] == int(np.count_nonzero(want_walks))
     o = oracle.diag(csr, oracle_fn("exp"), N=1, K=K, scale=scale, seed=2, rows=rows, want_digest=True,
-                    walks=want_walks)
+                    walks=want_walks, sampler=default_sampler(csr))
     assert np.array_equal(dig, o["digest"])
     assert st["walk_steps"] == o["steps"]
     assert_close(d, o["d"], 1e-10, atol=1e-13 * np.max(np.abs(o["d"])))
@@ -109,7 +109,7 @@ def test_action_with_norm_allocation(directed, per_row, alloc, min_one):
                                    min_one=min_one)
     assert np.array_equal(walks, want_walks) and np.array_equal(walks32, want_walks)
     o = oracle.action(csr, oracle_fn("resolvent"), v, N=1, K=K, scale=scale, seed=2, want_digest=True,
-                      walks=want_walks)
+                      walks=want_walks, sampler=default_sampler(csr))
     assert np.array_equal(dig, o["digest"]) and np.array_equal(dig32, o["digest"])
     assert st["walk_steps"] == o["steps"]
     assert_close(y, o["y"], 1e-10, atol=1e-13 * np.max(np.abs(o["y"])))
@@ -137,10 +137,12 @@ def test_rows_without_walks_keep_only_H():
     h = np.array([c[0] * v[50] + c[1] * (s * (v[50] + v[51])), c[0] * v[51] + c[1] * (s * v[50])])
     assert np.all(np.abs(y[50:] - h) <= 2 * np.finfo(float).eps * h)
     assert dig[50] == 0 and dig[51] == 0 and st["start_rows"] == 50
-    o = oracle.diag(csr, oracle_fn("exp"), N=1, K=K, scale=s, seed=2, walks=walks, want_digest=True)
+    o = oracle.diag(csr, oracle_fn("exp"), N=1, K=K, scale=s, seed=2, walks=walks, want_digest=True,
+                    sampler=default_sampler(csr))
     assert np.array_equal(dig, o["digest"])
     assert_close(d, o["d"], 1e-10)
-    o = oracle.action(csr, oracle_fn("exp"), v, N=1, K=K, scale=s, seed=2, walks=walks)
+    o = oracle.action(csr, oracle_fn("exp"), v, N=1, K=K, scale=s, seed=2, walks=walks,
+                      sampler=default_sampler(csr))
     assert_close(y, o["y"], 1e-10)
 
 

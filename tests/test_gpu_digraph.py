@@ -15,7 +15,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from _gpu import assert_close, gpu_action, gpu_diag, oracle_fn  # noqa: E402
+from _gpu import assert_close, default_sampler, gpu_action, gpu_diag, oracle_fn  # noqa: E402
 from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
 
@@ -50,12 +50,14 @@ def test_digraph_symmetrised_matches_oracle(weighted, device_input):
         assert g.info["n"] == 2 * a.shape[0] and g.info["nnz"] == 2 * a.nnz
         scale = 1.0 / max(1.0, float(abs(b).sum(axis=1).max()))
         for fn in ("exp", "resolvent"):
-            o = oracle.diag(bcsr, oracle_fn(fn), N=64, K=12, scale=scale, seed=4, want_digest=True)
+            o = oracle.diag(bcsr, oracle_fn(fn), N=64, K=12, scale=scale, seed=4, want_digest=True,
+                            sampler=default_sampler(bcsr))
             r = gpu_diag(g, fn, 64, 12, scale, seed=4, want_digest=True)
             assert np.array_equal(r["digest"], o["digest"])
             assert_close(r["d"], o["d"], 1e-10, atol=1e-13 * np.max(np.abs(o["d"])))
             v = np.random.default_rng(5).random(b.shape[0])
-            o = oracle.action(bcsr, oracle_fn(fn), v, N=64, K=12, scale=scale, seed=4, want_digest=True)
+            o = oracle.action(bcsr, oracle_fn(fn), v, N=64, K=12, scale=scale, seed=4, want_digest=True,
+                              sampler=default_sampler(bcsr))
             r = gpu_action(g, fn, v, 64, 12, scale, seed=4, want_digest=True)
             assert np.array_equal(r["digest"], o["digest"])
             assert_close(r["y"], o["y"], 1e-10, atol=1e-13 * np.max(np.abs(o["y"])))

@@ -17,7 +17,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs a GPU", allow_module_level=True)
 
-from _gpu import (assert_close, assert_mc_part_close, gpu_action, gpu_diag, graph,  # noqa: E402
+from _gpu import (assert_close, assert_mc_part_close, default_sampler, gpu_action, gpu_diag, graph,  # noqa: E402
                   oracle_fn)
 from paper_2308_01037_amd import mcmf as M  # noqa: E402
 
@@ -44,7 +44,7 @@ def check_action(csr, fn, N, K, scale, seed=1, request=0, cutoff=0.0, v=None, fl
                  host=False):
     v = np.ones(csr.n) if v is None else v
     o = oracle.action(csr, oracle_fn(fn), v, N=N, K=K, scale=scale, seed=seed, request=request,
-                      cutoff=cutoff, want_q=True, want_digest=True)
+                      cutoff=cutoff, want_q=True, want_digest=True, sampler=default_sampler(csr))
     with graph(csr, flags) as g:
         r = gpu_action(g, fn, v, N, K, scale, seed, request, cutoff, want_q=True, want_digest=True,
                        stats=True, host=host)
@@ -58,7 +58,7 @@ def check_action(csr, fn, N, K, scale, seed=1, request=0, cutoff=0.0, v=None, fl
 
 def check_diag(csr, fn, N, K, scale, seed=1, request=0, cutoff=0.0, rows=None, host=False):
     o = oracle.diag(csr, oracle_fn(fn), N=N, K=K, scale=scale, seed=seed, request=request,
-                    cutoff=cutoff, rows=rows, want_digest=True)
+                    cutoff=cutoff, rows=rows, want_digest=True, sampler=default_sampler(csr))
     with graph(csr) as g:
         r = gpu_diag(g, fn, N, K, scale, seed, request, cutoff, rows=rows, want_digest=True,
                      stats=True, host=host)

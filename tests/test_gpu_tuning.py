@@ -177,15 +177,15 @@ def test_value_records_action_matches_edge_and_oracle(stream):
         M.mcmf_graph_set_tuning(g.handle, t)
         ws = 0.5 / float(np.max(np.add.reduceat(np.abs(wcsr.val), wcsr.row_ptr[:-1])))
         r = gpu_action(g, "exp", v, N, K, ws, seed=4)
-        o = oracle.action(wcsr, oracle_fn("exp"), v, N=N, K=K, scale=ws, seed=4)
+        o = oracle.action(wcsr, oracle_fn("exp"), v, N=N, K=K, scale=ws, seed=4)  # VALUE set: running sums
         assert_close(r["y"], o["y"], 1e-10)
 
 
 def test_default_diag_layout_by_size():
     """An unweighted graph whose column array and row records take at most
     16 MiB starts with the ROW layout for the diagonal walk; a larger one
-    with wide hubs starts with WIDE, a weighted graph with EDGE.  The
-    layouts give the same walks."""
+    with wide hubs starts with WIDE; a weighted graph starts with the alias
+    records for both walks.  The unweighted layouts give the same walks."""
     small, big = G.rmat(12, seed=4), G.rmat(18, seed=0)
     assert 4 * small.nnz + 8 * small.n <= (16 << 20) < 4 * big.nnz + 8 * big.n
     K, N, s = 12, 32, 1.0 / small.d_max
@@ -199,7 +199,8 @@ def test_default_diag_layout_by_size():
         assert np.array_equal(r_row["digest"], r_edge["digest"])
         assert_close(r_row["d"], r_edge["d"], 1e-12)
     with graph(G.with_random_weights(small, seed=1)) as g:
-        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_EDGE
+        t = M.mcmf_graph_get_tuning(g.handle)
+        assert (t.diag_sampler, t.action_sampler) == (M.MCMF_SAMPLER_ALIAS, M.MCMF_SAMPLER_ALIAS)
     with graph(big) as g:
         assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_WIDE
 

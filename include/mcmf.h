@@ -224,8 +224,9 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
                                record per step instead of a binary search.  Same law
                                (Definition 1 (ii)), other paths.  The default for both
                                walks on weighted graphs; the records (16 bytes per stored
-                               entry) are built with the graph.  EDGE or ROW select the
-                               running sums of |a| instead */
+                               entry, 12 more during the build) are built with the graph,
+                               which keeps the running sums when they do not fit.  EDGE or
+                               ROW select the running sums of |a| instead */
 
 /* Per-graph choices of the walk kernels and of the diagonal gather.  On
  * unweighted graphs they change memory traffic and the order of

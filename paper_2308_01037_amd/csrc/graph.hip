@@ -3,6 +3,7 @@
 // rows), plus the small utility kernels (fills, ordered compaction).
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -498,10 +499,16 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
         g->tuning.diag_sampler = MCMF_SAMPLER_WIDE;
     // Weighted rows walk by the alias method: one 16-byte record per step
     // instead of a binary search (4.6x faster diagonal walks and 3.6x faster
-    // action walks on a weighted R-MAT 20).
+    // action walks on a weighted R-MAT 20).  A graph whose records do not fit
+    // keeps the running sums.
     if (g->weighted) {
-        MCMF_TRY(ensure_alias(g));
-        g->tuning.action_sampler = g->tuning.diag_sampler = MCMF_SAMPLER_ALIAS;
+        const Status st = ensure_alias(g);
+        if (!st)
+            g->tuning.action_sampler = g->tuning.diag_sampler = MCMF_SAMPLER_ALIAS;
+        else if (st.code == MCMF_E_NOMEM)
+            clear_error();
+        else
+            return st;
     }
     return {};
 }
@@ -573,6 +580,10 @@ __global__ void k_build_alias(const uint2 *node, const int32_t *col, const doubl
 Status ensure_alias(mcmf_graph *g) {
     if (!g->weighted || g->alias_rec || g->nnz == 0)
         return {};
+    // Test hook: the alias records "do not fit" (MCMF_TEST_FAIL_ALIAS=1).
+    const char *no_room = getenv("MCMF_TEST_FAIL_ALIAS");
+    if (no_room && no_room[0] == '1')
+        return fail(MCMF_E_NOMEM, "alias records refused (MCMF_TEST_FAIL_ALIAS)");
     MCMF_HIP(hipSetDevice(g->device));
     hipStream_t s = g->stream;
     uint4 *rec = nullptr;

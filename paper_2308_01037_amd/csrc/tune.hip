@@ -184,9 +184,13 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
     best.diag_sampler = bd >> 1;
     best.diag_stream = bd & 1;
     // Weighted graphs: the running sums (any of the four above) against the
-    // alias records.
-    if (g->weighted) {
-        MCMF_TRY(ensure_alias(g));
+    // alias records (unless those do not fit).
+    Status alias_room = g->weighted ? ensure_alias(g) : Status{};
+    if (alias_room && alias_room.code != MCMF_E_NOMEM)
+        return alias_room;
+    if (alias_room)
+        clear_error();
+    if (g->weighted && !alias_room) {
         p.sampler = MCMF_SAMPLER_ALIAS;
         p.stream = 0;
         MCMF_TRY(time_it([&]() { return action_walks(g, r.ptr, rows.ptr, m, p, q.ptr, nullptr, steps.ptr, s); },

@@ -189,3 +189,29 @@ def test_tuner_times_the_alias_layout():
     o = oracle.diag(csr, oracle_fn("exp"), N=32, K=10, scale=s, seed=4, want_digest=True, sampler=mode)
     assert np.array_equal(r["digest"], o["digest"])
     assert_close(r["d"], o["d"], 1e-10)
+
+
+def test_graph_keeps_running_sums_when_alias_records_do_not_fit(monkeypatch):
+    # Creating a weighted graph never fails for want of room for its alias
+    # records: it keeps the running sums (EDGE), whose walks are the oracle's
+    # default mode; asking for ALIAS then reports MCMF_E_NOMEM.
+    csr = weighted(9, seed=4)
+    s = 0.5 / row_abs_max(csr)
+    monkeypatch.setenv("MCMF_TEST_FAIL_ALIAS", "1")
+    with graph(csr) as g:
+        t = M.mcmf_graph_get_tuning(g.handle)
+        assert (t.action_sampler, t.diag_sampler) != (M.MCMF_SAMPLER_ALIAS, M.MCMF_SAMPLER_ALIAS)
+        assert t.diag_sampler != M.MCMF_SAMPLER_ALIAS
+        r = gpu_diag(g, "exp", 24, 8, s, seed=2, want_digest=True)
+        o = oracle.diag(csr, oracle_fn("exp"), N=24, K=8, scale=s, seed=2, want_digest=True)
+        assert np.array_equal(r["digest"], o["digest"])
+        assert_close(r["d"], o["d"], 1e-10)
+        with pytest.raises(M.MCMFError) as e:
+            use(g)
+        assert e.value.status == M.MCMF_E_NOMEM
+        monkeypatch.delenv("MCMF_TEST_FAIL_ALIAS")
+        use(g)  # room again: built on demand
+        r = gpu_diag(g, "exp", 24, 8, s, seed=2, want_digest=True)
+    o = oracle.diag(csr, oracle_fn("exp"), N=24, K=8, scale=s, seed=2, want_digest=True, sampler="alias")
+    assert np.array_equal(r["digest"], o["digest"])
+    assert_close(r["d"], o["d"], 1e-10)

@@ -71,7 +71,8 @@ def _exact_part(csr, fn, s, v):
     av = np.zeros(csr.n)
     for i in range(csr.n):
         a, b = csr.row_ptr[i], csr.row_ptr[i + 1]
-        av[i] = v[csr.col[a:b]].sum()
+        w = 1.0 if csr.val is None else csr.val[a:b]
+        av[i] = (w * v[csr.col[a:b]]).sum()
     return c0 * v + c1 * s * av
 
 
@@ -94,6 +95,17 @@ def test_two_calls_second_smaller():
             (small, "resolvent", 0.5 / small.d_max, 193, 21, True, "ER 700, resolvent, digest")):
         res, h = _both(csr, fn, s, N, K, seed=11, request=2, digest=digest)
         _check(res, h, what)
+
+
+def test_weighted_graph_walks_its_alias_records():
+    # A weighted graph walks by its alias records (built with the graph), so
+    # the no-allocation call needs no more memory there either.
+    csr = G.with_random_weights(G.rmat(11, seed=8), seed=9, negative_fraction=0.3)
+    with graph(csr) as g:
+        assert M.mcmf_graph_get_tuning(g.handle).action_sampler == M.MCMF_SAMPLER_ALIAS
+    ra = float(np.max(np.add.reduceat(np.abs(csr.val), csr.row_ptr[:-1][csr.deg > 0])))
+    res, h = _both(csr, "exp", 0.6 / ra, 96, 16, seed=3, request=1, digest=True)
+    _check(res, h, "weighted R-MAT 11, alias records")
 
 
 def test_errors_and_small_K():

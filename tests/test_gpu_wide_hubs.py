@@ -193,3 +193,19 @@ def test_graphs_without_wide_hubs_reject_the_layout():
         t.action_sampler, t.hub_count = M.MCMF_SAMPLER_WIDE, 0  # the diagonal's only
         with pytest.raises(M.MCMFError):
             M.mcmf_graph_set_tuning(g.handle, t)
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_wide_hubs_with_the_shortest_walks(K):
+    # K = 2 records only step 0 (the start row itself: every hub next to k
+    # gets the row's whole sum); K = 3 adds one transition.
+    csr = G.rmat(11, seed=13)
+    s = 0.7 / csr.d_max
+    sel = np.concatenate([G.random_rows(csr.n, 100, seed=5), top_rows(csr, 1024)[::9]]).astype(np.int32)
+    with graph(csr) as g:
+        for rows in (None, sel):
+            r = run3(g, "exp", 64, K, s, seed=7, rows=rows)
+            check_same(r)
+            o = oracle.diag(csr, oracle_fn("exp"), N=64, K=K, scale=s, seed=7, rows=rows, want_digest=True)
+            assert np.array_equal(r["wide"]["digest"], o["digest"])
+            assert_close(r["wide"]["d"], o["d"], 1e-10, what=f"K={K}")

@@ -17,9 +17,9 @@
 // up to the order of floating-point additions.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <type_traits>
 #include <utility>
-#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -814,25 +814,24 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         MCMF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        Status st = enqueue();
-        hipError_t ce = hipStreamEndCapture(s, &graph);
-        if (ce == hipErrorStreamCaptureInvalidated) {
-            // Another host thread made a call that invalidates captures in
-            // progress (the runtime checks some calls against every capture
-            // in the process).  Nothing captured has run: run the batch's
-            // launches directly instead.
+        // Test hook: the capture "fails" before its first launch (MCMF_TEST_FAIL_CAPTURE=1).
+        const char *refuse = getenv("MCMF_TEST_FAIL_CAPTURE");
+        const Status st = refuse && refuse[0] == '1' ? fail(MCMF_E_DEVICE, "capture refused (MCMF_TEST_FAIL_CAPTURE)")
+                                                     : enqueue();
+        const hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (st || ce != hipSuccess) {
+            // The capture failed.  Another host thread can make a call that
+            // invalidates captures in progress (the runtime checks some calls
+            // against every capture in the process); the runtime reports it
+            // at the next launch being recorded or at the end of the capture.
+            // Nothing captured has run: run the batch's launches directly
+            // instead (a genuine error then shows again, and is returned).
             (void)hipGetLastError();
             if (graph)
                 (void)hipGraphDestroy(graph);
             clear_error();
             MCMF_TRY(enqueue());
         } else {
-            if (st) {
-                if (graph)
-                    (void)hipGraphDestroy(graph);
-                return st;
-            }
-            MCMF_HIP(ce);
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (ie != hipSuccess) {
                 (void)hipGraphDestroy(graph);

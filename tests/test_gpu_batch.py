@@ -93,6 +93,21 @@ def test_graph_launch_matches_eager(graphs):
             check_same(q, g, w, f"eager after launch {rep}, request {i}")
 
 
+def test_failed_capture_runs_the_launches_directly(graphs, monkeypatch):
+    # A capture that fails (as when another host thread invalidates it) falls
+    # back to launching the batch directly: same results as eager.
+    reqs = _mixed(graphs)[:6]
+    eager, _ = run_batch(reqs)
+    monkeypatch.setenv("MCMF_TEST_FAIL_CAPTURE", "1")
+    got, _ = run_batch(reqs, use_graph=True)
+    monkeypatch.delenv("MCMF_TEST_FAIL_CAPTURE")
+    for i, (q, g, w) in enumerate(zip(reqs, got, eager)):
+        check_same(q, g, w, f"after a failed capture, request {i}")
+    got, _ = run_batch(reqs, use_graph=True)  # and the next capture works
+    for i, (q, g, w) in enumerate(zip(reqs, got, eager)):
+        check_same(q, g, w, f"capture after the failed one, request {i}")
+
+
 def test_many_small_requests(graphs):
     # 64 requests on one graph with distinct request ids: one batch equals 64
     # single calls.

@@ -14,6 +14,9 @@
   bit-exact paths against the oracle and the same estimates.  Every output
   must also satisfy x >= h (all terms are non-negative).  The sample
   includes a hub row, whose diagonal the walk kernel sums.
+* The same graph with signed random weights, walking through its alias
+  records: full diagonal and action against the oracle's alias mode on
+  sampled rows.
 """
 import numpy as np
 import pytest
@@ -134,3 +137,39 @@ def test_rmat20_bench_configuration(rmat20, fn):
     # Every term of the series is non-negative here: x >= h = c0 v + c1 s A v.
     assert np.all(np.isfinite(ra["y"])) and np.all(ra["y"] >= h_action * (1 - 1e-15))
     assert np.all(np.isfinite(rd["d"])) and np.all(rd["d"] >= c[0])
+
+
+def test_weighted_rmat20_alias_walks(rmat20):
+    # The R-MAT 20 workload with signed random weights: its walks go through
+    # the alias records (the weighted default, built with the graph).  Full
+    # diagonal and action at K = 40, N = 256, against the oracle's alias mode
+    # on sampled rows (paths bit-exact, estimates within 1e-10).
+    csr = G.with_random_weights(rmat20[0], seed=21, negative_fraction=0.25)
+    K, N = 40, 256
+    ra = float(np.max(np.add.reduceat(np.abs(csr.val), csr.row_ptr[:-1][csr.deg > 0])))
+    scale = 1.0 / ra
+    deg = csr.deg
+    rng = np.random.default_rng(7)
+    small = np.nonzero((deg > 0) & (deg <= 200))[0]
+    mid = np.nonzero((deg > 1000) & (deg <= 3000))[0]
+    rows = np.concatenate([rng.choice(small, 12, replace=False), rng.choice(mid, 1),
+                           np.nonzero(deg == 0)[0][:1]]).astype(np.int32)
+    v = G.uniform_vector(csr.n, seed=3)
+    with graph(csr) as g:
+        t = M.mcmf_graph_get_tuning(g.handle)
+        assert (t.action_sampler, t.diag_sampler) == (M.MCMF_SAMPLER_ALIAS, M.MCMF_SAMPLER_ALIAS)
+        ra_ = gpu_action(g, "exp", v, N, K, scale, seed=2, want_digest=True, stats=True)
+        rd = gpu_diag(g, "exp", N, K, scale, seed=2, want_digest=True, stats=True)
+    oa = oracle.action(csr, oracle.FN_EXP, v, N=N, K=K, scale=scale, seed=2, rows=rows, want_digest=True,
+                       sampler="alias")
+    od = oracle.diag(csr, oracle.FN_EXP, N=N, K=K, scale=scale, seed=2, rows=rows, assume_symmetric=True,
+                     want_digest=True, sampler="alias")
+    started = oa["digest"] != 0
+    assert np.array_equal(ra_["digest"][started], oa["digest"][started])
+    started = od["digest"] != 0
+    assert np.array_equal(rd["digest"][started], od["digest"][started])
+    assert_close(ra_["y"][rows], oa["y"], 1e-10, what="weighted action (alias)")
+    assert_close(rd["d"][rows], od["d"], 1e-10, what="weighted diag (alias)")
+    active = int(np.count_nonzero(deg))
+    assert ra_["stats"]["walk_steps"] == active * N * (K - 1)
+    assert np.all(np.isfinite(ra_["y"])) and np.all(np.isfinite(rd["d"]))

@@ -37,8 +37,11 @@ constexpr int kWalkThreads = 256;
 // cutoff, path digest.
 // kModeValue: an action request walking over its own value records (see
 // walk_core.hpp, action_walk_value): unweighted graphs without a digest.
-enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4, kModeDigest = 8, kModeValue = 16 };
-constexpr int kWalkModes = 32;
+// kModeWide: a diagonal request with wide hub sums (diag_walk_wide), one
+// start row per task: unweighted graphs whose layout is MCMF_SAMPLER_WIDE.
+enum : int32_t { kModeFp32 = 1, kModeWeighted = 2, kModeCutoff = 4, kModeDigest = 8, kModeValue = 16,
+                 kModeWide = 32 };
+constexpr int kWalkModes = 64;
 
 // Device descriptor of one request.
 struct BReq {
@@ -59,6 +62,12 @@ struct BReq {
     const uint8_t *hub_of;     // diag: hub index per node
     uint32_t hub_act;          // diag: hubs the walks sum (a.hub_act), left out of the probes
     uint32_t item;             // diag: neighbours per gather work item (the graph's tuning)
+    // kModeWide: the graph's wide masks and hub rows, and the active prefix
+    // of wide hubs the walks sum and the gather leaves out (0 otherwise).
+    const uint32_t *wmask;
+    const int32_t *whub_rows;
+    const uint16_t *whub_of;
+    int32_t whub_act;
 };
 
 // A run of one request's start rows inside a walk launch.  A task is one
@@ -114,7 +123,60 @@ __device__ __forceinline__ void one_walk(const BReq &R, const WSeg &sg, int64_t 
     }
 }
 
-template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST, bool VALUE>
+// One-row task of a diagonal request with wide hub sums: the walks of start
+// row k over edge records, <Q_k, C_h> for every requested active wide hub h
+// next to k summed into hsumw (as k_diag_walk_wide does), then flushed.
+template <class WT, bool DIGEST, bool CUTOFF>
+__device__ void wide_row_task(const BReq &R, const WSeg &sg, int64_t rel, uint32_t k, uint2 rk, int32_t *vstate,
+                              unsigned char *vxb, uint64_t &dig, unsigned long long &ns, double *hsumw,
+                              uint32_t *hkw, double *red) {
+    const int tid = threadIdx.x;
+    const int64_t N = R.a.N;
+    __syncthreads(); // the previous task is done with hkw and hsumw
+    if (tid < kWideWords)
+        hkw[tid] = 0u;
+    __syncthreads();
+    for (int hb = tid; hb < R.whub_act; hb += blockDim.x) {
+        const bool adj = (R.wmask[int64_t(k) * kWideWords + hb / 32] >> (hb % 32)) & 1u;
+        if (adj && (!R.a.in_set || R.a.in_set[R.whub_rows[hb]])) {
+            atomicOr(&hkw[hb / 32], 1u << (hb % 32));
+            hsumw[hb] = 0.0;
+        }
+    }
+    __syncthreads();
+    walk::WideRow hr;
+    hr.chunks = 0u;
+#pragma unroll
+    for (int wd = 0; wd < kWideWords; ++wd) {
+        hr.hk[wd] = static_cast<uint32_t>(dev::uniform(static_cast<int32_t>(hkw[wd])));
+        if (hr.hk[wd] != 0u)
+            hr.chunks |= 1u << (wd >> 2);
+    }
+    hr.any = hr.chunks != 0u;
+    const int64_t span = int64_t(R.a.K - 1) * N;
+    WT *vx = reinterpret_cast<WT *>(vxb + sg.xoff) + rel * span;
+    int32_t *vs = vstate + sg.slot_base + rel * span;
+    double acc0 = 0.0;
+    for (int64_t w = tid; w < N; w += blockDim.x) {
+        uint64_t h = dev::kFnvBasis;
+        walk::diag_walk_wide<WT, DIGEST, CUTOFF>(R.g.edge, reinterpret_cast<const uint4 *>(R.wmask), R.a, k, rk,
+                                                 static_cast<uint32_t>(w), vs + w, vx + w, N, &h, &ns, hr, hsumw,
+                                                 &acc0);
+        dig += h;
+    }
+    if (hr.any) {
+        const double x0 = dev::block_sum(acc0, red);
+        for (int hb = tid; hb < R.whub_act; hb += blockDim.x) {
+            if ((hkw[hb / 32] >> (hb % 32)) & 1u) {
+                const double hs = hsumw[hb] + x0;
+                if (hs != 0.0)
+                    atomicAdd(&R.a.dacc[R.whub_rows[hb]], R.a.scale * (R.a.scale * hs) * (1.0 / static_cast<double>(N)));
+            }
+        }
+    }
+}
+
+template <class WT, bool WEIGHTED, bool CUTOFF, bool DIGEST, bool VALUE, bool WIDE>
 __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restrict__ reqs,
                                                              const WSeg *__restrict__ segs,
                                                              int n_segs, int64_t n_tasks,
@@ -123,6 +185,8 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
     __shared__ double red[kWalkThreads / 64];
     __shared__ unsigned long long redu[kWalkThreads / 64];
     __shared__ double hsum[kHubRows * kMaxHubs]; // per row of the task, per hub
+    __shared__ double hsumw[WIDE ? kMaxWideHubs : 1];
+    __shared__ uint32_t hkw[WIDE ? kWideWords : 1];
     __shared__ int64_t task_slot;
     const int tid = threadIdx.x;
     // Tasks come from a queue counter in order, so the rows in flight stay a
@@ -151,7 +215,19 @@ __global__ __launch_bounds__(kWalkThreads) void k_batch_walk(const BReq *__restr
         const int64_t local = task - sg.task_base;
         uint64_t h = dev::kFnvBasis;
         unsigned long long ns = 0;
-        if (sg.rows_per_task == 0) {
+        if (WIDE && sg.rows_per_task == 0) {
+            // Wide hub sums (every task of a wide request is one row).
+            const int64_t rel = local;
+            const uint32_t k = static_cast<uint32_t>(dev::uniform(R.starts[sg.kk0 + rel]));
+            const uint2 rk = R.g.node[k];
+            uint64_t dig = 0;
+            wide_row_task<WT, DIGEST, CUTOFF>(R, sg, rel, k, rk, vstate, vxb, dig, ns, hsumw, hkw, red);
+            if (DIGEST) {
+                const unsigned long long dg = dev::block_sum(static_cast<unsigned long long>(dig), redu);
+                if (tid == 0)
+                    atomicAdd(reinterpret_cast<unsigned long long *>(&R.digest[k]), dg);
+            }
+        } else if (sg.rows_per_task == 0) {
             // One row: every thread loops over its walks.
             const int64_t rel = local;
             const uint32_t k = static_cast<uint32_t>(dev::uniform(R.starts[sg.kk0 + rel]));
@@ -270,7 +346,9 @@ WalkKernel walk_kernel_of() {
     // The value mode exists only unweighted without a digest; the other
     // combinations never occur and share the plain kernel.
     constexpr bool kValue = (M & kModeValue) != 0 && (M & (kModeWeighted | kModeDigest)) == 0;
-    return &k_batch_walk<WT, (M & kModeWeighted) != 0, (M & kModeCutoff) != 0, (M & kModeDigest) != 0, kValue>;
+    constexpr bool kWide = (M & kModeWide) != 0 && (M & (kModeWeighted | kModeValue)) == 0;
+    return &k_batch_walk<WT, (M & kModeWeighted) != 0, (M & kModeCutoff) != 0, (M & kModeDigest) != 0, kValue,
+                         kWide>;
 }
 
 template <int... M>
@@ -349,6 +427,8 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         job.overflow = probes_out + 1;
         job.hub_of = R.hub_of;
         job.hub_act = R.hub_act;
+        job.whub_of = R.whub_of;
+        job.whub_act = R.whub_act;
         gather_row<WEIGHTED, VT>(sh, job, reinterpret_cast<const VT *>(vxb + sg.xoff) + rel * span,
                                  probes);
     }
@@ -563,7 +643,18 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.dacc = P.dacc.ptr;
         B.item_off = P.item_off;
         B.item = gather_item(q.graph);
-        if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kHubMinWalks) {
+        if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kRowTaskWalks &&
+            q.graph->n_whubs > 0 && q.graph->tuning.diag_sampler == MCMF_SAMPLER_WIDE) {
+            // Wide hub rows (one start row per task): the walks sum them, the
+            // gather leaves them out.
+            B.mode |= kModeWide;
+            B.wmask = q.graph->wmask;
+            B.whub_rows = q.graph->whub_rows;
+            B.whub_of = q.graph->whub_of;
+            B.whub_act = active_wide_hubs(q.graph, q.n_walks, q.K);
+            B.a.in_set = B.in_set;
+            B.a.dacc = B.dacc;
+        } else if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kHubMinWalks) {
             // Hub rows: the walks sum them, the gather leaves them out.
             B.hub_of = q.graph->hub_of;
             B.hub_act = active_hubs(q.graph, q.n_walks, q.K);
@@ -752,18 +843,18 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             }
 
     // The device work of the batch: fills, walks, gathers, assembly.
-    auto enqueue = [&]() -> Status {
-        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, n_reqs + 2, s));
-        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_queues, s));
+    auto enqueue = [&](hipStream_t es) -> Status {
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(counters.ptr), 0, n_reqs + 2, es));
+        MCMF_TRY(fill_u64(reinterpret_cast<uint64_t *>(queues.ptr), 0, n_queues, es));
         for (int64_t i = 0; i < n_reqs; ++i) {
             Prep &P = *preps[i];
             const int64_t n = reqs[i].graph->n;
             if (P.q.ptr)
-                MCMF_TRY(fill_f64(P.q.ptr, 0.0, n, s));
+                MCMF_TRY(fill_f64(P.q.ptr, 0.0, n, es));
             if (P.dacc.ptr)
-                MCMF_TRY(fill_f64(P.dacc.ptr, 0.0, n, s));
+                MCMF_TRY(fill_f64(P.dacc.ptr, 0.0, n, es));
             if (P.dig.ptr)
-                MCMF_TRY(fill_u64(P.dig.ptr, 0, n, s));
+                MCMF_TRY(fill_u64(P.dig.ptr, 0, n, es));
         }
         int64_t gi = 0;
         for (size_t ci = 0; ci < chunks.size(); ++ci) {
@@ -773,7 +864,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
                     continue;
                 const int64_t blocks = std::min<int64_t>(walk_blocks[m], c.tasks[m]);
                 hipLaunchKernelGGL(walk_kernel(m), dim3(static_cast<uint32_t>(blocks)), dim3(kWalkThreads), 0,
-                                   s, dreq.ptr, dws[ci * kWalkModes + m]->ptr, static_cast<int>(c.w[m].size()),
+                                   es, dreq.ptr, dws[ci * kWalkModes + m]->ptr, static_cast<int>(c.w[m].size()),
                                    c.tasks[m], vstate.ptr, vxb.ptr,
                                    queues.ptr + walk_queue0 + static_cast<int64_t>(ci) * kWalkModes + m);
                 MCMF_HIP(hipGetLastError());
@@ -781,10 +872,10 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             for (const GatherGroup &gg : c.g) {
                 GSeg *segs = dgs[gi]->ptr;
                 const int n_segs = static_cast<int>(gg.segs.size());
-                hipLaunchKernelGGL(k_seg_items, dim3(1), dim3(64), 0, s, dreq.ptr, segs, n_segs);
+                hipLaunchKernelGGL(k_seg_items, dim3(1), dim3(64), 0, es, dreq.ptr, segs, n_segs);
                 MCMF_HIP(hipGetLastError());
                 hipLaunchKernelGGL(gather_kernel(gg.variant), dim3(static_cast<uint32_t>(group_blocks[gi])),
-                                   dim3(gather::kGatherThreads), gg.lds, s, dreq.ptr, segs, n_segs,
+                                   dim3(gather::kGatherThreads), gg.lds, es, dreq.ptr, segs, n_segs,
                                    vstate.ptr, vxb.ptr, gg.nb, counters.ptr + n_reqs, queues.ptr + gi);
                 MCMF_HIP(hipGetLastError());
                 ++gi;
@@ -796,10 +887,10 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             const double c1 = q.K >= 1 ? P.c[1] : 0.0;
             if (q.kind == MCMF_REQ_ACTION)
                 MCMF_TRY(spmv_assemble(q.graph, P.vin.ptr, P.r.ptr, q.K >= 2 ? P.q.ptr : nullptr,
-                                       P.c[0], c1, q.fn.scale, P.out.ptr, s));
+                                       P.c[0], c1, q.fn.scale, P.out.ptr, es));
             else
                 MCMF_TRY(diag_finish(q.graph, P.all ? nullptr : P.rows.ptr, P.count, q.K, P.c[0], c1,
-                                     q.fn.scale, P.dacc.ptr, P.out.ptr, s));
+                                     q.fn.scale, P.dacc.ptr, P.out.ptr, es));
         }
         return {};
     };
@@ -811,27 +902,38 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         MCMF_HIP(hipEventRecord(e0, s));
     }
     if (use_graph) {
+        // Record on a stream of the batch's own: a capture that fails leaves
+        // its stream unusable on this runtime (still marked as an invalidated
+        // capture after hipStreamEndCapture), so the caller's stream never
+        // enters capture mode; the graph is launched on it.
+        hipStream_t cs = nullptr;
+        MCMF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        MCMF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        const hipError_t be = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         // Test hook: the capture "fails" before its first launch (MCMF_TEST_FAIL_CAPTURE=1).
         const char *refuse = getenv("MCMF_TEST_FAIL_CAPTURE");
-        const Status st = refuse && refuse[0] == '1' ? fail(MCMF_E_DEVICE, "capture refused (MCMF_TEST_FAIL_CAPTURE)")
-                                                     : enqueue();
-        const hipError_t ce = hipStreamEndCapture(s, &graph);
+        const Status st = be != hipSuccess ? hip_fail(be, "hipStreamBeginCapture", __FILE__, __LINE__)
+                          : refuse && refuse[0] == '1'
+                              ? fail(MCMF_E_DEVICE, "capture refused (MCMF_TEST_FAIL_CAPTURE)")
+                              : enqueue(cs);
+        const hipError_t ce = be == hipSuccess ? hipStreamEndCapture(cs, &graph) : hipSuccess;
         if (st || ce != hipSuccess) {
             // The capture failed.  Another host thread can make a call that
-            // invalidates captures in progress (the runtime checks some calls
-            // against every capture in the process); the runtime reports it
-            // at the next launch being recorded or at the end of the capture.
-            // Nothing captured has run: run the batch's launches directly
-            // instead (a genuine error then shows again, and is returned).
+            // invalidates captures in progress; the runtime reports it at the
+            // next launch being recorded or at the end of the capture.
+            // Nothing captured has run: run the batch's launches directly on
+            // the caller's stream instead (a genuine error then shows again,
+            // and is returned).
             (void)hipGetLastError();
             if (graph)
                 (void)hipGraphDestroy(graph);
+            (void)hipStreamDestroy(cs);
+            (void)hipGetLastError();
             clear_error();
-            MCMF_TRY(enqueue());
+            MCMF_TRY(enqueue(s));
         } else {
+            (void)hipStreamDestroy(cs);
             hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
             if (ie != hipSuccess) {
                 (void)hipGraphDestroy(graph);
@@ -845,7 +947,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             MCMF_HIP(se);
         }
     } else {
-        MCMF_TRY(enqueue());
+        MCMF_TRY(enqueue(s));
     }
     if (stats)
         MCMF_HIP(hipEventRecord(e1, s));

@@ -209,3 +209,40 @@ def test_wide_hubs_with_the_shortest_walks(K):
             o = oracle.diag(csr, oracle_fn("exp"), N=64, K=K, scale=s, seed=7, rows=rows, want_digest=True)
             assert np.array_equal(r["wide"]["digest"], o["digest"])
             assert_close(r["wide"]["d"], o["d"], 1e-10, what=f"K={K}")
+
+
+def test_batched_requests_use_wide_hub_sums():
+    # Batched diagonal requests with N >= 128 (one start row per task) on a
+    # graph whose layout is WIDE take the wide hub sums too; requests with
+    # fewer walks keep the 32 hubs.  Each equals its single call (which walks
+    # with the wide sums) and the oracle; the wide sums leave fewer probes.
+    from _reqs import Req, run_batch
+    csr = G.rmat(12, seed=17)
+    s = 0.8 / csr.d_max
+    sel = np.concatenate([G.random_rows(csr.n, 200, seed=6), top_rows(csr, 1024)[::5]]).astype(np.int32)
+
+    def reqs(g):
+        return [Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, 160, 10, seed=1),
+                Req(g, csr, M.MCMF_REQ_DIAG, "resolvent", s, 128, 12, seed=2, request=1, rows=sel),
+                Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, 48, 9, seed=3, request=2, rows=sel),
+                Req(g, csr, M.MCMF_REQ_DIAG, "exp", s, 256, 8, seed=4, request=3,
+                    precision=M.MCMF_PRECISION_FP32_WEIGHTS, cutoff=1e-4),
+                Req(g, csr, M.MCMF_REQ_ACTION, "exp", s, 64, 10, seed=5, request=4)]
+    with graph(csr) as g:
+        setup(g, M.MCMF_SAMPLER_WIDE, 1)
+        rs = reqs(g)
+        want = [q.single() for q in rs]
+        eager, st_wide = run_batch(rs)
+        captured, _ = run_batch(rs, use_graph=True)
+        setup(g, M.MCMF_SAMPLER_EDGE, 1)
+        narrow, st_narrow = run_batch(reqs(g))
+    for got in (eager, captured, narrow):
+        for r, w in zip(got, want):
+            assert np.array_equal(r["digest"], w["digest"])
+            assert r["steps"] == w["steps"]
+            assert_close(r["x"], w["x"], 1e-10)
+    assert st_wide["gather_probes"] < st_narrow["gather_probes"]
+    o = oracle.diag(csr, oracle_fn("resolvent"), N=128, K=12, scale=s, seed=2, request=1, rows=sel,
+                    want_digest=True)
+    assert np.array_equal(eager[1]["digest"], o["digest"])
+    assert_close(eager[1]["x"], o["d"], 1e-10, what="batched wide diag vs oracle")

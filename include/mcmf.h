@@ -311,9 +311,14 @@ mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t);
  * items of 128, 256, 512 and 1024 neighbours; and, on graphs with hub rows,
  * diagonal walk plus gather with hub sums at the automatic threshold and
  * off, and with wide hub sums where the graph has wide hubs; on weighted
- * graphs, both walks with the running sums and with alias records.  It keeps the fastest of each and stores it in the graph
- * (mcmf_graph_set_tuning).  out receives the choice and the measured times.  The caller may cache the result by a
- * fingerprint of the graph and reapply it with mcmf_graph_set_tuning.
+ * graphs, both walks with the running sums and with alias records.  It keeps
+ * the fastest of each, except that the lanes, the work-item size, hub sums
+ * on and the graph's current wide-hub choice stay unless another option is
+ * more than 3% faster on the sample (its timings carry a few per cent of
+ * noise and of sampling bias), and stores the result in the graph
+ * (mcmf_graph_set_tuning).  out receives the choice and the measured times.
+ * The caller may cache the result by a fingerprint of the graph and reapply
+ * it with mcmf_graph_set_tuning.
  * Errors: as mcmf_action (K >= 2, n_walks >= 1 required), MCMF_E_NOMEM,
  * MCMF_E_DEVICE.
  */

@@ -273,17 +273,19 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
         if (auto_hubs != 0u) {
             MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], auto_hubs, true); }, &best.hub_ms[0]));
             MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true); }, &best.hub_ms[1]));
-            best.hub_min_degree = best.hub_ms[1] < best.hub_ms[0] ? INT32_MAX : 0;
+            best.hub_min_degree = best.hub_ms[1] < kMargin * best.hub_ms[0] ? INT32_MAX : 0;
         }
-        // Wide hub records: walk and gather with the wide hub sums at the
-        // automatic threshold, against the better of the two above.
+        // Wide hubs: walk and gather with the wide hub sums at the automatic
+        // threshold, against the better of the two above.  The graph's
+        // current layout stays unless the other wins by the margin.
         if (g->n_whubs > 0 && !g->weighted) {
             const int32_t auto_wide = active_wide_hubs(g, N, K);
             MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true, auto_wide); }, &best.wide_ms));
             double other = std::min(best.hub_ms[0], best.hub_ms[1]);
             if (auto_hubs == 0u)
                 MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true); }, &other));
-            if (best.wide_ms < other) {
+            const bool wide_now = g->tuning.diag_sampler == MCMF_SAMPLER_WIDE;
+            if (wide_now ? !(other < kMargin * best.wide_ms) : best.wide_ms < kMargin * other) {
                 best.diag_sampler = MCMF_SAMPLER_WIDE;
                 best.diag_stream = 0;
                 best.hub_min_degree = 0;

@@ -294,6 +294,9 @@ typedef struct {
                                   (MCMF_SAMPLER_WIDE; 0 without wide hubs) */
     double alias_ms[2];        /* mcmf_tune only, weighted graphs: ms of the action and the
                                   diagonal walk with MCMF_SAMPLER_ALIAS (0 otherwise) */
+    int32_t wide_hub_count;    /* out of mcmf_graph_get_tuning: wide hub rows the graph holds
+                                  (0: MCMF_SAMPLER_WIDE is not available); ignored on input */
+    int32_t reserved;          /* zero */
 } mcmf_tuning;
 
 /* Set / read a graph's tuning.  Not to be called while a request on the

@@ -187,7 +187,7 @@ struct mcmf_graph {
     size_t bytes = 0;
     // Walk-kernel choices (mcmf_graph_set_tuning / mcmf_tune).
     mcmf_tuning tuning = {MCMF_SAMPLER_VALUE, 0, MCMF_SAMPLER_EDGE, 0, {0, 0, 0, 0}, {0, 0, 0, 0}, 0, 0, 0, {0, 0},
-                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}, 0, {0, 0}};
+                          0, 0, {0, 0, 0}, {0, 0, 0, 0}, {0, 0}, 0, {0, 0}, 0, 0};
     // Hub rows (unweighted symmetric graphs with strictly increasing rows):
     // the rows of largest degree, at most kMaxHubs.  hubmask[j] has bit h set
     // when j is a column of row hub_rows[h] (by symmetry: when j is adjacent

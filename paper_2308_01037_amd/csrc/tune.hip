@@ -305,6 +305,7 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
         MCMF_TRY(refresh_active_items(g));
     *out = best;
     out->hub_count = g->n_hubs;
+    out->wide_hub_count = g->n_whubs;
     return {};
 }
 
@@ -357,6 +358,7 @@ extern "C" mcmf_status mcmf_graph_get_tuning(const mcmf_graph *g, mcmf_tuning *t
     }
     *t = g->tuning;
     t->hub_count = g->n_hubs;
+    t->wide_hub_count = g->n_whubs;
     return MCMF_OK;
 }
 

@@ -97,7 +97,8 @@ class mcmf_tuning(ctypes.Structure):
                 ("walk_threads", ctypes.c_int32), ("gather_item", ctypes.c_int32),
                 ("walk_threads_ms", ctypes.c_double * 3), ("gather_item_ms", ctypes.c_double * 4),
                 ("hub_ms", ctypes.c_double * 2), ("wide_ms", ctypes.c_double),
-                ("alias_ms", ctypes.c_double * 2)]
+                ("alias_ms", ctypes.c_double * 2), ("wide_hub_count", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {"action_sampler": self.action_sampler, "action_stream": self.action_stream,
@@ -108,7 +109,8 @@ class mcmf_tuning(ctypes.Structure):
                 "walk_threads": self.walk_threads, "gather_item": self.gather_item,
                 "walk_threads_ms": list(self.walk_threads_ms),
                 "gather_item_ms": list(self.gather_item_ms), "hub_ms": list(self.hub_ms),
-                "wide_ms": self.wide_ms, "alias_ms": list(self.alias_ms)}
+                "wide_ms": self.wide_ms, "alias_ms": list(self.alias_ms),
+                "wide_hub_count": self.wide_hub_count}
 
 
 MCMF_REQ_DIAG = 0

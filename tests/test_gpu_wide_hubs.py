@@ -69,7 +69,8 @@ def test_wide_hubs_match_narrow_probes_and_oracle(rows, fn):
         sel = np.concatenate([G.random_rows(csr.n, 300, seed=2), top_rows(csr, 1024)[::7]])
         sel = np.unique(sel).astype(np.int32)
     with graph(csr) as g:
-        assert M.mcmf_graph_get_tuning(g.handle).hub_count == 32
+        t = M.mcmf_graph_get_tuning(g.handle)
+        assert (t.hub_count, t.wide_hub_count) == (32, 1024)
         r = run3(g, fn, N, K, s, seed=5, rows=sel)
         check_same(r)
         # The wide sums replace probes: fewer than with 32 hubs, fewer than none.
@@ -181,6 +182,7 @@ def test_graphs_without_wide_hubs_reject_the_layout():
                        (base, 0)):
         with graph(csr, flags=flags) as g:
             assert M.mcmf_graph_get_tuning(g.handle).diag_sampler != M.MCMF_SAMPLER_WIDE
+            assert M.mcmf_graph_get_tuning(g.handle).wide_hub_count == 0
             t = M.mcmf_graph_get_tuning(g.handle)
             t.diag_sampler, t.hub_count = M.MCMF_SAMPLER_WIDE, 0
             with pytest.raises(M.MCMFError) as e:

@@ -216,6 +216,14 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
                                up to 1024 hubs (the chunks a start row needs, loaded
                                with the step's record); the walk sums <Q_k, C_h> for
                                all those hubs as it goes and the gather skips them */
+#define MCMF_SAMPLER_AUTO 5  /* mcmf_diag: per call, WIDE where the wide hub sums save at
+                               least 4 probed column entries per recorded walk state
+                               (the squared degrees of the active wide hubs beyond the
+                               first 32, over the call's n_active N (K-1) states), else
+                               EDGE.  The default on graphs with wide hubs unless the ROW
+                               default applies; measured crossover on R-MAT graphs at
+                               N = 256, K = 40: 3.5 saved per state 2% slower, 5.1 4%
+                               faster */
 #define MCMF_SAMPLER_ALIAS 4 /* weighted graphs only, action or diagonal: Walker's alias
                                method (Vose's construction) instead of the running sums
                                of |a|.  Entry i = floor(u deg / 2^64) from Philox words
@@ -234,7 +242,7 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
  * weighted graphs ALIAS and the running sums (EDGE, ROW) draw other paths
  * from the same law.  Defaults: action VALUE with cached loads; diag ROW
  * with cached loads when the column array and row records take at most
- * 16 MiB (4 nnz + 8 n bytes; they then stay in cache), WIDE where the graph
+ * 16 MiB (4 nnz + 8 n bytes; they then stay in cache), AUTO where the graph
  * has wide hubs, else EDGE with cached loads; ALIAS for both walks on
  * weighted graphs; automatic hub threshold.  The batched walks (mcmf_batch
  * and the server) use EDGE records (value records for unweighted actions,
@@ -254,7 +262,7 @@ mcmf_status mcmf_graph_create(int64_t n, const int64_t *row_ptr, const int32_t *
  * Wide hubs: such a graph with more than 32 rows with entries also keeps its
  * (up to 1024) rows of largest degree as wide hubs, with a 128-byte mask per
  * node of those adjacent to it (130 bytes per node in all), when that fits
- * 1/32 of device memory, and then defaults diag_sampler to MCMF_SAMPLER_WIDE
+ * 1/32 of device memory, and then defaults diag_sampler to MCMF_SAMPLER_AUTO
  * unless the ROW default above applies.  hub_min_degree picks the active wide
  * hubs as it picks the 32-bit ones.  The batched walks keep the 32-bit hubs. */
 typedef struct {

@@ -644,7 +644,9 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
         B.item_off = P.item_off;
         B.item = gather_item(q.graph);
         if (q.kind == MCMF_REQ_DIAG && !q.graph->weighted && q.n_walks >= kRowTaskWalks &&
-            q.graph->n_whubs > 0 && q.graph->tuning.diag_sampler == MCMF_SAMPLER_WIDE) {
+            q.graph->n_whubs > 0 &&
+            (q.graph->tuning.diag_sampler == MCMF_SAMPLER_WIDE ||
+             (q.graph->tuning.diag_sampler == MCMF_SAMPLER_AUTO && auto_wide(q.graph, q.n_walks, q.K)))) {
             // Wide hub rows (one start row per task): the walks sum them, the
             // gather leaves them out.
             B.mode |= kModeWide;

@@ -143,6 +143,9 @@ constexpr uint8_t kNoHub = 0xFF;
 constexpr int kWideWords = 32;
 constexpr int kMaxWideHubs = 32 * kWideWords; // 1024
 constexpr uint16_t kNoWideHub = 0xFFFF;
+// MCMF_SAMPLER_AUTO takes the wide hub sums when they save at least this
+// many probed column entries per recorded walk state.
+constexpr double kWideMinSavedPerState = 4.0;
 
 } // namespace mcmf
 
@@ -210,6 +213,7 @@ struct mcmf_graph {
     // to i (128 bytes per node, line aligned).
     int32_t n_whubs = 0;
     std::vector<int64_t> whub_deg_host;
+    std::vector<double> whub_sq_prefix; // [n_whubs + 1] prefix sums of deg^2 (MCMF_SAMPLER_AUTO)
     int32_t *whub_rows = nullptr; // [n_whubs]
     uint16_t *whub_of = nullptr;  // [n]
     uint32_t *wmask = nullptr;    // [n * kWideWords]

@@ -337,10 +337,13 @@ Status build_hubs(mcmf_graph *g, hipStream_t s) {
     if (top.size() > static_cast<size_t>(kMaxHubs) && wide_bytes <= device_memory_bytes() / 32) {
         g->n_whubs = static_cast<int32_t>(top.size());
         g->whub_deg_host.resize(top.size());
+        g->whub_sq_prefix.assign(top.size() + 1, 0.0);
         std::vector<int32_t> rows(top.size());
         for (size_t h = 0; h < top.size(); ++h) {
             rows[h] = top[h].second;
             g->whub_deg_host[h] = top[h].first;
+            const double d = static_cast<double>(top[h].first);
+            g->whub_sq_prefix[h + 1] = g->whub_sq_prefix[h] + d * d;
         }
         MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->whub_rows), sizeof(int32_t) * g->n_whubs));
         MCMF_TRY(dev_alloc_sync(reinterpret_cast<void **>(&g->whub_of), sizeof(uint16_t) * n));
@@ -493,10 +496,10 @@ Status build_graph(mcmf_graph *g, int64_t n, const int64_t *row_ptr, const int32
                (g->n_hubs > 0 ? (sizeof(uint32_t) + sizeof(uint8_t)) * n + sizeof(int32_t) * kMaxHubs : 0) +
                (g->n_whubs > 0 ? (sizeof(uint32_t) * kWideWords + sizeof(uint16_t)) * n + sizeof(int32_t) * g->n_whubs
                                : 0);
-    // The diagonal walk with wide hub sums where the graph has wide hubs and
-    // is past the size at which the ROW layout pays.
+    // The diagonal walk chooses the wide hub sums per call where the graph
+    // has wide hubs and is past the size at which the ROW layout pays.
     if (g->n_whubs > 0 && g->tuning.diag_sampler != MCMF_SAMPLER_ROW)
-        g->tuning.diag_sampler = MCMF_SAMPLER_WIDE;
+        g->tuning.diag_sampler = MCMF_SAMPLER_AUTO;
     // Weighted rows walk by the alias method: one 16-byte record per step
     // instead of a binary search (4.6x faster diagonal walks and 3.6x faster
     // action walks on a weighted R-MAT 20).  A graph whose records do not fit
@@ -612,6 +615,16 @@ Status ensure_alias(mcmf_graph *g) {
     g->alias_rec = rec;
     g->bytes += sizeof(uint4) * g->nnz;
     return {};
+}
+
+bool auto_wide(const mcmf_graph *g, int64_t n_walks, int K) {
+    if (g->n_whubs == 0 || g->weighted || K < 2 || n_walks < 1 || g->n_active == 0)
+        return false;
+    const int32_t act = active_wide_hubs(g, n_walks, K);
+    const int32_t narrow = std::min<int32_t>(act, g->n_hubs); // summed by the EDGE walk too
+    const double saved = g->whub_sq_prefix[static_cast<size_t>(act)] - g->whub_sq_prefix[static_cast<size_t>(narrow)];
+    const double states = static_cast<double>(g->n_active) * static_cast<double>(n_walks) * (K - 1);
+    return saved >= kWideMinSavedPerState * states;
 }
 
 int32_t active_wide_hubs(const mcmf_graph *g, int64_t n_walks, int K) {

@@ -27,6 +27,10 @@ Status ensure_alias(mcmf_graph *g);
 // n_walks and K: the prefix of degree >= the same threshold; 0 without them.
 int32_t active_wide_hubs(const mcmf_graph *g, int64_t n_walks, int K);
 
+// MCMF_SAMPLER_AUTO's choice for n_walks and K: the wide hub sums save at
+// least kWideMinSavedPerState probed entries per recorded state.
+bool auto_wide(const mcmf_graph *g, int64_t n_walks, int K);
+
 
 // Ascending indices i < n with flags[i] == match written to out; *count (host)
 // receives how many.  Synchronises the stream to read the count back.

@@ -38,8 +38,9 @@ Status check_tuning(const mcmf_tuning *t) {
     auto flag_ok = [](int32_t v) { return v == 0 || v == 1; };
     if (!(sampler_ok(t->action_sampler) || t->action_sampler == MCMF_SAMPLER_VALUE ||
           t->action_sampler == MCMF_SAMPLER_ALIAS) ||
-        !(sampler_ok(t->diag_sampler) || t->diag_sampler == MCMF_SAMPLER_WIDE || t->diag_sampler == MCMF_SAMPLER_ALIAS))
-        return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only, WIDE for the diagonal)");
+        !(sampler_ok(t->diag_sampler) || t->diag_sampler == MCMF_SAMPLER_WIDE || t->diag_sampler == MCMF_SAMPLER_ALIAS ||
+          t->diag_sampler == MCMF_SAMPLER_AUTO))
+        return fail(MCMF_E_ARG, "unknown sampler layout (VALUE is for the action only, WIDE and AUTO for the diagonal)");
     if (!flag_ok(t->action_stream) || !flag_ok(t->diag_stream))
         return fail(MCMF_E_ARG, "stream flags must be 0 or 1");
     if (t->hub_min_degree < 0)
@@ -279,12 +280,13 @@ Status tune(mcmf_graph *g, const mcmf_fn *f, int64_t N, int32_t K, mcmf_tuning *
         // threshold, against the better of the two above.  The graph's
         // current layout stays unless the other wins by the margin.
         if (g->n_whubs > 0 && !g->weighted) {
-            const int32_t auto_wide = active_wide_hubs(g, N, K);
-            MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true, auto_wide); }, &best.wide_ms));
+            const int32_t wide_act = active_wide_hubs(g, N, K);
+            MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true, wide_act); }, &best.wide_ms));
             double other = std::min(best.hub_ms[0], best.hub_ms[1]);
             if (auto_hubs == 0u)
                 MCMF_TRY(time_it([&]() { return run_diag(sizes[bi], 0u, true); }, &other));
-            const bool wide_now = g->tuning.diag_sampler == MCMF_SAMPLER_WIDE;
+            const bool wide_now = g->tuning.diag_sampler == MCMF_SAMPLER_WIDE ||
+                                  (g->tuning.diag_sampler == MCMF_SAMPLER_AUTO && auto_wide(g, N, K));
             if (wide_now ? !(other < kMargin * best.wide_ms) : best.wide_ms < kMargin * other) {
                 best.diag_sampler = MCMF_SAMPLER_WIDE;
                 best.diag_stream = 0;

@@ -313,8 +313,10 @@ Status action_walks(const mcmf_graph *g, const double *r, const int32_t *starts,
 }
 
 bool wide_diag(const mcmf_graph *g, const WalkParams &p) {
-    return g->n_whubs > 0 && !g->weighted &&
-           (p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler) == MCMF_SAMPLER_WIDE;
+    if (g->n_whubs == 0 || g->weighted)
+        return false;
+    const int s = p.sampler >= 0 ? p.sampler : g->tuning.diag_sampler;
+    return s == MCMF_SAMPLER_WIDE || (s == MCMF_SAMPLER_AUTO && auto_wide(g, p.n_walks, p.K));
 }
 
 Status diag_walks(const mcmf_graph *g, const int32_t *starts, int64_t n_start, const WalkParams &p,

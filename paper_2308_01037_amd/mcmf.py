@@ -62,6 +62,7 @@ MCMF_SAMPLER_ROW = 1
 MCMF_SAMPLER_VALUE = 2
 MCMF_SAMPLER_WIDE = 3
 MCMF_SAMPLER_ALIAS = 4
+MCMF_SAMPLER_AUTO = 5
 
 
 class mcmf_fn(ctypes.Structure):

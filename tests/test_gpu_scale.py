@@ -95,9 +95,10 @@ def test_rmat20_bench_configuration(rmat20, fn):
     scale = 1.0 / csr.d_max if fn == "exp" else 0.85 / lam
     rows = _sample_rows(csr, seed=5 if fn == "exp" else 6)
     with graph(csr) as g:
-        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_WIDE
+        assert M.mcmf_graph_get_tuning(g.handle).diag_sampler == M.MCMF_SAMPLER_AUTO
         # As benchmarked: no digest (value-record action walk, digest-free
-        # diag walk with wide hub sums).
+        # diag walk; AUTO takes the wide hub sums here, 5.1 probes saved per
+        # recorded state, as the gather's probe count below shows).
         ra = gpu_action(g, fn, np.ones(csr.n), N, K, scale, seed=1, stats=True)
         rd = gpu_diag(g, fn, N, K, scale, seed=1, stats=True)
         # With path digests (edge-record action walk, wide diag walk).

@@ -248,3 +248,39 @@ def test_batched_requests_use_wide_hub_sums():
                     want_digest=True)
     assert np.array_equal(eager[1]["digest"], o["digest"])
     assert_close(eager[1]["x"], o["d"], 1e-10, what="batched wide diag vs oracle")
+
+
+def _auto_takes_wide(csr, N, K):
+    # The AUTO rule: the squared degrees of the active wide hubs beyond the
+    # first 32 (degree >= N (K-1) / 4), over the recorded states, at least 4.
+    deg = np.sort(np.diff(csr.row_ptr))[::-1][:1024].astype(float)
+    thr = max(1, N * (K - 1) // 4)
+    act = int(np.count_nonzero(deg >= thr))
+    saved = float((deg[min(act, 32):act] ** 2).sum())
+    states = np.count_nonzero(np.diff(csr.row_ptr)) * N * (K - 1)
+    return saved >= 4 * states
+
+
+@pytest.mark.parametrize("N,K", [(16, 10), (2048, 40)])
+def test_auto_layout_chooses_per_call(N, K):
+    # MCMF_SAMPLER_AUTO walks with the wide hub sums exactly when they save at
+    # least 4 probed entries per recorded state; the probe count tells which
+    # kernel ran, the estimate is the same either way.
+    csr = G.rmat(14, seed=21)
+    s = 0.5 / csr.d_max
+    rows = G.random_rows(csr.n, 64, seed=2)
+    with graph(csr) as g:
+        setup(g, M.MCMF_SAMPLER_AUTO, 0)
+        auto = gpu_diag(g, "exp", N, K, s, seed=3, rows=rows, want_digest=True, stats=True)
+        setup(g, M.MCMF_SAMPLER_WIDE, 0)
+        wide = gpu_diag(g, "exp", N, K, s, seed=3, rows=rows, want_digest=True, stats=True)
+        setup(g, M.MCMF_SAMPLER_EDGE, 0)
+        edge = gpu_diag(g, "exp", N, K, s, seed=3, rows=rows, want_digest=True, stats=True)
+    takes = _auto_takes_wide(csr, N, K)
+    assert takes == (N == 16)  # the two cases fall on either side of the rule
+    want = wide if takes else edge
+    assert auto["stats"]["gather_probes"] == want["stats"]["gather_probes"]
+    if takes:
+        assert wide["stats"]["gather_probes"] < edge["stats"]["gather_probes"]
+    assert np.array_equal(auto["digest"], edge["digest"])
+    assert_close(auto["d"], edge["d"], 1e-10, what=f"AUTO N={N} K={K}")

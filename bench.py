@@ -860,6 +860,27 @@ def main():
         k["ms_per_launch"] = k["ms"] / k["launches"]
         log(f"{kind}: {k['ms'] / args.steps:.1f} ms/step, {k['launches']} launches, "
             f"{k['gbs']:.1f} GB/s algorithmic ({k['gbs'] / HBM_PEAK_GBS:.3f} of peak)")
+    # The diagonal query as a whole, with the method's own bytes per query:
+    # 4 B for every column entry of every requested neighbour of every start
+    # row (sum of deg(i)^2 over the requested rows: the probes the gather
+    # would make with no hub sums), 8 B per atomic into d and 12 B per walk
+    # transition, over the query's walk and gather time.  Hub sums done by the
+    # walk and summed hub columns skipped by the gather count here at the
+    # method's price, which the per-kernel figures leave out.
+    diag_recs = [st for what, _, st, _ in records if what == "diag"]
+    diag_query = None
+    if diag_recs:
+        deg = csr.deg.astype(np.float64)
+        method_bytes = 4.0 * float(np.dot(deg, deg)) + 8.0 * csr.nnz
+        per_q = [(method_bytes + 12.0 * (st["walk_steps"] - st["walks"]),
+                  st["ms_walk"] + st["ms_gather"]) for st in diag_recs]
+        b_q = sum(b for b, _ in per_q) / len(per_q)
+        ms_q = sum(ms for _, ms in per_q) / len(per_q)
+        diag_query = {"method_bytes_per_query": b_q, "ms_per_query": ms_q,
+                      "gbs_method": b_q / (ms_q * 1e-3) / 1e9,
+                      "frac": b_q / (ms_q * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"diag query: {ms_q:.1f} ms walk + gather, {b_q / 1e9:.1f} GB method bytes, "
+            f"{diag_query['gbs_method']:.1f} GB/s ({diag_query['frac']:.3f} of peak)")
     dominant = max(kernels, key=lambda kk: kernels[kk]["ms"])
     dk = kernels[dominant]
     alg_total = sum(k["bytes"] for k in kernels.values())
@@ -924,6 +945,7 @@ def main():
                         "traffic_over_algorithmic": (v_["traffic"] / v_["per_launch"]
                                                      if v_["traffic"] else None)}
                     for k, v_ in kernels.items()},
+        "diag_query": diag_query,
         "roofline": {
             "kernel": dominant,
             "bound": "hbm",

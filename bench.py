@@ -47,10 +47,11 @@ def parse():
                     help="write the hashes of the timed kernels' sources to PATH (for --summarize)")
     ap.add_argument("--probe-bytes", type=int, default=0,
                     help="with --summarize: size of the calibration copy in that run")
-    ap.add_argument("--workload", choices=["hotpath", "batch", "serve"], default="hotpath",
+    ap.add_argument("--workload", choices=["hotpath", "batch", "serve", "fp32"], default="hotpath",
                     help="hotpath: the R-MAT workload above (default); batch: 64 uneven requests "
                          "batched vs one at a time; serve: Poisson arrivals on resident graphs, "
-                         "served vs sequential")
+                         "served vs sequential; fp32: FP32 vs FP64 walk weights on the "
+                         "4M-node Barabasi-Albert graph")
     ap.add_argument("--requests", type=int, default=0, help="batch/serve: number of requests")
     ap.add_argument("--qps", type=float, default=0.0,
                     help="serve: arrival rate (0: the sequential path's measured capacity)")
@@ -452,6 +453,84 @@ def bench_batch(args):
     }
 
 
+def bench_fp32(args):
+    """The Barabasi-Albert configuration (n = 4,000,000, m = 8): exp(A/d_max),
+    K = 40, N = 256, the full action with v = 1 and the diagonal on 1% of the
+    rows, each timed with FP64 walk weights and with FP32 walk weights (FP64
+    sums) on the same walks.  Reports walk steps/s of both, the per-kernel
+    device time from the library's HIP events, and the largest FP32-FP64
+    difference over the stated rounding bound 2 K 2^-24 sum|terms|: the terms
+    are non-negative here, so sum|terms| is the Monte Carlo part, the result
+    less c_0 v + c_1 s A v (exp: c_0 = c_1 = 1)."""
+    import torch
+    import graphgen as G
+    from paper_2308_01037_amd import mcmf as M
+    assert torch.cuda.is_available(), "needs a GPU"
+    K, N = args.K, args.walks
+    t0 = time.time()
+    csr = G.barabasi_albert(4_000_000, 8, seed=0)
+    rows = G.random_rows(csr.n, csr.n // 100, seed=0)
+    s = 1.0 / csr.d_max
+    log(f"BA n={csr.n} nnz={csr.nnz} d_max={csr.d_max} ({time.time() - t0:.1f} s)")
+    g = M.Graph.from_csr(csr)
+    stream = torch.cuda.current_stream().cuda_stream
+    v = torch.ones(csr.n, dtype=torch.float64, device="cuda")
+    y = torch.empty(csr.n, dtype=torch.float64, device="cuda")
+    d = torch.empty(len(rows), dtype=torch.float64, device="cuda")
+    rt = torch.as_tensor(rows, dtype=torch.int32, device="cuda")
+    f = M.make_fn(M.MCMF_FN_EXP, s)
+
+    def query(what, precision, req):
+        st = M.mcmf_stats()
+        opts = M.make_opts(seed=1, request_id=req, precision=precision, stream=stream)
+        if what == "action":
+            M.mcmf_action(g.handle, f, v, N, K, opts, y, st)
+        else:
+            M.mcmf_diag(g.handle, f, rt, len(rows), N, K, opts, d, st)
+        return st.as_dict()
+
+    out = {}
+    results = {}
+    for pname, prec in (("fp64", M.MCMF_PRECISION_FP64), ("fp32_weights", M.MCMF_PRECISION_FP32_WEIGHTS)):
+        for what in ("action", "diag"):
+            query(what, prec, 1000)
+            torch.cuda.synchronize()
+            sts = []
+            t = time.perf_counter()
+            for i in range(max(1, args.steps)):
+                sts.append(query(what, prec, 0))
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t) / len(sts)
+            steps = sts[0]["walk_steps"]
+            out.setdefault(pname, {})[what] = {
+                "ms": wall * 1e3, "walk_steps": steps, "walk_steps_per_s": steps / wall,
+                "ms_walk": float(np.mean([x["ms_walk"] for x in sts])),
+                "ms_gather": float(np.mean([x["ms_gather"] for x in sts])),
+                "ms_spmv": float(np.mean([x["ms_spmv"] for x in sts]))}
+            results[(pname, what)] = (y if what == "action" else d).cpu().numpy().copy()
+            log(f"{pname} {what}: {wall * 1e3:.1f} ms, {steps / wall:.3e} steps/s")
+    bound_use = {}
+    for what, h in (("action", 1.0 + s * csr.deg), ("diag", np.ones(len(rows)))):
+        x64, x32 = results[("fp64", what)], results[("fp32_weights", what)]
+        bound = 2 * K * 2.0 ** -24 * np.abs(x64 - h) + 4 * np.finfo(np.float64).eps * np.abs(x64) + 1e-30
+        bound_use[what] = float(np.max(np.abs(x32 - x64) / bound))
+    g.close()
+    total = {p: sum(q["walk_steps"] for q in out[p].values()) / sum(q["ms"] for q in out[p].values()) * 1e3
+             for p in out}
+    return {
+        "metric": "walk steps/s, FP32 walk weights (FP64 sums) vs FP64, same walks",
+        "value": total["fp32_weights"], "unit": "walk-steps/s", "n_gpus": 1, "steps": args.steps,
+        "higher_is_better": True, "data": "synthetic", "dtype": "f32 weights, f64 sums",
+        "config": {"workload": f"Barabasi-Albert n=4e6 m=8 (seed K_9): exp(A/d_max), K={K}, N={N}/row; "
+                               f"full f(A)1 and diag on 1% of rows ({len(rows)})",
+                   "n": csr.n, "nnz": csr.nnz, "d_max": csr.d_max},
+        "walk_steps_per_s": total,
+        "speedup_fp32_vs_fp64": total["fp32_weights"] / total["fp64"],
+        "queries": out,
+        "max_diff_over_bound": bound_use,
+    }
+
+
 def lambda_max_device(M, torch, g, n, iters=50):
     """Largest eigenvalue by power iteration from 1/sqrt(n) * 1, every product
     A x taken by the library itself (mcmf_action with K = 1 and coefficients
@@ -756,6 +835,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "fp32":
+        print(json.dumps(bench_fp32(args)), flush=True)
         return
 
     if args.record_sources:

@@ -112,6 +112,7 @@ KERNELS = {"k_diag_gather": ("diag_gather", "gather.hip+gather_core.hpp"),
 # (device-to-device memcpy may run on a DMA engine and show no kernel).
 COPY_KERNEL = "neg_kernel"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_rmat20.md")
+CHUNK_KEY = "visit_chunk_bytes"
 
 
 def source_sha(fnames):
@@ -200,6 +201,8 @@ def summarize(directory, probe_bytes):
                     if src not in recorded:
                         continue  # no record of the sources this run was built from
                     t = traffic.setdefault(kname, {"source": src, "sha": recorded[src]})
+                    if kname.startswith("diag"):
+                        t[CHUNK_KEY] = recorded.get(CHUNK_KEY)
                     t[ctr.lower() + "_bytes_per_launch"] = tot2 / nd * 1024.0 * factor
         if traffic:
             lines.append("")
@@ -207,14 +210,25 @@ def summarize(directory, probe_bytes):
     return "\n".join(lines)
 
 
-def load_traffic(kernel):
+def visit_chunk_bytes(torch):
+    """The library's diagonal visit buffer: MCMF_DIAG_CHUNK_BYTES, else 1/16
+    of device memory within [256 MiB, 16 GiB] (it sets the start rows one
+    diagonal walk and gather launch take)."""
+    return int(os.environ.get("MCMF_DIAG_CHUNK_BYTES", "0")) or min(
+        16 << 30, max(256 << 20, torch.cuda.get_device_properties(0).total_memory // 16))
+
+
+def load_traffic(kernel, chunk_bytes=None):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None when there is none or the kernel's source changed since it was taken."""
+    None when there is none, the kernel's source changed since it was taken,
+    or (diagonal kernels) the visit buffer, hence the work per launch, differs."""
     try:
         for line in open(TRAFFIC_FILE):
             if line.startswith("traffic: "):
                 t = json.loads(line[len("traffic: "):]).get(kernel)
                 if not t or t["sha"] != source_sha(t["source"]):
+                    return None
+                if kernel.startswith("diag") and t.get(CHUNK_KEY) != chunk_bytes:
                     return None
                 if "fetch_size_bytes_per_launch" in t and "write_size_bytes_per_launch" in t:
                     return t["fetch_size_bytes_per_launch"] + t["write_size_bytes_per_launch"]
@@ -840,14 +854,18 @@ def main():
         print(json.dumps(bench_fp32(args)), flush=True)
         return
 
-    if args.record_sources:
-        os.makedirs(os.path.dirname(os.path.abspath(args.record_sources)), exist_ok=True)
-        with open(args.record_sources, "w") as fh:
-            json.dump({src: source_sha(src) for _, src in KERNELS.values()}, fh)
-
     import torch
     import graphgen as G
     from paper_2308_01037_amd import mcmf as M
+
+    if args.record_sources:
+        # The kernels' source hashes and the diagonal's visit-buffer size
+        # (which sets how much work one launch does), for --summarize.
+        os.makedirs(os.path.dirname(os.path.abspath(args.record_sources)), exist_ok=True)
+        rec = {src: source_sha(src) for _, src in KERNELS.values()}
+        rec[CHUNK_KEY] = visit_chunk_bytes(torch)
+        with open(args.record_sources, "w") as fh:
+            json.dump(rec, fh)
 
     def oracle_fn_kind(fname):
         import oracle
@@ -911,10 +929,8 @@ def main():
     value = total_steps / elapsed
     lat = np.array([r[3] for r in records]) * 1e3
     # Launches per query: one action walk; per diagonal query one walk and one
-    # gather launch per visit-buffer chunk.  The library's visit buffer:
-    # MCMF_DIAG_CHUNK_BYTES, else 1/32 of device memory within [256 MiB, 8 GiB].
-    chunk_bytes = int(os.environ.get("MCMF_DIAG_CHUNK_BYTES", "0")) or min(
-        8 << 30, max(256 << 20, torch.cuda.get_device_properties(0).total_memory // 32))
+    # gather launch per visit-buffer chunk.
+    chunk_bytes = visit_chunk_bytes(torch)
 
     def launches_of(what, st):
         if what == "action":
@@ -937,7 +953,7 @@ def main():
             k["launches"] += launches_of(what, st)
     for kind, k in kernels.items():
         k["gbs"] = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
-        k["traffic"] = load_traffic(kind)  # counter bytes per launch, None if stale
+        k["traffic"] = load_traffic(kind, chunk_bytes)  # counter bytes per launch, None if stale
         k["per_launch"] = k["bytes"] / k["launches"]
         k["ms_per_launch"] = k["ms"] / k["launches"]
         log(f"{kind}: {k['ms'] / args.steps:.1f} ms/step, {k['launches']} launches, "

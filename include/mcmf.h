@@ -368,7 +368,8 @@ mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64
  *
  * Device memory: the visit records (12 bytes per walk step, 8 with FP32
  * weights) go through one buffer of at most the MCMF_DIAG_CHUNK_BYTES
- * environment value, else 1/32 of device memory within [256 MiB, 8 GiB]; a
+ * environment value, else 1/16 of device memory within [256 MiB, 16 GiB],
+ * halved (down to 256 MiB) while the allocation fails for lack of memory; a
  * larger total is walked and gathered in chunks of start rows.
  *
  * Errors: MCMF_E_ARG (null g/f/out, K out of range, n_walks < 1 with K >= 2,
@@ -475,8 +476,8 @@ typedef struct {
                                    mode do), the batch is launched directly instead */
     int32_t reserved0;          /* must be zero */
     uint64_t visit_chunk_bytes; /* diagonal visit-record buffer of the batch; 0: the
-                                   MCMF_DIAG_CHUNK_BYTES environment value, else 1/32 of
-                                   device memory within [256 MiB, 8 GiB] (as mcmf_diag) */
+                                   MCMF_DIAG_CHUNK_BYTES environment value, else 1/16 of
+                                   device memory within [256 MiB, 16 GiB] */
     uint32_t reserved[4];       /* must be zero */
 } mcmf_batch_opts;
 

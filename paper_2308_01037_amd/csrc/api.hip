@@ -568,31 +568,46 @@ Status run_diag(const mcmf_graph *g, const mcmf_fn *f, const int32_t *rows, int6
         // FP32 walk weights).  Chunk boundaries: rows [bounds[i], bounds[i+1]).
         const int64_t per_row = N * (K - 1);
         const int64_t xbytes = p.precision == MCMF_PRECISION_FP32_WEIGHTS ? 4 : 8;
-        const int64_t chunk_bytes = default_visit_chunk_bytes();
-        const int64_t chunk_recs = std::max<int64_t>(1, chunk_bytes / (4 + xbytes));
-        std::vector<int64_t> bounds(1, 0);
+        std::vector<int64_t> bounds;
         int64_t most_recs = 0;
-        if (by_norm) {
-            int64_t c0 = 0;
-            while (c0 < n_start) {
-                int64_t c1 = c0 + 1; // at least one row per chunk
-                while (c1 < n_start && alloc.host_rec[c1 + 1] - alloc.host_rec[c0] <= chunk_recs)
-                    ++c1;
-                most_recs = std::max(most_recs, alloc.host_rec[c1] - alloc.host_rec[c0]);
-                bounds.push_back(c1);
-                c0 = c1;
+        auto plan_chunks = [&](int64_t chunk_recs) {
+            bounds.assign(1, 0);
+            most_recs = 0;
+            if (by_norm) {
+                int64_t c0 = 0;
+                while (c0 < n_start) {
+                    int64_t c1 = c0 + 1; // at least one row per chunk
+                    while (c1 < n_start && alloc.host_rec[c1 + 1] - alloc.host_rec[c0] <= chunk_recs)
+                        ++c1;
+                    most_recs = std::max(most_recs, alloc.host_rec[c1] - alloc.host_rec[c0]);
+                    bounds.push_back(c1);
+                    c0 = c1;
+                }
+            } else {
+                int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(chunk_recs / per_row, n_start));
+                for (int64_t c0 = rows_per_chunk; c0 < n_start; c0 += rows_per_chunk)
+                    bounds.push_back(c0);
+                bounds.push_back(n_start);
+                most_recs = rows_per_chunk * per_row;
             }
-        } else {
-            int64_t rows_per_chunk = std::max<int64_t>(1, std::min<int64_t>(chunk_recs / per_row, n_start));
-            for (int64_t c0 = rows_per_chunk; c0 < n_start; c0 += rows_per_chunk)
-                bounds.push_back(c0);
-            bounds.push_back(n_start);
-            most_recs = rows_per_chunk * per_row;
-        }
+        };
         DevBuf<int32_t> vstate;
         DevBuf<unsigned char> vx;
-        MCMF_TRY(vstate.alloc(most_recs, s));
-        MCMF_TRY(vx.alloc(most_recs * xbytes, s));
+        // The default buffer is halved while device memory (or the byte
+        // budget) refuses it; an explicit MCMF_DIAG_CHUNK_BYTES is kept.
+        for (int64_t chunk_bytes = default_visit_chunk_bytes();; chunk_bytes /= 2) {
+            plan_chunks(std::max<int64_t>(1, chunk_bytes / (4 + xbytes)));
+            Status st = vstate.alloc(most_recs, s);
+            if (!st)
+                st = vx.alloc(most_recs * xbytes, s);
+            if (!st)
+                break;
+            vstate.reset();
+            vx.reset();
+            if (st.code != MCMF_E_NOMEM || visit_chunk_bytes_fixed() || chunk_bytes / 2 < kMinVisitChunkBytes)
+                return st;
+            clear_error();
+        }
         // Per-chunk events are read only after the call's final synchronisation,
         // so timing does not stall the stream between chunks.
         const int64_t n_chunks = static_cast<int64_t>(bounds.size()) - 1;

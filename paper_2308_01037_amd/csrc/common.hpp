@@ -46,7 +46,8 @@ Mem classify(const void *p);
 
 // Device memory accounting against an optional byte budget (environment
 // variable MCMF_HBM_BUDGET_BYTES).  MCMF_TEST_FAIL_ALLOC=1 makes every
-// allocation fail, so the out-of-memory path can be exercised on purpose.
+// allocation fail, MCMF_TEST_FAIL_ALLOC_ABOVE=B every one of more than B
+// bytes, so the out-of-memory paths can be exercised on purpose.
 Status dev_alloc(void **p, size_t bytes, hipStream_t stream);
 void dev_free(void *p, size_t bytes, hipStream_t stream);
 Status dev_alloc_sync(void **p, size_t bytes);
@@ -124,9 +125,14 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c);
 int num_cus();
 
 // Default size of a call's diagonal visit-record buffer: the
-// MCMF_DIAG_CHUNK_BYTES environment value, else 1/32 of device memory
-// clamped to [256 MiB, 8 GiB] (fewer, larger chunks mean fewer launch tails).
+// MCMF_DIAG_CHUNK_BYTES environment value, else 1/16 of device memory
+// clamped to [256 MiB, 16 GiB] (fewer, larger chunks mean fewer launch tails;
+// at most half the block cache's 1/8 of device memory, so the buffer stays
+// cached between calls).  Without the environment value a call that cannot
+// get its buffer halves it, down to kMinVisitChunkBytes.
+constexpr int64_t kMinVisitChunkBytes = int64_t(256) << 20;
 int64_t default_visit_chunk_bytes();
+bool visit_chunk_bytes_fixed();
 
 // Total memory of the current device (cached; 64 GiB if it cannot be read).
 uint64_t device_memory_bytes();

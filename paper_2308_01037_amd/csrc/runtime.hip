@@ -72,13 +72,18 @@ static int64_t budget_bytes() {
     return budget;
 }
 
-static bool forced_failure() {
+// Test hooks: MCMF_TEST_FAIL_ALLOC=1 refuses every allocation,
+// MCMF_TEST_FAIL_ALLOC_ABOVE=B every allocation of more than B bytes.
+static bool forced_failure(size_t bytes) {
     const char *s = getenv("MCMF_TEST_FAIL_ALLOC");
-    return s && s[0] == '1';
+    if (s && s[0] == '1')
+        return true;
+    const char *a = getenv("MCMF_TEST_FAIL_ALLOC_ABOVE");
+    return a && a[0] && bytes > static_cast<size_t>(strtoull(a, nullptr, 10));
 }
 
 static Status reserve(size_t bytes) {
-    if (forced_failure())
+    if (forced_failure(bytes))
         return fail(MCMF_E_NOMEM, "device allocation of %zu bytes refused (MCMF_TEST_FAIL_ALLOC)",
                     bytes);
     const int64_t b = budget_bytes();
@@ -306,11 +311,13 @@ uint64_t device_memory_bytes() {
     return bytes;
 }
 
+bool visit_chunk_bytes_fixed() { return getenv("MCMF_DIAG_CHUNK_BYTES") != nullptr; }
+
 int64_t default_visit_chunk_bytes() {
     if (const char *e = getenv("MCMF_DIAG_CHUNK_BYTES"))
         return std::max<int64_t>(1, strtoll(e, nullptr, 10));
-    return std::min<int64_t>(int64_t(8) << 30,
-                             std::max<int64_t>(int64_t(256) << 20, static_cast<int64_t>(device_memory_bytes() / 32)));
+    return std::min<int64_t>(int64_t(16) << 30,
+                             std::max<int64_t>(kMinVisitChunkBytes, static_cast<int64_t>(device_memory_bytes() / 16)));
 }
 
 int num_cus() {

@@ -162,6 +162,28 @@ def test_multi_pass_gather_and_chunks(monkeypatch):
     check_diag(csr, "exp", N=600, K=30, scale=0.5 / csr.d_max, rows=rows)
 
 
+def test_visit_buffer_halved_when_memory_refuses(monkeypatch):
+    # A full diagonal whose visit records (about 1.2 GB) fit the default
+    # buffer in one chunk.  With every allocation above 300 MiB refused, the
+    # call halves its buffer until it fits (256 MiB: several chunks) and gives
+    # the same walks and estimates; with the buffer size fixed by
+    # MCMF_DIAG_CHUNK_BYTES it reports MCMF_E_NOMEM instead.
+    csr = G.rmat(14, seed=3)
+    N, K, s = 256, 40, 1.0 / csr.d_max
+    with graph(csr) as g:
+        whole = gpu_diag(g, "exp", N, K, s, want_digest=True, stats=True)
+        assert whole["stats"]["walk_steps"] * 12 > 600 << 20
+        monkeypatch.setenv("MCMF_TEST_FAIL_ALLOC_ABOVE", str(300 << 20))
+        halved = gpu_diag(g, "exp", N, K, s, want_digest=True, stats=True)
+        assert np.array_equal(whole["digest"], halved["digest"])
+        assert whole["stats"]["walk_steps"] == halved["stats"]["walk_steps"]
+        assert_close(halved["d"], whole["d"], RTOL, what="halved visit buffer")
+        monkeypatch.setenv("MCMF_DIAG_CHUNK_BYTES", str(1 << 30))
+        with pytest.raises(M.MCMFError) as e:
+            gpu_diag(g, "exp", N, K, s)
+        assert e.value.status == M.MCMF_E_NOMEM
+
+
 def test_validation_errors():
     csr = G.path(6)
     bad = G.CSR(6, csr.row_ptr.copy(), csr.col.copy())

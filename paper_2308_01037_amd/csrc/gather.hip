@@ -53,7 +53,25 @@ __global__ __launch_bounds__(kScanThreads) void k_item_scan(const uint32_t *__re
         off[n] = carry;
 }
 
+// Start row of each work item of one gather launch: item_row[it - off[lo]]
+// = kk for every item it of start row kk in [lo, hi), so that a workgroup
+// finds its row with one load instead of a binary search over off (one
+// dependent global load per level, paid by every item).  Entries beyond cap
+// are not written; the kernel searches for those.
+__global__ void k_item_rows(const int64_t *__restrict__ off, int64_t lo, int64_t hi,
+                            int32_t *__restrict__ item_row, int64_t cap) {
+    const int64_t kk = lo + int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (kk >= hi)
+        return;
+    const int64_t base = off[lo];
+    const int64_t e = off[kk + 1];
+    for (int64_t it = off[kk]; it < e && it - base < cap; ++it)
+        item_row[it - base] = static_cast<int32_t>(kk);
+}
+
 struct GatherArgs {
+    const int32_t *item_row; // k_item_rows of this launch
+    int64_t item_cap;        // entries of item_row
     const uint2 *node;
     const int32_t *col;
     const double *val;
@@ -108,11 +126,24 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.hub_act = a.hub_act;
     job.whub_of = a.whub_of;
     job.whub_act = a.whub_act;
+    // The queue counter of the next item is fetched while the current one
+    // runs.
+    unsigned long long next = 0;
+    if (threadIdx.x == 0)
+        next = atomicAdd(a.queue, 1ull);
     for (;;) {
-        const int64_t item = dev::uniform(first + next_item(a.queue, &item_slot));
+        __syncthreads(); // every thread has read the previous item
+        if (threadIdx.x == 0)
+            item_slot = static_cast<int64_t>(next);
+        __syncthreads();
+        const int64_t item = dev::uniform(first + item_slot);
         if (item >= last)
             break;
-        const int64_t kk = dev::uniform(row_of_item(a.item_off, a.row_begin, a.row_end, item));
+        if (threadIdx.x == 0)
+            next = atomicAdd(a.queue, 1ull);
+        const int64_t kk = item - first < a.item_cap
+                               ? dev::uniform(static_cast<int64_t>(a.item_row[item - first]))
+                               : dev::uniform(row_of_item(a.item_off, a.row_begin, a.row_end, item));
         const uint32_t part = static_cast<uint32_t>(item - dev::uniform(a.item_off[kk]));
         job.k = dev::uniform(a.starts[kk]);
         const uint2 rk = a.node[job.k];
@@ -195,6 +226,15 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.whub_of = g->whub_of;
     a.whub_act = wide_diag(g, p) ? p.whub_act : 0;
     a.item = p.gather_item ? p.gather_item : gather_item(g);
+    // Items of these rows: at most one per row plus one per `item` entries
+    // of the (distinct) start rows.
+    DevBuf<int32_t> item_rows;
+    a.item_cap = (row_end - row_begin) + g->nnz / a.item + 1;
+    MCMF_TRY(item_rows.alloc(a.item_cap, s));
+    hipLaunchKernelGGL(k_item_rows, dim3(static_cast<uint32_t>((row_end - row_begin + 255) / 256)), dim3(256), 0, s,
+                       item_off, row_begin, row_end, item_rows.ptr, a.item_cap);
+    MCMF_HIP(hipGetLastError());
+    a.item_row = item_rows.ptr;
     const GatherPlan plan = plan_gather(g->n, p.n_walks, p.K, kMaxTableLds,
                                         sizeof(uint32_t) * kFilterWords, kSlots);
     if (!plan.ok)

@@ -66,6 +66,17 @@ struct Table {
     uint32_t *filter;
     uint32_t nb;
 
+    // Empties the first cap slots and the filter (all threads of the block,
+    // between barriers).
+    __device__ void clear(uint32_t cap) const {
+        for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
+            keys[i] = kEmpty;
+            vals[i] = 0.0;
+        }
+        for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
+            filter[i] = 0u;
+    }
+
     // Multiplicative hashing: node ids of the graphs here carry no structure
     // that a multiply-shift hash would keep.
     __device__ __forceinline__ uint32_t bucket_of(int32_t key) const {
@@ -302,7 +313,6 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
     const Table &tab = sh.tab;
     Batch &bt = *sh.bt;
     uint32_t *scan_scratch = sh.scan_scratch;
-    unsigned long long *red = sh.red;
     const uint32_t cap = kSlots * tab.nb;
     const double inv_n = 1.0 / static_cast<double>(j.N);
     const int32_t k = j.k;
@@ -386,12 +396,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             restricted = uint64_t(total0) * kChunk * kRestrictNum <= static_cast<uint64_t>(count) * kRestrictDen;
         }
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < cap; i += blockDim.x) {
-            tab.keys[i] = kEmpty;
-            tab.vals[i] = 0.0;
-        }
-        for (uint32_t i = threadIdx.x; i < kFilterWords; i += blockDim.x)
-            tab.filter[i] = 0u;
+        tab.clear(cap);
         __syncthreads();
         if (restricted) {
             // (1') the column entries of the batch as keys.
@@ -416,15 +421,12 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             }
             __syncthreads();
             // (2') every visit added to its key when the key is present.
+            // Step 0 of every walk sits at k: its visits are summed per
+            // wavefront and added once per wavefront, after the others, so
+            // that their loads overlap the loop's and no barrier is needed.
             double x0 = 0.0;
             for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
                 x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
-            x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
-            if (threadIdx.x == 0 && x0 != 0.0) {
-                const int sk = tab.locate(k);
-                if (sk >= 0)
-                    atomicAdd(&tab.vals[sk], x0);
-            }
             for (int64_t i0 = nw + threadIdx.x; i0 < count; i0 += kVisits * int64_t(blockDim.x)) {
                 int32_t sv[kVisits];
                 double xv[kVisits];
@@ -441,16 +443,20 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                         atomicAdd(&tab.vals[sl], xv[u]);
                 }
             }
+            x0 = dev::wave_sum(x0);
+            if ((threadIdx.x & 63) == 0 && x0 != 0.0) {
+                const int sk = tab.locate(k);
+                if (sk >= 0)
+                    atomicAdd(&tab.vals[sk], x0);
+            }
         } else if (nw == j.N) {
-            // (1) Q_k from all walks.  Step 0 of every walk sits at k: insert
-            // the sum of those visits once instead of N colliding atomic
-            // updates of one slot.
+            // (1) Q_k from all walks.  Step 0 of every walk sits at k: those
+            // visits are summed per wavefront and inserted once per
+            // wavefront, after the others, instead of N colliding atomic
+            // updates of one slot (and with no barrier of their own).
             double x0 = 0.0;
             for (int64_t i = threadIdx.x; i < nw; i += blockDim.x)
                 x0 += st[i] >= 0 ? static_cast<double>(xs[i]) : 0.0;
-            x0 = dev::block_sum(x0, reinterpret_cast<double *>(red));
-            if (threadIdx.x == 0 && x0 != 0.0 && !tab.insert(k, x0))
-                atomicAdd(j.overflow, 1ull);
             // kVisits records per thread: their loads are issued together
             // before the inserts.
             for (int64_t i0 = nw + threadIdx.x; i0 < count; i0 += kVisits * int64_t(blockDim.x)) {
@@ -467,6 +473,9 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
                     if (sv[u] >= 0 && !tab.insert(sv[u], xv[u]))
                         atomicAdd(j.overflow, 1ull);
             }
+            x0 = dev::wave_sum(x0);
+            if ((threadIdx.x & 63) == 0 && x0 != 0.0 && !tab.insert(k, x0))
+                atomicAdd(j.overflow, 1ull);
         } else {
             // (1) Q_k from walks [w0, w0 + nw).
             for (int64_t i = threadIdx.x; i < count; i += blockDim.x) {

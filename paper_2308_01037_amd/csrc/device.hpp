@@ -104,9 +104,11 @@ __device__ __forceinline__ T block_sum(T x, T *scratch) {
 }
 
 // Exclusive prefix sum of one value per thread across the workgroup;
-// *total receives the sum.  scratch: one slot per wavefront.
+// *total receives the sum.  scratch: one slot per wavefront.  scratch_free:
+// the caller has a barrier after the last read of scratch by an earlier scan,
+// so the scan skips its own.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *scratch,
-                                                         uint32_t *total) {
+                                                         uint32_t *total, bool scratch_free = false) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int waves = (blockDim.x + 63) >> 6;
@@ -117,7 +119,8 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t *s
         if (lane >= off)
             incl += y;
     }
-    __syncthreads();
+    if (!scratch_free) // a previous scan may still be reading scratch
+        __syncthreads();
     if (lane == 63)
         scratch[wave] = incl;
     __syncthreads();

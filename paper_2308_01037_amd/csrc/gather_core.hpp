@@ -323,8 +323,12 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
 
     // Neighbours [p0, p0 + m) of k into bt; returns the number of column
     // chunks (kChunk entries each) of those that are requested and probed.
+    // The first batch of a job needs no barrier of its own: the caller's
+    // barrier before the job, or the one after the table is cleared, already
+    // separates it from the last reads of bt and of scan_scratch.
     auto setup_batch = [&](uint32_t p0, uint32_t m) -> uint32_t {
-        __syncthreads(); // table complete / previous batch flushed
+        if (p0 != j.p_begin)
+            __syncthreads(); // previous batch flushed
         uint32_t nchunks = 0;
         if (threadIdx.x < kBatch) {
             const int t = threadIdx.x;
@@ -355,7 +359,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             }
         }
         uint32_t total = 0;
-        const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total);
+        const uint32_t before = dev::block_exclusive_scan(nchunks, scan_scratch, &total, true);
         if (threadIdx.x < kBatch)
             bt.prefix[threadIdx.x] = before;
         if (threadIdx.x == 0)
@@ -395,7 +399,7 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             // total0 * kChunk bounds the batch's column entries from above.
             restricted = uint64_t(total0) * kChunk * kRestrictNum <= static_cast<uint64_t>(count) * kRestrictDen;
         }
-        __syncthreads();
+        // The last probe of the previous pass or job came before a barrier.
         tab.clear(cap);
         __syncthreads();
         if (restricted) {

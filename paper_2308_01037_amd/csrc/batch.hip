@@ -374,11 +374,28 @@ __global__ void k_seg_items(const BReq *__restrict__ reqs, GSeg *segs, int n_seg
     segs[n_segs].item_base = base;
 }
 
+// The run and start row of every item of one gather launch, map[item] =
+// {run, kk}, so that a workgroup finds them with one load instead of two
+// binary searches.  One block row per run (blockIdx.y), one thread per start
+// row; entries at or beyond cap are not written (the kernel searches).
+__global__ void k_seg_item_rows(const BReq *__restrict__ reqs, const GSeg *__restrict__ segs, int2 *map,
+                                int64_t cap) {
+    const GSeg sg = segs[blockIdx.y];
+    const int64_t rel = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (rel >= sg.rows)
+        return;
+    const int64_t *off = reqs[sg.req].item_off;
+    const int64_t kk = sg.kk0 + rel;
+    const int64_t first = sg.item_base - off[sg.kk0];
+    for (int64_t it = off[kk]; it < off[kk + 1] && first + it < cap; ++it)
+        map[first + it] = make_int2(static_cast<int>(blockIdx.y), static_cast<int>(kk));
+}
+
 template <bool WEIGHTED, class VT>
 __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
     const BReq *__restrict__ reqs, const GSeg *__restrict__ segs, int n_segs,
     const int32_t *vstate, const unsigned char *vxb, uint32_t nb, unsigned long long *probes_out,
-    unsigned long long *queue) {
+    unsigned long long *queue, const int2 *__restrict__ map, int64_t map_cap) {
     using namespace gather;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ Batch bt;
@@ -392,18 +409,27 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
         const int64_t item = dev::uniform(next_item(queue, &item_slot));
         if (item >= n_items)
             break;
-        int lo = 0, hi = n_segs;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (segs[mid].item_base <= item)
-                lo = mid;
-            else
-                hi = mid;
+        int lo = 0;
+        int64_t kk = -1;
+        if (map && item < map_cap) {
+            const int2 e = map[item];
+            lo = dev::uniform(e.x);
+            kk = dev::uniform(static_cast<int64_t>(e.y));
+        } else {
+            int hi = n_segs;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (segs[mid].item_base <= item)
+                    lo = mid;
+                else
+                    hi = mid;
+            }
         }
         const GSeg sg = segs[lo];
         const BReq &R = reqs[sg.req];
         const int64_t ri = dev::uniform(R.item_off[sg.kk0]) + (item - sg.item_base);
-        const int64_t kk = dev::uniform(row_of_item(R.item_off, sg.kk0, sg.kk0 + sg.rows, ri));
+        if (kk < 0)
+            kk = dev::uniform(row_of_item(R.item_off, sg.kk0, sg.kk0 + sg.rows, ri));
         const uint32_t part = static_cast<uint32_t>(ri - dev::uniform(R.item_off[kk]));
         const int64_t rel = kk - sg.kk0;
         const int64_t span = int64_t(R.a.K - 1) * R.a.N;
@@ -440,7 +466,7 @@ __global__ __launch_bounds__(gather::kGatherThreads) void k_batch_gather(
 // Gather kernel for variant v = (FP32 weights ? 1 : 0) | (weighted ? 2 : 0).
 using GatherKernel = void (*)(const BReq *, const GSeg *, int, const int32_t *,
                               const unsigned char *, uint32_t, unsigned long long *,
-                              unsigned long long *);
+                              unsigned long long *, const int2 *, int64_t);
 constexpr int kGatherVariants = 4;
 GatherKernel gather_kernel(int v) {
     switch (v) {
@@ -790,6 +816,12 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     // spare entry for its item count.
     std::vector<std::unique_ptr<DevBuf<WSeg>>> dws;
     std::vector<std::unique_ptr<DevBuf<GSeg>>> dgs;
+    // Item maps of the gather launches (k_seg_item_rows), sized from the
+    // runs: at most one item per start row plus one per `item` stored
+    // entries of the run's graph.  Launches with more runs than a grid's
+    // second dimension holds search instead.
+    std::vector<std::unique_ptr<DevBuf<int2>>> dmaps;
+    std::vector<int64_t> map_caps, map_rows;
     size_t lds_max[kGatherVariants] = {0, 0, 0, 0};
     int64_t n_groups = 0;
     for (const Chunk &c : chunks) {
@@ -807,6 +839,18 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             MCMF_HIP(hipMemcpyAsync(dgs.back()->ptr, gg.segs.data(), sizeof(GSeg) * gg.segs.size(),
                                     hipMemcpyHostToDevice, s));
             lds_max[gg.variant] = std::max(lds_max[gg.variant], gg.lds);
+            int64_t cap = 0, most_rows = 0;
+            for (const GSeg &sg : gg.segs) {
+                cap += sg.rows + reqs[sg.req].graph->nnz / std::max<uint32_t>(1u, hreq[sg.req].item) + 1;
+                most_rows = std::max(most_rows, sg.rows);
+            }
+            dmaps.emplace_back(new DevBuf<int2>());
+            if (gg.segs.size() > 65535u || most_rows == 0)
+                cap = 0;
+            if (cap > 0)
+                MCMF_TRY(dmaps.back()->alloc(cap, s));
+            map_caps.push_back(cap);
+            map_rows.push_back(most_rows);
             ++n_groups;
         }
     }
@@ -876,9 +920,17 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
                 const int n_segs = static_cast<int>(gg.segs.size());
                 hipLaunchKernelGGL(k_seg_items, dim3(1), dim3(64), 0, es, dreq.ptr, segs, n_segs);
                 MCMF_HIP(hipGetLastError());
+                if (map_caps[gi] > 0) {
+                    hipLaunchKernelGGL(k_seg_item_rows,
+                                       dim3(static_cast<uint32_t>((map_rows[gi] + 255) / 256),
+                                            static_cast<uint32_t>(n_segs)),
+                                       dim3(256), 0, es, dreq.ptr, segs, dmaps[gi]->ptr, map_caps[gi]);
+                    MCMF_HIP(hipGetLastError());
+                }
                 hipLaunchKernelGGL(gather_kernel(gg.variant), dim3(static_cast<uint32_t>(group_blocks[gi])),
                                    dim3(gather::kGatherThreads), gg.lds, es, dreq.ptr, segs, n_segs,
-                                   vstate.ptr, vxb.ptr, gg.nb, counters.ptr + n_reqs, queues.ptr + gi);
+                                   vstate.ptr, vxb.ptr, gg.nb, counters.ptr + n_reqs, queues.ptr + gi,
+                                   map_caps[gi] > 0 ? dmaps[gi]->ptr : nullptr, map_caps[gi]);
                 MCMF_HIP(hipGetLastError());
                 ++gi;
             }

@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     __shared__ Batch bt;
     __shared__ uint32_t scan_scratch[kWaves];
     __shared__ unsigned long long red[kWaves];
-    __shared__ int64_t item_slot;
+    __shared__ int64_t item_slot[2];
     const Shared sh = shared_views(smem, a.nb, &bt, scan_scratch, red);
     const int64_t span = int64_t(a.K - 1) * a.N;
     const int64_t first = a.item_off[a.row_begin];
@@ -128,15 +128,14 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
     job.whub_act = a.whub_act;
     // The queue counter of the next item is fetched while the current one
     // runs.
+    // Two slots: thread 0 writes the next item's at the end of an item, while
+    // the other threads may still be reading the current one's.
     unsigned long long next = 0;
     if (threadIdx.x == 0)
-        next = atomicAdd(a.queue, 1ull);
-    for (;;) {
-        __syncthreads(); // every thread has read the previous item
-        if (threadIdx.x == 0)
-            item_slot = static_cast<int64_t>(next);
-        __syncthreads();
-        const int64_t item = dev::uniform(first + item_slot);
+        item_slot[0] = static_cast<int64_t>(atomicAdd(a.queue, 1ull));
+    for (int64_t it = 0;; ++it) {
+        __syncthreads(); // the slot is written; every thread is done with the previous item
+        const int64_t item = dev::uniform(first + item_slot[it & 1]);
         if (item >= last)
             break;
         if (threadIdx.x == 0)
@@ -158,6 +157,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_diag_gather(GatherArgs a) {
         }
         job.st = a.vstate + rec;
         gather_row<WEIGHTED, VT>(sh, job, static_cast<const VT *>(a.vx) + rec, probes);
+        if (threadIdx.x == 0)
+            item_slot[(it + 1) & 1] = static_cast<int64_t>(next);
     }
     if (a.probes) {
         const unsigned long long total = dev::block_sum(probes, red);

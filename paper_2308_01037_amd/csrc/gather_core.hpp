@@ -391,6 +391,9 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
         uint32_t total0 = 0;
         bool restricted = false;
         if (single) {
+            // The last probe of the previous job came before a barrier; the
+            // batch setup's barriers order this clear before the inserts.
+            tab.clear(cap);
             total0 = setup_batch(j.p_begin, j.p_end - j.p_begin);
             // Nothing to probe (every neighbour unrequested or summed by the
             // walk): no table either.
@@ -399,9 +402,11 @@ __device__ void gather_row(const Shared &sh, const RowJob &j, const VT *__restri
             // total0 * kChunk bounds the batch's column entries from above.
             restricted = uint64_t(total0) * kChunk * kRestrictNum <= static_cast<uint64_t>(count) * kRestrictDen;
         }
-        // The last probe of the previous pass or job came before a barrier.
-        tab.clear(cap);
-        __syncthreads();
+        if (!single) {
+            // The last probe of the previous pass or job came before a barrier.
+            tab.clear(cap);
+            __syncthreads();
+        }
         if (restricted) {
             // (1') the column entries of the batch as keys.
             const uint32_t per = (total0 + kGroups - 1) / kGroups;

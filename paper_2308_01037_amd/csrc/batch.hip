@@ -845,6 +845,7 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
                 most_rows = std::max(most_rows, sg.rows);
             }
             dmaps.emplace_back(new DevBuf<int2>());
+            cap = item_map_cap(cap);
             if (gg.segs.size() > 65535u || most_rows == 0)
                 cap = 0;
             if (cap > 0)

@@ -124,6 +124,11 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c);
 
 int num_cus();
 
+// Test hook: MCMF_TEST_ITEM_MAP_CAP=C caps the gather launches' item maps at
+// C entries, so that the items beyond take the binary-search path; returns
+// cap unchanged without it.
+int64_t item_map_cap(int64_t cap);
+
 // Default size of a call's diagonal visit-record buffer: the
 // MCMF_DIAG_CHUNK_BYTES environment value, else 1/16 of device memory
 // clamped to [256 MiB, 16 GiB] (fewer, larger chunks mean fewer launch tails;

@@ -311,6 +311,14 @@ uint64_t device_memory_bytes() {
     return bytes;
 }
 
+int64_t item_map_cap(int64_t cap) {
+    const char *e = getenv("MCMF_TEST_ITEM_MAP_CAP");
+    if (!e || !e[0])
+        return cap;
+    const int64_t c = strtoll(e, nullptr, 10);
+    return c >= 0 && c < cap ? c : cap;
+}
+
 bool visit_chunk_bytes_fixed() { return getenv("MCMF_DIAG_CHUNK_BYTES") != nullptr; }
 
 int64_t default_visit_chunk_bytes() {

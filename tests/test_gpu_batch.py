@@ -79,6 +79,19 @@ def test_small_visit_chunks(graphs, monkeypatch):
         check_same(q, g, w, f"request {i}")
 
 
+@pytest.mark.parametrize("cap", [0, 5])
+def test_item_map_fallback(graphs, monkeypatch, cap):
+    # Gather items beyond the launch's item map find their run and start row
+    # by binary search: with the map capped at 0 or 5 entries nearly every
+    # item does, and every request still equals its single call.
+    reqs = _mixed(graphs)[:8]
+    want = [q.single() for q in reqs]
+    monkeypatch.setenv("MCMF_TEST_ITEM_MAP_CAP", str(cap))
+    got, _ = run_batch(reqs)
+    for i, (q, g, w) in enumerate(zip(reqs, got, want)):
+        check_same(q, g, w, f"item map capped at {cap}, request {i}")
+
+
 def test_graph_launch_matches_eager(graphs):
     # The batch recorded into a hipGraph and launched, three times, with eager
     # batches and synchronisations in between: every launch equals eager.

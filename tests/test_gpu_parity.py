@@ -184,6 +184,24 @@ def test_visit_buffer_halved_when_memory_refuses(monkeypatch):
         assert e.value.status == M.MCMF_E_NOMEM
 
 
+@pytest.mark.parametrize("cap", [0, 7])
+def test_item_map_fallback(monkeypatch, cap):
+    # Gather items beyond the launch's item map find their start row by binary
+    # search over the item offsets.  With the map capped at 0 or 7 entries the
+    # full diagonal and a row subset (rows of several items each included)
+    # take the same walks and give the uncapped estimates.
+    csr = G.rmat(12, seed=5)
+    rows = np.concatenate([np.argsort(csr.deg)[-3:], G.random_rows(csr.n, 40, seed=2)]).astype(np.int32)
+    with graph(csr) as g:
+        for r in (None, rows):
+            want = gpu_diag(g, "exp", 64, 12, 1.0 / csr.d_max, rows=r, want_digest=True)
+            monkeypatch.setenv("MCMF_TEST_ITEM_MAP_CAP", str(cap))
+            got = gpu_diag(g, "exp", 64, 12, 1.0 / csr.d_max, rows=r, want_digest=True)
+            monkeypatch.delenv("MCMF_TEST_ITEM_MAP_CAP")
+            assert np.array_equal(got["digest"], want["digest"])
+            assert_close(got["d"], want["d"], RTOL, what=f"item map capped at {cap}")
+
+
 def test_validation_errors():
     csr = G.path(6)
     bad = G.CSR(6, csr.row_ptr.copy(), csr.col.copy())

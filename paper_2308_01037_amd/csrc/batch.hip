@@ -817,9 +817,8 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
     std::vector<std::unique_ptr<DevBuf<WSeg>>> dws;
     std::vector<std::unique_ptr<DevBuf<GSeg>>> dgs;
     // Item maps of the gather launches (k_seg_item_rows), sized from the
-    // runs: at most one item per start row plus one per `item` stored
-    // entries of the run's graph.  Launches with more runs than a grid's
-    // second dimension holds search instead.
+    // runs (item_map_entries per run, at most kMaxItemMap in all).  Launches
+    // with more runs than a grid's second dimension holds search instead.
     std::vector<std::unique_ptr<DevBuf<int2>>> dmaps;
     std::vector<int64_t> map_caps, map_rows;
     size_t lds_max[kGatherVariants] = {0, 0, 0, 0};
@@ -841,7 +840,9 @@ Status run_batch(mcmf_request *reqs, int64_t n_reqs, const mcmf_batch_opts *o, m
             lds_max[gg.variant] = std::max(lds_max[gg.variant], gg.lds);
             int64_t cap = 0, most_rows = 0;
             for (const GSeg &sg : gg.segs) {
-                cap += sg.rows + reqs[sg.req].graph->nnz / std::max<uint32_t>(1u, hreq[sg.req].item) + 1;
+                const mcmf_graph *sgg = reqs[sg.req].graph;
+                cap = std::min(kMaxItemMap,
+                               cap + item_map_entries(sg.rows, sgg->nnz, sgg->d_max, hreq[sg.req].item));
                 most_rows = std::max(most_rows, sg.rows);
             }
             dmaps.emplace_back(new DevBuf<int2>());

@@ -124,6 +124,13 @@ Status make_coeffs(const mcmf_fn *f, int K, double *c);
 
 int num_cus();
 
+// Entries of a gather launch's item map for `rows` distinct start rows of a
+// graph with nnz stored entries and rows of at most d_max entries, cut into
+// items of `item` neighbours: the items there can be, at most kMaxItemMap
+// (items beyond take the binary-search path).
+constexpr int64_t kMaxItemMap = int64_t(1) << 23;
+int64_t item_map_entries(int64_t rows, int64_t nnz, int64_t d_max, uint32_t item);
+
 // Test hook: MCMF_TEST_ITEM_MAP_CAP=C caps the gather launches' item maps at
 // C entries, so that the items beyond take the binary-search path; returns
 // cap unchanged without it.

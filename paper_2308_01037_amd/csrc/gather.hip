@@ -227,10 +227,8 @@ Status diag_gather(const mcmf_graph *g, const int32_t *starts, const int64_t *it
     a.whub_of = g->whub_of;
     a.whub_act = wide_diag(g, p) ? p.whub_act : 0;
     a.item = p.gather_item ? p.gather_item : gather_item(g);
-    // Items of these rows: at most one per row plus one per `item` entries
-    // of the (distinct) start rows.
     DevBuf<int32_t> item_rows;
-    a.item_cap = item_map_cap((row_end - row_begin) + g->nnz / a.item + 1);
+    a.item_cap = item_map_cap(item_map_entries(row_end - row_begin, g->nnz, g->d_max, a.item));
     MCMF_TRY(item_rows.alloc(a.item_cap > 0 ? a.item_cap : 1, s));
     hipLaunchKernelGGL(k_item_rows, dim3(static_cast<uint32_t>((row_end - row_begin + 255) / 256)), dim3(256), 0, s,
                        item_off, row_begin, row_end, item_rows.ptr, a.item_cap);

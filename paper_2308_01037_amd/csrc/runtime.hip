@@ -311,6 +311,16 @@ uint64_t device_memory_bytes() {
     return bytes;
 }
 
+int64_t item_map_entries(int64_t rows, int64_t nnz, int64_t d_max, uint32_t item) {
+    const int64_t it = item > 0 ? item : 1;
+    // Each row has at most ceil(d_max / item) items, and the rows together
+    // one each plus one per `item` of their (at most nnz) entries.
+    const int64_t per_row = (d_max + it - 1) / it;
+    const int64_t by_rows = per_row > 0 && rows > kMaxItemMap / per_row ? kMaxItemMap : rows * per_row;
+    const int64_t by_nnz = rows + nnz / it + 1;
+    return std::min(kMaxItemMap, std::min(by_rows, by_nnz));
+}
+
 int64_t item_map_cap(int64_t cap) {
     const char *e = getenv("MCMF_TEST_ITEM_MAP_CAP");
     if (!e || !e[0])

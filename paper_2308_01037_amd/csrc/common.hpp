@@ -176,7 +176,6 @@ struct mcmf_graph {
     int64_t n_active = 0; // rows with at least one entry
     bool weighted = false;
     bool symmetric = false;
-    bool has_loops = false;
     hipStream_t stream = nullptr; // the graph's own stream
 
     // Device arrays.
@@ -189,7 +188,6 @@ struct mcmf_graph {
     // MCMF_SAMPLER_ALIAS: {col_j | sign_j << 31, col_a | sign_a << 31,
     // prob_j low word, high word} with a = alias_j (sign: a < 0).
     uint4 *alias_rec = nullptr;
-    double *diagval = nullptr;  // [n] a_ii (only when the graph has loops)
     uint2 *node = nullptr;      // [n] {first entry, row length}
     // [nnz] per stored entry a_ij: {j, first entry of row j, length of row j,
     // hubmask[j] (0 without hubs)}.  A walk step then needs one dependent

@@ -370,7 +370,9 @@ mcmf_status mcmf_graph_info(const mcmf_graph *g, int64_t *n, int64_t *nnz, int64
  * weights) go through one buffer of at most the MCMF_DIAG_CHUNK_BYTES
  * environment value, else 1/16 of device memory within [256 MiB, 16 GiB],
  * halved (down to 256 MiB) while the allocation fails for lack of memory; a
- * larger total is walked and gathered in chunks of start rows.
+ * larger total is walked and gathered in chunks of start rows.  Each chunk's
+ * gather also takes a map of its work items (4 bytes per item: at most one
+ * per start row plus one per 256 stored entries, at most 32 MiB).
  *
  * Errors: MCMF_E_ARG (null g/f/out, K out of range, n_walks < 1 with K >= 2,
  * n_rows < 0, a row outside [0, n), non-finite scale or coefficients,
